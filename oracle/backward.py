@@ -1,0 +1,129 @@
+"""Backward pass: implicit-function-theorem VJP through the dense KKT matrix
+(oracle side; test infrastructure only).
+
+* ``adjoint``        -- Eq. ocp:backward / Eq. loss_gradient: solve
+                        K [z~; lam~] = [dl/dz; dl/dlam] with the LU factors of
+                        the final QP's K (the paper's Alg. backward uses
+                        dl/dlam = 0; a non-zero one is the general VJP).
+* ``qp_cotangents``  -- -dF/dtheta' [z~; lam~] with F = [G z + b + H' lam;
+                        H z - d] (Eq. KKT) taken with respect to the dense
+                        matrices: dG = -z~ z', db = -z~, dH = -(lam z~' + lam~ z'),
+                        dd = lam~; then read off at the positions where the QP
+                        data sit in G, b, H, d (Eq. KKTmatrix).
+* ``vjp``            -- cotangents of the problem's own inputs: x_s, the cost
+                        parameters (through the QP cost data, by complex step
+                        for the softplus weights; with the PD-projection mask
+                        for diagonal costs), and for linear dynamics A, B, c
+                        (the constraint's Jacobians are A+ = I, -A, -B and
+                        C_t = c_t by definition of f_t).  The linearisation
+                        point is held fixed: the backward is the VJP of the
+                        final QP's solution map.
+
+Pinned (tests): central finite differences of the oracle's QP solution map,
+the envelope identity (dl/dz = G z + b gives z~ = 0, lam~ = -lam), and
+dJ*/dx_s = -lam_0 on LQ problems.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+
+from . import costs, qp
+
+
+def adjoint(sol, gx, gu, glam=None):
+    """(x~ [N,nx], u~ [T,nu], lam~ [N,nx]) solving K xi = (dl/dz, dl/dlam)."""
+    T, nx = gu.shape[0], gx.shape[1]
+    nu = gu.shape[1]
+    if glam is None:
+        glam = np.zeros_like(gx)
+    v = qp.join_w(np.asarray(gx, np.float64), np.asarray(gu, np.float64),
+                  np.asarray(glam, np.float64))
+    xi = sla.lu_solve(sol["lu"], v)
+    return qp.split_w(xi, T, nx, nu)
+
+
+def qp_cotangents(qpd, sol, xt, ut, lamt):
+    """Cotangents of the QP data (lists per stage, paper's sign convention)."""
+    T, nx, nu = qpd["T"], qpd["nx"], qpd["nu"]
+    parts = sol["parts"]
+    xi, ui = parts["xi"], parts["ui"]
+    z = sol["w"][:parts["nz"]]
+    lam = sol["w"][parts["nz"]:]
+    w_t = qp.join_w(xt, ut, lamt)
+    zt, lt = w_t[:parts["nz"]], w_t[parts["nz"]:]
+    dG = -np.outer(zt, z)
+    db = -zt
+    dH = -(np.outer(lam, zt) + np.outer(lt, z))
+    dd = lt
+    out = dict(Q=[], q=[], R=[], r=[], A=[], B=[], C=[])
+    for t in range(T + 1):
+        out["Q"].append(dG[xi[t]:xi[t] + nx, xi[t]:xi[t] + nx])
+        out["q"].append(db[xi[t]:xi[t] + nx])
+    for t in range(T):
+        out["R"].append(dG[ui[t]:ui[t] + nu, ui[t]:ui[t] + nu])
+        out["r"].append(db[ui[t]:ui[t] + nu])
+        row = (t + 1) * nx
+        out["A"].append(dH[row:row + nx, xi[t]:xi[t] + nx])
+        out["B"].append(dH[row:row + nx, ui[t]:ui[t] + nu])
+        out["C"].append(dd[row:row + nx])
+    out["xs"] = dd[0:nx]
+    return out
+
+
+def _cost_qp_part(prob, xbar, ubar, cp):
+    """(Q_t, q_t, R_t, r_t) of Eq. QPmatrices as a function of the cost
+    parameters cp at a fixed linearisation point."""
+    T = prob["T"]
+    Q, q, R, r = [], [], [], []
+    for t in range(T + 1):
+        _, g, Hm = costs.stage_x(prob, t, xbar[t].astype(np.complex128), cp)
+        Qt = qp.project_pd(Hm)
+        Q.append(Qt)
+        q.append(g - Qt @ xbar[t])
+    for t in range(T):
+        _, g, Hm = costs.stage_u(prob, t, ubar[t].astype(np.complex128), cp)
+        Rt = qp.project_pd(Hm)
+        R.append(Rt)
+        r.append(g - Rt @ ubar[t])
+    return Q, q, R, r
+
+
+def _pair(cot, part):
+    """<cotangent, perturbation> summed over all stages."""
+    s = 0.0
+    for key, val in zip(("Q", "q", "R", "r"), part):
+        for a, b in zip(cot[key], val):
+            s += np.sum(np.asarray(a) * np.asarray(b))
+    return s
+
+
+def vjp(prob, xbar, ubar, qpd, sol, gx, gu, glam=None, h=1e-30):
+    """Gradient of l with respect to the problem inputs through the final QP's
+    solution map.  Returns (grads dict, (x~, u~, lam~))."""
+    xt, ut, lamt = adjoint(sol, gx, gu, glam)
+    cot = qp_cotangents(qpd, sol, xt, ut, lamt)
+    g = {"x0": np.array(cot["xs"])}
+    cp = costs.cost_params(prob)
+    if prob["cost"] == "diag":
+        # the cost parameters are the QP cost data; the projection clamps entries
+        Qd, Rd = np.asarray(cp["Qd"]), np.asarray(cp["Rd"])
+        g["Qd"] = np.array([np.diag(a) for a in cot["Q"]]) * (Qd >= qp.PD_EPS)
+        g["Rd"] = np.array([np.diag(a) for a in cot["R"]]) * (Rd >= qp.PD_EPS)
+        g["q"] = np.array(cot["q"])
+        g["r"] = np.array(cot["r"])
+    else:
+        for key, val in cp.items():
+            val = np.asarray(val, dtype=np.float64)
+            gk = np.zeros(val.shape)
+            for idx in np.ndindex(val.shape):
+                cpc = {k: np.asarray(v, dtype=np.complex128).copy() for k, v in cp.items()}
+                cpc[key][idx] += 1j * h
+                part = _cost_qp_part(prob, xbar, ubar, cpc)
+                gk[idx] = np.imag(_pair(cot, part)) / h
+            g[key] = gk
+    if prob["dyn"] == "ltv":
+        g["A"] = -np.array(cot["A"])
+        g["B"] = -np.array(cot["B"])
+        g["c"] = np.array(cot["C"])
+    return g, (xt, ut, lamt)
