@@ -1,0 +1,206 @@
+/*
+ * dmpc.h -- C ABI of the batched differentiable-MPC solver for AMD MI355X (gfx950).
+ *
+ * The library solves batches of optimal control problems (the OCP of Sec. 3 of
+ * "Differentiable Model Predictive Control on the GPU"):
+ *
+ *   min_{x,u}  sum_{t=0}^{T} c_t^x(x_t) + sum_{t=0}^{T-1} c_t^u(u_t)
+ *   s.t.       x_{t+1} = phi_t(x_t, u_t),   x_0 = x_s
+ *
+ * by SQP (Alg. sqp) whose QP (Sec. 3.1) is solved through the Schur complement
+ * of its KKT system (Eq. shurcomplement, Eq. schur) with preconditioned
+ * conjugate gradients (Alg. pcg) and the symmetric stair preconditioner
+ * (Eq. S_Phiinv), followed by the merit line search (App. A.3).  The backward
+ * pass (Alg. backward, Eq. ocp:backward, Eq. loss_gradient) reuses the same
+ * Schur blocks and PCG for the adjoint solve and writes the vector-Jacobian
+ * product with respect to every differentiable input.
+ *
+ * Conventions
+ *   - Every pointer argument is a DEVICE pointer unless documented as host.
+ *   - All floating point data is float32, row-major, stage-major.
+ *   - The caller owns every buffer (arenas, workspace, status arrays).  The
+ *     library allocates device memory only in dmpc_plan_create (the plan's
+ *     descriptor table), never in a solve call.
+ *   - Calls return a dmpc_status; they never throw.  Numeric trouble of a
+ *     single problem is reported in its per-problem status word, not as a call
+ *     failure.  Solve calls are asynchronous on the given stream.
+ *   - A handle and its plans may be used from one host thread at a time.
+ */
+#ifndef DMPC_H
+#define DMPC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* Return codes of the API calls                                            */
+/* ------------------------------------------------------------------------ */
+typedef enum dmpc_status {
+  DMPC_OK = 0,
+  DMPC_ERR_INVALID_ARG = 1,   /* a descriptor, offset, size or option is invalid */
+  DMPC_ERR_UNSUPPORTED = 2,   /* valid but not built (e.g. a state size without a kernel) */
+  DMPC_ERR_HIP = 3,           /* a HIP runtime call failed */
+  DMPC_ERR_NOMEM = 4          /* plan allocation failed, or a buffer is too small */
+} dmpc_status;
+
+/* Per-problem status bits written by the kernels (0 = converged normally). */
+enum {
+  DMPC_PROB_PCG_MAXITER = 1,      /* forward PCG hit its iteration cap before its tolerance */
+  DMPC_PROB_NONPD = 2,            /* a Schur diagonal block had a non-positive pivot, or p'Sp <= 0 */
+  DMPC_PROB_NONFINITE = 4,        /* NaN/Inf met in the iterate or in PCG scalars */
+  DMPC_PROB_LS_FALLBACK = 8,      /* no step size passed the decrease test; the smallest was taken */
+  DMPC_PROB_BWD_PCG_MAXITER = 16  /* backward PCG hit its iteration cap */
+};
+
+/* Dynamics x_{t+1} = phi_t(x_t, u_t) of a problem.  The data block at dyn_off holds:
+ *   LTV      : A [T][nx][nx], B [T][nx][nu], c [T][nx]    (phi_t = A_t x + B_t u + c_t)
+ *   CARTPOLE : (m_c, m_p, L, g, dt): the cart-pole of App. B.2 as printed, explicit
+ *              Euler; nx = 4, nu = 1
+ *   BICYCLE  : 16 parameters (a, b, m, Iz, rw, Iw, Bf, Cf, Df, Br, Cr, Dr, Cx, kappa,
+ *              dt, vmin): a dynamic single-track model with Pacejka-type lateral tyre
+ *              forces, explicit Euler; state (r, v, beta, omega, dpsi, e, delta, tau),
+ *              input (ddelta, dtau); nx = 8, nu = 2 */
+typedef enum dmpc_dyn_kind { DMPC_DYN_LTV = 0, DMPC_DYN_CARTPOLE = 1, DMPC_DYN_BICYCLE = 2 } dmpc_dyn_kind;
+
+/* Costs.  The data block at cost_off holds:
+ *   DIAG     : Qd [T+1][nx], q [T+1][nx], Rd [T][nu], r [T][nu]
+ *              c_t^x = 1/2 x'diag(Qd_t)x + q_t'x, c_t^u = 1/2 u'diag(Rd_t)u + r_t'u
+ *   SOFTPLUS : theta [P][nw+nu], wscale [nw+nu], wfix [nx-nw], xref [nx]
+ *              (P = cost_phases, nw = cost_nw).  Stage t uses phase
+ *              k = min(P*t/T, P-1) (integer division); its weights are
+ *              wscale*softplus(theta[k]) for the first nw states and all inputs,
+ *              wfix for the remaining states:
+ *              c_t^x = 1/2 sum_i w_i (x_i - xref_i)^2, c_t^u = 1/2 sum_j w_j u_j^2
+ * Cost Hessians are projected onto {H >= 1e-6 I} when the QP is formed (Sec. 3.1). */
+typedef enum dmpc_cost_kind { DMPC_COST_DIAG = 0, DMPC_COST_SOFTPLUS = 1 } dmpc_cost_kind;
+
+/* Initial guess of the SQP (Alg. sqp inputs). */
+typedef enum dmpc_init_kind {
+  DMPC_INIT_GIVEN = 0,   /* (x, u, lambda) from the solution arena; x_0 is reset to x_s */
+  DMPC_INIT_ROLLOUT = 1  /* u from the solution arena, x rolled out from x_s, lambda = 0 */
+} dmpc_init_kind;
+
+/* One problem of a batch (host struct, 64 bytes).  Offsets are in floats. */
+typedef struct dmpc_problem {
+  int32_t T;            /* horizon, >= 1 */
+  int32_t nx, nu;       /* state and input sizes */
+  int32_t dyn;          /* dmpc_dyn_kind */
+  int32_t cost;         /* dmpc_cost_kind */
+  int32_t cost_phases;  /* SOFTPLUS: number of phases P (>= 1); else 0 */
+  int32_t cost_nw;      /* SOFTPLUS: number of leading states with learned weights; else 0 */
+  int32_t reserved;     /* must be 0 */
+  int64_t dyn_off;      /* data arena: dynamics block */
+  int64_t cost_off;     /* data arena: cost block */
+  int64_t x0_off;       /* data arena: x_s [nx] */
+  int64_t sol_off;      /* solution arena: x [T+1][nx], u [T][nu], lambda [T+1][nx] */
+} dmpc_problem;
+
+/* Solver options (host struct). */
+typedef struct dmpc_opts {
+  int32_t sqp_iters;        /* fixed SQP iteration count, 1..1000 */
+  int32_t pcg_max_iter;     /* forward PCG cap; 0 = N*nx + 10 */
+  float pcg_tol;            /* stop when ||r||_{Phi^-1} <= pcg_tol * ||g||_{Phi^-1} */
+  float pcg_abs_tol;        /* also stop when r'Phi^-1 r <= pcg_abs_tol (0 = off) */
+  int32_t n_alphas;         /* number of line-search candidates, 1..8 */
+  float alphas[8];          /* candidates in decreasing order, in (0, 1] */
+  float ls_eta;             /* decrease parameter eta of Eq. linesearch:decrease, in (0, 1) */
+  int32_t init;             /* dmpc_init_kind */
+  int32_t bwd_warm_start;   /* 1: start the adjoint PCG from lambda~ in the adjoint arena */
+  int32_t bwd_pcg_max_iter; /* backward PCG cap; 0 = N*nx + 10 */
+  float bwd_pcg_tol;        /* backward relative tolerance (as pcg_tol) */
+  int32_t block_threads;    /* threads per workgroup; 0 = chosen by the library */
+  int32_t reserved[3];      /* must be 0 */
+} dmpc_opts;
+
+/* Fills *o with the defaults: 1 SQP iteration, PCG tol 1e-6, candidates
+ * {1, 0.7, 0.3, 0.1, 0.01} (App. A.3), eta = 0.4, INIT_GIVEN. Host only. */
+void dmpc_default_opts(dmpc_opts* o);
+
+typedef struct dmpc_handle dmpc_handle;
+typedef struct dmpc_plan dmpc_plan;
+
+/* Handle bound to a HIP device. */
+dmpc_status dmpc_create(dmpc_handle** h, int device);
+dmpc_status dmpc_destroy(dmpc_handle* h);
+
+/* Host-only validation of a batch (no GPU needed).  problems: HOST array of
+ * count descriptors; data_len / sol_len: arena lengths in floats.  On an
+ * invalid problem, *bad_index (host, may be NULL) receives its index. */
+dmpc_status dmpc_validate(const dmpc_problem* problems, int32_t count, int64_t data_len,
+                          int64_t sol_len, const dmpc_opts* opts, int32_t* bad_index);
+
+/* Host-only workspace size in bytes for a batch (no GPU needed). */
+dmpc_status dmpc_workspace_size(const dmpc_problem* problems, int32_t count,
+                                const dmpc_opts* opts, size_t* bytes);
+
+/* Validates the batch and uploads its descriptor table to the handle's device
+ * (the only device allocation of the library).  problems is a HOST array; the
+ * plan keeps its own copy.  The plan fixes the problem shapes and offsets; the
+ * arenas passed to the solve calls may change between calls. */
+dmpc_status dmpc_plan_create(dmpc_handle* h, const dmpc_problem* problems, int32_t count,
+                             int64_t data_len, int64_t sol_len, const dmpc_opts* opts,
+                             dmpc_plan** plan);
+dmpc_status dmpc_plan_workspace_size(const dmpc_plan* plan, size_t* bytes);
+dmpc_status dmpc_plan_destroy(dmpc_plan* plan);
+
+/* Forward pass: Alg. sqp for every problem of the plan.
+ *   data      [data_len]  problem data (read only)
+ *   sol       [sol_len]   in: initial guess per opts->init; out: x, u after the last
+ *                         line search and lambda of the last QP
+ *   workspace [plan_workspace_size bytes]; holds what the backward pass reuses
+ *             (the last QP's data, its solution and the Schur/preconditioner
+ *             blocks); must stay untouched until dmpc_solve_backward
+ *   status    [count] int32 per-problem status bits (DMPC_PROB_*)
+ *   info      [count][4] int32: forward PCG iterations (sum over SQP iterations),
+ *             backward PCG iterations, index of the last accepted step size,
+ *             SQP iterations run
+ *   stream    a hipStream_t (NULL = default stream) */
+dmpc_status dmpc_solve(dmpc_plan* plan, const float* data, float* sol, void* workspace,
+                       int32_t* status, int32_t* info, void* stream);
+
+/* Backward pass (Alg. backward): VJP of the last QP's solution map with the
+ * linearisation point held fixed.
+ *   dl_dsol [sol_len]  cotangent laid out like the solution arena: dl/dx, dl/du and
+ *                      dl/dlambda (the paper's pass uses dl/dlambda = 0)
+ *   adj     [sol_len]  out: x~, u~, lambda~ of Eq. ocp:backward; in: lambda~ as the
+ *                      PCG warm start when opts->bwd_warm_start
+ *   grad    [data_len] out: dl/d(data), laid out like the data arena: A, B, c (LTV),
+ *                      Qd, q, Rd, r (DIAG), theta, xref (SOFTPLUS; wscale, wfix get 0),
+ *                      x_s; parameters of CARTPOLE/BICYCLE dynamics get 0.  Floats of
+ *                      the arena outside the problems' blocks are not written. */
+dmpc_status dmpc_solve_backward(dmpc_plan* plan, const float* data, const float* dl_dsol,
+                                float* adj, float* grad, void* workspace, int32_t* status,
+                                int32_t* info, void* stream);
+
+/* The same two passes for problem `index` of the plan alone, one launch each
+ * (the plain one-problem-per-launch form). */
+dmpc_status dmpc_solve_one(dmpc_plan* plan, int32_t index, const float* data, float* sol,
+                           void* workspace, int32_t* status, int32_t* info, void* stream);
+dmpc_status dmpc_solve_backward_one(dmpc_plan* plan, int32_t index, const float* data,
+                                    const float* dl_dsol, float* adj, float* grad,
+                                    void* workspace, int32_t* status, int32_t* info,
+                                    void* stream);
+
+/* Float offsets, inside the workspace, of what the forward pass keeps for the
+ * backward pass of problem `index` (host only; no GPU work):
+ *   out[0] x at the last linearisation point [T+1][nx]   out[1] u there [T][nu]
+ *   out[2] x of the last QP solution [T+1][nx]           out[3] its u [T][nu]
+ *   out[4] its multipliers [T+1][nx]
+ *   out[5] projected cost Hessian diagonal Qd [T+1][nx]  out[6] projected Rd [T][nu]
+ * Used to inspect the last QP (Alg. sqp returns the QP matrices). */
+dmpc_status dmpc_workspace_offsets(const dmpc_plan* plan, int32_t index, int64_t* out);
+
+/* Human-readable name of a return code (static string). */
+const char* dmpc_status_string(dmpc_status s);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t dmpc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DMPC_H */

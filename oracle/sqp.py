@@ -93,7 +93,8 @@ def sqp_step(prob, x, u, alphas=ALPHAS, eta=ETA):
     a, idx, det = line_search(prob, x, u, sol["x"], sol["u"], alphas, eta)
     xn = x + a * (sol["x"] - x)
     un = u + a * (sol["u"] - u)
-    return xn, un, sol["lam"], dict(qp=qpd, sol=sol, alpha=a, alpha_idx=idx, ls=det)
+    return xn, un, sol["lam"], dict(qp=qpd, sol=sol, alpha=a, alpha_idx=idx, ls=det,
+                                      xbar=x, ubar=u)
 
 
 def sqp(prob, iters, alphas=ALPHAS, eta=ETA, x=None, u=None):

@@ -1,0 +1,132 @@
+"""ctypes view of the C ABI in include/dmpc.h (argument marshalling only).
+
+The shared library is the in-tree ``libdmpc.so`` built by
+``paper_2510_06179_amd.build``.  Loading fails loudly when it is missing: there
+is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libdmpc.so")
+
+# enums of dmpc.h
+DMPC_OK, DMPC_ERR_INVALID_ARG, DMPC_ERR_UNSUPPORTED, DMPC_ERR_HIP, DMPC_ERR_NOMEM = range(5)
+DYN_LTV, DYN_CARTPOLE, DYN_BICYCLE = 0, 1, 2
+COST_DIAG, COST_SOFTPLUS = 0, 1
+INIT_GIVEN, INIT_ROLLOUT = 0, 1
+PROB_PCG_MAXITER, PROB_NONPD, PROB_NONFINITE, PROB_LS_FALLBACK, PROB_BWD_PCG_MAXITER = 1, 2, 4, 8, 16
+
+DYN_KIND = {"ltv": DYN_LTV, "cartpole": DYN_CARTPOLE, "bicycle": DYN_BICYCLE}
+COST_KIND = {"diag": COST_DIAG, "softplus": COST_SOFTPLUS}
+INIT_KIND = {"given": INIT_GIVEN, "rollout": INIT_ROLLOUT}
+
+EXPORTED = (
+    "dmpc_default_opts", "dmpc_create", "dmpc_destroy", "dmpc_validate", "dmpc_workspace_size",
+    "dmpc_plan_create", "dmpc_plan_workspace_size", "dmpc_plan_destroy", "dmpc_solve",
+    "dmpc_solve_backward", "dmpc_solve_one", "dmpc_solve_backward_one", "dmpc_status_string",
+    "dmpc_version", "dmpc_workspace_offsets",
+)
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [
+        ("T", ctypes.c_int32), ("nx", ctypes.c_int32), ("nu", ctypes.c_int32),
+        ("dyn", ctypes.c_int32), ("cost", ctypes.c_int32), ("cost_phases", ctypes.c_int32),
+        ("cost_nw", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("dyn_off", ctypes.c_int64), ("cost_off", ctypes.c_int64),
+        ("x0_off", ctypes.c_int64), ("sol_off", ctypes.c_int64),
+    ]
+
+
+PROBLEM_DTYPE = np.dtype([
+    ("T", "<i4"), ("nx", "<i4"), ("nu", "<i4"), ("dyn", "<i4"), ("cost", "<i4"),
+    ("cost_phases", "<i4"), ("cost_nw", "<i4"), ("reserved", "<i4"),
+    ("dyn_off", "<i8"), ("cost_off", "<i8"), ("x0_off", "<i8"), ("sol_off", "<i8"),
+])
+assert PROBLEM_DTYPE.itemsize == ctypes.sizeof(Problem) == 64
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [
+        ("sqp_iters", ctypes.c_int32), ("pcg_max_iter", ctypes.c_int32),
+        ("pcg_tol", ctypes.c_float), ("pcg_abs_tol", ctypes.c_float),
+        ("n_alphas", ctypes.c_int32), ("alphas", ctypes.c_float * 8),
+        ("ls_eta", ctypes.c_float), ("init", ctypes.c_int32),
+        ("bwd_warm_start", ctypes.c_int32), ("bwd_pcg_max_iter", ctypes.c_int32),
+        ("bwd_pcg_tol", ctypes.c_float), ("block_threads", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
+    ]
+
+
+class DmpcError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load():
+    """Load libdmpc.so (once).  Raises DmpcError if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise DmpcError(f"{LIB_PATH} is missing: run `python -m paper_2510_06179_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    P = ctypes.POINTER
+    sig = {
+        "dmpc_default_opts": (None, [P(Opts)]),
+        "dmpc_create": (i32, [P(vp), ctypes.c_int]),
+        "dmpc_destroy": (i32, [vp]),
+        "dmpc_validate": (i32, [vp, i32, i64, i64, P(Opts), P(i32)]),
+        "dmpc_workspace_size": (i32, [vp, i32, P(Opts), P(ctypes.c_size_t)]),
+        "dmpc_plan_create": (i32, [vp, vp, i32, i64, i64, P(Opts), P(vp)]),
+        "dmpc_plan_workspace_size": (i32, [vp, P(ctypes.c_size_t)]),
+        "dmpc_plan_destroy": (i32, [vp]),
+        "dmpc_solve": (i32, [vp, vp, vp, vp, vp, vp, vp]),
+        "dmpc_solve_backward": (i32, [vp, vp, vp, vp, vp, vp, vp, vp, vp]),
+        "dmpc_solve_one": (i32, [vp, i32, vp, vp, vp, vp, vp, vp]),
+        "dmpc_solve_backward_one": (i32, [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]),
+        "dmpc_status_string": (ctypes.c_char_p, [i32]),
+        "dmpc_version": (i32, []),
+        "dmpc_workspace_offsets": (i32, [vp, i32, P(i64)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(rc, what=""):
+    if rc != DMPC_OK:
+        msg = load().dmpc_status_string(rc).decode()
+        raise DmpcError(f"{what}: {msg} (code {rc})")
+
+
+def make_opts(sqp_iters=1, pcg_tol=1e-6, pcg_abs_tol=0.0, pcg_max_iter=0,
+              alphas=(1.0, 0.7, 0.3, 0.1, 0.01), ls_eta=0.4, init="given",
+              bwd_warm_start=False, bwd_pcg_tol=None, bwd_pcg_max_iter=0, block_threads=0):
+    o = Opts()
+    load().dmpc_default_opts(ctypes.byref(o))
+    o.sqp_iters = int(sqp_iters)
+    o.pcg_tol = float(pcg_tol)
+    o.pcg_abs_tol = float(pcg_abs_tol)
+    o.pcg_max_iter = int(pcg_max_iter)
+    o.n_alphas = len(alphas)
+    for i in range(8):
+        o.alphas[i] = float(alphas[i]) if i < len(alphas) else 0.0
+    o.ls_eta = float(ls_eta)
+    o.init = INIT_KIND[init] if isinstance(init, str) else int(init)
+    o.bwd_warm_start = int(bool(bwd_warm_start))
+    o.bwd_pcg_tol = float(pcg_tol if bwd_pcg_tol is None else bwd_pcg_tol)
+    o.bwd_pcg_max_iter = int(bwd_pcg_max_iter)
+    o.block_threads = int(block_threads)
+    return o

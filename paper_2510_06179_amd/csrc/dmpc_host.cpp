@@ -1,0 +1,463 @@
+// Host runtime of the C ABI declared in include/dmpc.h: validation, plan
+// construction (grouping problems by kernel instantiation, workspace layout,
+// descriptor upload) and launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "dmpc.h"
+#include "dmpc_internal.h"
+
+using namespace dmpc;
+
+struct dmpc_handle {
+  int device;
+};
+
+struct Group {
+  LaunchCfg cfg;
+  int first, count;
+};
+
+struct dmpc_plan {
+  dmpc_handle* h;
+  int count;
+  std::vector<ProbRec> recs;  // grouped; within a group heaviest first
+  std::vector<int> pos;       // pos[problem index] = record index
+  std::vector<int> grp;       // grp[record index] = group index
+  std::vector<Group> groups;
+  ProbRec* d_recs;
+  size_t ws_bytes;
+  dmpc_opts opts;
+};
+
+namespace {
+
+const int kStateSizes[] = {2, 3, 4, 8, 12, 16};
+
+bool nx_supported(int nx) {
+  for (int v : kStateSizes)
+    if (v == nx) return true;
+  return false;
+}
+
+bool finite_nonneg(float v) { return std::isfinite(v) && v >= 0.f; }
+
+dmpc_status check_opts(const dmpc_opts* o) {
+  if (!o) return DMPC_ERR_INVALID_ARG;
+  if (o->sqp_iters < 1 || o->sqp_iters > 1000) return DMPC_ERR_INVALID_ARG;
+  if (o->pcg_max_iter < 0 || o->bwd_pcg_max_iter < 0) return DMPC_ERR_INVALID_ARG;
+  if (!finite_nonneg(o->pcg_tol) || !finite_nonneg(o->pcg_abs_tol) || !finite_nonneg(o->bwd_pcg_tol))
+    return DMPC_ERR_INVALID_ARG;
+  if (o->n_alphas < 1 || o->n_alphas > kMaxAlphas) return DMPC_ERR_INVALID_ARG;
+  for (int i = 0; i < o->n_alphas; ++i) {
+    const float a = o->alphas[i];
+    if (!(a > 0.f && a <= 1.f)) return DMPC_ERR_INVALID_ARG;
+    if (i > 0 && !(a < o->alphas[i - 1])) return DMPC_ERR_INVALID_ARG;
+  }
+  if (!(o->ls_eta > 0.f && o->ls_eta < 1.f)) return DMPC_ERR_INVALID_ARG;
+  if (o->init != DMPC_INIT_GIVEN && o->init != DMPC_INIT_ROLLOUT) return DMPC_ERR_INVALID_ARG;
+  if (o->bwd_warm_start != 0 && o->bwd_warm_start != 1) return DMPC_ERR_INVALID_ARG;
+  if (o->block_threads != 0 &&
+      (o->block_threads < 64 || o->block_threads > 1024 || o->block_threads % 64 != 0))
+    return DMPC_ERR_INVALID_ARG;
+  for (int r : o->reserved)
+    if (r != 0) return DMPC_ERR_INVALID_ARG;
+  return DMPC_OK;
+}
+
+bool in_arena(int64_t off, int64_t len, int64_t arena) {
+  return off >= 0 && len >= 0 && off <= arena && len <= arena - off;
+}
+
+dmpc_status check_problem(const dmpc_problem& p, int64_t data_len, int64_t sol_len) {
+  if (p.T < 1 || p.T > 1000000) return DMPC_ERR_INVALID_ARG;
+  if (p.nx < 1 || p.nx > 16 || p.nu < 1 || p.nu > kMaxNu) return DMPC_ERR_INVALID_ARG;
+  if (p.reserved != 0) return DMPC_ERR_INVALID_ARG;
+  switch (p.dyn) {
+    case DMPC_DYN_LTV:
+      break;
+    case DMPC_DYN_CARTPOLE:
+      if (p.nx != 4 || p.nu != 1) return DMPC_ERR_INVALID_ARG;
+      break;
+    case DMPC_DYN_BICYCLE:
+      if (p.nx != 8 || p.nu != 2) return DMPC_ERR_INVALID_ARG;
+      break;
+    default:
+      return DMPC_ERR_INVALID_ARG;
+  }
+  switch (p.cost) {
+    case DMPC_COST_DIAG:
+      if (p.cost_phases != 0 || p.cost_nw != 0) return DMPC_ERR_INVALID_ARG;
+      break;
+    case DMPC_COST_SOFTPLUS:
+      if (p.cost_phases < 1 || p.cost_phases > p.T + 1 || p.cost_nw < 0 || p.cost_nw > p.nx)
+        return DMPC_ERR_INVALID_ARG;
+      break;
+    default:
+      return DMPC_ERR_INVALID_ARG;
+  }
+  if (!in_arena(p.dyn_off, dyn_block_len(p.T, p.nx, p.nu, p.dyn), data_len))
+    return DMPC_ERR_INVALID_ARG;
+  if (!in_arena(p.cost_off, cost_block_len(p.T, p.nx, p.nu, p.cost, p.cost_phases, p.cost_nw),
+                data_len))
+    return DMPC_ERR_INVALID_ARG;
+  if (!in_arena(p.x0_off, p.nx, data_len)) return DMPC_ERR_INVALID_ARG;
+  if (!in_arena(p.sol_off, sol_block_len(p.T, p.nx, p.nu), sol_len)) return DMPC_ERR_INVALID_ARG;
+  return DMPC_OK;
+}
+
+// Kernel mapping of one problem: rows R = (T+1)*nx spread over the threads.
+bool choose_cfg(const dmpc_problem& p, int force_bt, LaunchCfg* c) {
+  const int64_t R = (int64_t)(p.T + 1) * p.nx;
+  c->nx = p.nx;
+  auto rup = [](int64_t v) { return (int)((v + 63) / 64 * 64); };
+  if (force_bt > 0) {
+    const int bt = force_bt;
+    struct Opt { int slots, maxbt, reg; };
+    const Opt opts[] = {{1, 256, 1}, {1, 512, 1}, {1, 1024, 1}, {2, 256, 1},
+                        {4, 256, 0}, {8, 256, 0}, {8, 512, 0}};
+    for (const Opt& o : opts) {
+      if (bt <= o.maxbt && R <= (int64_t)o.slots * bt) {
+        c->slots = o.slots;
+        c->maxbt = o.maxbt;
+        c->reg = o.reg;
+        c->bt = bt;
+        return true;
+      }
+    }
+    return false;
+  }
+  if (R <= 256) {
+    *c = LaunchCfg{p.nx, 1, 256, 1, std::max(64, rup(R)), 0, 0};
+  } else if (R <= 512) {
+    *c = LaunchCfg{p.nx, 1, 512, 1, rup(R), 0, 0};
+  } else if (R <= 1024) {
+    *c = LaunchCfg{p.nx, 4, 256, 0, rup((R + 3) / 4), 0, 0};
+  } else if (R <= 2048) {
+    *c = LaunchCfg{p.nx, 8, 256, 0, rup((R + 7) / 8), 0, 0};
+  } else if (R <= 4096) {
+    *c = LaunchCfg{p.nx, 8, 512, 0, rup((R + 7) / 8), 0, 0};
+  } else {
+    return false;
+  }
+  return true;
+}
+
+KArgs make_args(const dmpc_plan* pl, const float* data, float* sol, void* ws, const float* dl,
+                float* adj, float* grad, int32_t* status, int32_t* info) {
+  KArgs a;
+  std::memset(&a, 0, sizeof(a));
+  const dmpc_opts& o = pl->opts;
+  a.recs = pl->d_recs;
+  a.data = data;
+  a.sol = sol;
+  a.ws = (float*)ws;
+  a.dl = dl;
+  a.adj = adj;
+  a.grad = grad;
+  a.status = status;
+  a.info = info;
+  a.sqp_iters = o.sqp_iters;
+  a.pcg_max_iter = o.pcg_max_iter;
+  a.n_alphas = o.n_alphas;
+  a.init = o.init;
+  a.bwd_warm = o.bwd_warm_start;
+  a.bwd_max_iter = o.bwd_pcg_max_iter;
+  a.pcg_tol = o.pcg_tol;
+  a.pcg_abs_tol = o.pcg_abs_tol;
+  a.ls_eta = o.ls_eta;
+  a.bwd_tol = o.bwd_pcg_tol;
+  for (int i = 0; i < kMaxAlphas; ++i) a.alphas[i] = i < o.n_alphas ? o.alphas[i] : 0.f;
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+void dmpc_default_opts(dmpc_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->sqp_iters = 1;
+  o->pcg_tol = 1e-6f;
+  o->n_alphas = 5;
+  const float al[5] = {1.0f, 0.7f, 0.3f, 0.1f, 0.01f};
+  for (int i = 0; i < 5; ++i) o->alphas[i] = al[i];
+  o->ls_eta = 0.4f;
+  o->init = DMPC_INIT_GIVEN;
+  o->bwd_pcg_tol = 1e-6f;
+}
+
+const char* dmpc_status_string(dmpc_status s) {
+  switch (s) {
+    case DMPC_OK: return "ok";
+    case DMPC_ERR_INVALID_ARG: return "invalid argument";
+    case DMPC_ERR_UNSUPPORTED: return "unsupported problem shape";
+    case DMPC_ERR_HIP: return "HIP runtime error";
+    case DMPC_ERR_NOMEM: return "out of memory or buffer too small";
+  }
+  return "unknown status";
+}
+
+int32_t dmpc_version(void) { return 100; }
+
+dmpc_status dmpc_validate(const dmpc_problem* problems, int32_t count, int64_t data_len,
+                          int64_t sol_len, const dmpc_opts* opts, int32_t* bad_index) {
+  if (bad_index) *bad_index = -1;
+  if (count < 0 || (count > 0 && !problems) || data_len < 0 || sol_len < 0)
+    return DMPC_ERR_INVALID_ARG;
+  dmpc_status st = check_opts(opts);
+  if (st != DMPC_OK) return st;
+  for (int i = 0; i < count; ++i) {
+    st = check_problem(problems[i], data_len, sol_len);
+    if (st != DMPC_OK) {
+      if (bad_index) *bad_index = i;
+      return st;
+    }
+  }
+  // solution blocks must not overlap (each workgroup writes its own block)
+  std::vector<std::pair<int64_t, int>> sb;
+  sb.reserve(count);
+  for (int i = 0; i < count; ++i) sb.push_back({problems[i].sol_off, i});
+  std::sort(sb.begin(), sb.end());
+  for (size_t k = 1; k < sb.size(); ++k) {
+    const dmpc_problem& p = problems[sb[k - 1].second];
+    if (sb[k - 1].first + sol_block_len(p.T, p.nx, p.nu) > sb[k].first) {
+      if (bad_index) *bad_index = sb[k].second;
+      return DMPC_ERR_INVALID_ARG;
+    }
+  }
+  for (int i = 0; i < count; ++i) {
+    LaunchCfg c;
+    if (!nx_supported(problems[i].nx) ||
+        !choose_cfg(problems[i], opts->block_threads, &c)) {
+      if (bad_index) *bad_index = i;
+      return DMPC_ERR_UNSUPPORTED;
+    }
+  }
+  return DMPC_OK;
+}
+
+dmpc_status dmpc_workspace_size(const dmpc_problem* problems, int32_t count,
+                                const dmpc_opts* opts, size_t* bytes) {
+  if (!bytes || count < 0 || (count > 0 && !problems)) return DMPC_ERR_INVALID_ARG;
+  (void)opts;
+  int64_t total = 0;
+  for (int i = 0; i < count; ++i) {
+    const dmpc_problem& p = problems[i];
+    if (p.T < 1 || p.nx < 1 || p.nu < 1) return DMPC_ERR_INVALID_ARG;
+    total += ws_layout(p.T, p.nx, p.nu, p.dyn).total;
+  }
+  *bytes = (size_t)total * sizeof(float);
+  return DMPC_OK;
+}
+
+dmpc_status dmpc_create(dmpc_handle** h, int device) {
+  if (!h) return DMPC_ERR_INVALID_ARG;
+  *h = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess) return DMPC_ERR_HIP;
+  if (device < 0 || device >= n) return DMPC_ERR_INVALID_ARG;
+  dmpc_handle* p = new (std::nothrow) dmpc_handle;
+  if (!p) return DMPC_ERR_NOMEM;
+  p->device = device;
+  *h = p;
+  return DMPC_OK;
+}
+
+dmpc_status dmpc_destroy(dmpc_handle* h) {
+  delete h;
+  return DMPC_OK;
+}
+
+dmpc_status dmpc_plan_create(dmpc_handle* h, const dmpc_problem* problems, int32_t count,
+                             int64_t data_len, int64_t sol_len, const dmpc_opts* opts,
+                             dmpc_plan** plan) {
+  if (!h || !plan) return DMPC_ERR_INVALID_ARG;
+  *plan = nullptr;
+  dmpc_status st = dmpc_validate(problems, count, data_len, sol_len, opts, nullptr);
+  if (st != DMPC_OK) return st;
+  dmpc_plan* pl = new (std::nothrow) dmpc_plan;
+  if (!pl) return DMPC_ERR_NOMEM;
+  pl->h = h;
+  pl->count = count;
+  pl->opts = *opts;
+  pl->d_recs = nullptr;
+
+  // kernel configuration per problem, then group (stable: heaviest first)
+  std::vector<LaunchCfg> cfg(count);
+  std::vector<int64_t> work(count);
+  for (int i = 0; i < count; ++i) {
+    choose_cfg(problems[i], opts->block_threads, &cfg[i]);
+    const dmpc_problem& p = problems[i];
+    work[i] = (int64_t)(p.T + 1) * p.nx * p.nx;
+  }
+  std::vector<int> order(count);
+  for (int i = 0; i < count; ++i) order[i] = i;
+  auto key = [&](int i) {
+    const LaunchCfg& c = cfg[i];
+    return std::make_tuple(c.nx, c.slots, c.maxbt, c.reg, c.bt);
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    if (key(a) != key(b)) return key(a) < key(b);
+    return work[a] > work[b];
+  });
+  pl->recs.resize(count);
+  pl->pos.resize(count);
+  pl->grp.resize(count);
+  int64_t ws_off = 0;
+  for (int k = 0; k < count; ++k) {
+    const int i = order[k];
+    const dmpc_problem& p = problems[i];
+    ProbRec r;
+    std::memset(&r, 0, sizeof(r));
+    r.T = p.T;
+    r.nx = p.nx;
+    r.nu = p.nu;
+    r.dyn = p.dyn;
+    r.cost = p.cost;
+    r.phases = p.cost_phases;
+    r.nw = p.cost_nw;
+    r.index = i;
+    r.dyn_off = p.dyn_off;
+    r.cost_off = p.cost_off;
+    r.x0_off = p.x0_off;
+    r.sol_off = p.sol_off;
+    r.ws_off = ws_off;
+    ws_off += ws_layout(p.T, p.nx, p.nu, p.dyn).total;
+    pl->recs[k] = r;
+    pl->pos[i] = k;
+    if (k == 0 || key(order[k - 1]) != key(i)) {
+      Group g;
+      g.cfg = cfg[i];
+      g.first = k;
+      g.count = 0;
+      g.cfg.lds_bytes = 0;
+      pl->groups.push_back(g);
+    }
+    Group& g = pl->groups.back();
+    g.count += 1;
+    g.cfg.lds_bytes = std::max(g.cfg.lds_bytes, (size_t)lds_floats(p.T, p.nx, p.nu) * sizeof(float));
+    pl->grp[k] = (int)pl->groups.size() - 1;
+  }
+  pl->ws_bytes = (size_t)ws_off * sizeof(float);
+  for (Group& g : pl->groups) {
+    g.cfg.grid = g.count;
+    if (g.cfg.lds_bytes > 160 * 1024 || !kernel_available(g.cfg.nx, g.cfg.slots, g.cfg.maxbt, g.cfg.reg)) {
+      delete pl;
+      return DMPC_ERR_UNSUPPORTED;
+    }
+  }
+  if (count > 0) {
+    int prev = 0;
+    if (hipGetDevice(&prev) != hipSuccess || hipSetDevice(h->device) != hipSuccess) {
+      delete pl;
+      return DMPC_ERR_HIP;
+    }
+    const size_t bytes = sizeof(ProbRec) * (size_t)count;
+    if (hipMalloc((void**)&pl->d_recs, bytes) != hipSuccess) {
+      hipSetDevice(prev);
+      delete pl;
+      return DMPC_ERR_NOMEM;
+    }
+    if (hipMemcpy(pl->d_recs, pl->recs.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+      hipFree(pl->d_recs);
+      hipSetDevice(prev);
+      delete pl;
+      return DMPC_ERR_HIP;
+    }
+    hipSetDevice(prev);
+  }
+  *plan = pl;
+  return DMPC_OK;
+}
+
+dmpc_status dmpc_plan_workspace_size(const dmpc_plan* plan, size_t* bytes) {
+  if (!plan || !bytes) return DMPC_ERR_INVALID_ARG;
+  *bytes = plan->ws_bytes;
+  return DMPC_OK;
+}
+
+dmpc_status dmpc_workspace_offsets(const dmpc_plan* plan, int32_t index, int64_t* out) {
+  if (!plan || !out || index < 0 || index >= plan->count) return DMPC_ERR_INVALID_ARG;
+  const ProbRec& r = plan->recs[plan->pos[index]];
+  const WsLayout L = ws_layout(r.T, r.nx, r.nu, r.dyn);
+  const int64_t v[7] = {L.xlin, L.ulin, L.xp, L.up, L.lam, L.Qd, L.Rd};
+  for (int i = 0; i < 7; ++i) out[i] = r.ws_off + v[i];
+  return DMPC_OK;
+}
+
+dmpc_status dmpc_plan_destroy(dmpc_plan* plan) {
+  if (!plan) return DMPC_OK;
+  if (plan->d_recs) hipFree(plan->d_recs);
+  delete plan;
+  return DMPC_OK;
+}
+
+static dmpc_status run(dmpc_plan* pl, int index, bool fwd, const float* data, float* sol,
+                       const float* dl, float* adj, float* grad, void* ws, int32_t* status,
+                       int32_t* info, void* stream) {
+  if (!pl) return DMPC_ERR_INVALID_ARG;
+  if (pl->count == 0) return DMPC_OK;
+  if (!data || !ws || !status || !info) return DMPC_ERR_INVALID_ARG;
+  if (fwd && !sol) return DMPC_ERR_INVALID_ARG;
+  if (!fwd && (!dl || !adj || !grad)) return DMPC_ERR_INVALID_ARG;
+  if (index >= pl->count) return DMPC_ERR_INVALID_ARG;
+  int prev = 0;
+  if (hipGetDevice(&prev) != hipSuccess) return DMPC_ERR_HIP;
+  if (prev != pl->h->device && hipSetDevice(pl->h->device) != hipSuccess) return DMPC_ERR_HIP;
+  KArgs a = make_args(pl, data, sol, ws, dl, adj, grad, status, info);
+  int rc = 0;
+  if (index >= 0) {
+    const int k = pl->pos[index];
+    LaunchCfg c = pl->groups[pl->grp[k]].cfg;
+    c.grid = 1;
+    a.first = k;
+    a.count = 1;
+    rc = fwd ? launch_forward(c, a, stream) : launch_backward(c, a, stream);
+  } else {
+    for (const Group& g : pl->groups) {
+      a.first = g.first;
+      a.count = g.count;
+      rc = fwd ? launch_forward(g.cfg, a, stream) : launch_backward(g.cfg, a, stream);
+      if (rc != 0) break;
+    }
+  }
+  if (prev != pl->h->device) hipSetDevice(prev);
+  if (rc == -1) return DMPC_ERR_UNSUPPORTED;
+  return rc == 0 ? DMPC_OK : DMPC_ERR_HIP;
+}
+
+dmpc_status dmpc_solve(dmpc_plan* plan, const float* data, float* sol, void* workspace,
+                       int32_t* status, int32_t* info, void* stream) {
+  return run(plan, -1, true, data, sol, nullptr, nullptr, nullptr, workspace, status, info, stream);
+}
+
+dmpc_status dmpc_solve_backward(dmpc_plan* plan, const float* data, const float* dl_dsol,
+                                float* adj, float* grad, void* workspace, int32_t* status,
+                                int32_t* info, void* stream) {
+  return run(plan, -1, false, data, nullptr, dl_dsol, adj, grad, workspace, status, info, stream);
+}
+
+dmpc_status dmpc_solve_one(dmpc_plan* plan, int32_t index, const float* data, float* sol,
+                           void* workspace, int32_t* status, int32_t* info, void* stream) {
+  if (index < 0) return DMPC_ERR_INVALID_ARG;
+  return run(plan, index, true, data, sol, nullptr, nullptr, nullptr, workspace, status, info,
+             stream);
+}
+
+dmpc_status dmpc_solve_backward_one(dmpc_plan* plan, int32_t index, const float* data,
+                                    const float* dl_dsol, float* adj, float* grad,
+                                    void* workspace, int32_t* status, int32_t* info,
+                                    void* stream) {
+  if (index < 0) return DMPC_ERR_INVALID_ARG;
+  return run(plan, index, false, data, nullptr, dl_dsol, adj, grad, workspace, status, info,
+             stream);
+}
+
+}  // extern "C"

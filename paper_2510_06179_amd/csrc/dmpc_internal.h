@@ -1,0 +1,137 @@
+// Internal declarations shared by the host runtime (dmpc_host.cpp) and the
+// device code (dmpc_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "dmpc.h"
+
+#if defined(__HIP__)
+#define DMPC_HD __host__ __device__
+#else
+#define DMPC_HD
+#endif
+
+namespace dmpc {
+
+constexpr float kPdEps = 1e-6f;   // eigenvalue floor of the PD projection (Sec. 3.1)
+constexpr int kMaxAlphas = 8;
+constexpr int kMaxNu = 16;
+constexpr int kCartpoleParams = 5;
+constexpr int kBicycleParams = 16;
+constexpr int kAlignFloats = 64;  // per-problem workspace alignment (256 B)
+
+// Device record of one problem (96 bytes).
+struct ProbRec {
+  int32_t T, nx, nu, dyn, cost, phases, nw, index;  // index: slot in status/info
+  int64_t dyn_off, cost_off, x0_off, sol_off;
+  int64_t ws_off;                                   // float offset into the workspace
+  int64_t pad[3];
+};
+
+// Per-problem workspace layout (float offsets from ProbRec::ws_off).
+struct WsLayout {
+  int64_t Qd, iQ, q, Rd, iR, r;   // projected Hessian diagonals, inverses, linear terms
+  int64_t A, B, c;                // linearised dynamics (nonlinear models only)
+  int64_t Dinv;                   // diagonal Schur blocks inverted [N][nx][nx]
+  int64_t blk;                    // saved rows of S^ and Phi^-1: [N*nx][6*nx]
+  int64_t xp, up, lam;            // last QP solution and multipliers
+  int64_t xlin, ulin;             // last linearisation point
+  int64_t total;
+};
+
+DMPC_HD inline int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+DMPC_HD inline WsLayout ws_layout(int T, int nx, int nu, int dyn) {
+  const int64_t N = T + 1, R = N * nx, TM = (int64_t)T * nu;
+  WsLayout L;
+  int64_t o = 0;
+  L.Qd = o; o += R;
+  L.iQ = o; o += R;
+  L.q = o; o += R;
+  L.Rd = o; o += TM;
+  L.iR = o; o += TM;
+  L.r = o; o += TM;
+  o = align_up(o, 4);
+  if (dyn != DMPC_DYN_LTV) {
+    L.A = o; o += (int64_t)T * nx * nx;
+    L.B = o; o += (int64_t)T * nx * nu;
+    L.c = o; o += (int64_t)T * nx;
+  } else {
+    L.A = L.B = L.c = -1;
+  }
+  o = align_up(o, 4);
+  L.Dinv = o; o += N * nx * nx;
+  o = align_up(o, 4);
+  L.blk = o; o += R * 6 * nx;
+  L.xp = o; o += R;
+  L.up = o; o += TM;
+  L.lam = o; o += R;
+  L.xlin = o; o += R;
+  L.ulin = o; o += TM;
+  L.total = align_up(o, kAlignFloats);
+  return L;
+}
+
+// Sizes (floats) of the data blocks of a problem.
+DMPC_HD inline int64_t dyn_block_len(int T, int nx, int nu, int dyn) {
+  if (dyn == DMPC_DYN_LTV) return (int64_t)T * (nx * nx + nx * nu + nx);
+  if (dyn == DMPC_DYN_CARTPOLE) return kCartpoleParams;
+  return kBicycleParams;
+}
+DMPC_HD inline int64_t cost_block_len(int T, int nx, int nu, int cost, int phases, int nw) {
+  if (cost == DMPC_COST_DIAG) return 2 * (int64_t)(T + 1) * nx + 2 * (int64_t)T * nu;
+  return (int64_t)phases * (nw + nu) + (nw + nu) + (nx - nw) + nx;
+}
+DMPC_HD inline int64_t sol_block_len(int T, int nx, int nu) {
+  return 2 * (int64_t)(T + 1) * nx + (int64_t)T * nu;
+}
+
+// LDS floats a workgroup needs for a problem (forward and backward kernels).
+DMPC_HD inline int64_t lds_floats(int T, int nx, int nu) {
+  const int64_t N = T + 1, R = N * nx, TM = (int64_t)T * nu;
+  return 3 * R + 2 * TM              // xbar/ubar/xp/up (fwd) or xt/ut/xp/up/lam (bwd)
+         + 2 * (R + 2 * nx)          // two padded windows
+         + 4 * N * nx                // Gauss-Jordan pivot rows, double buffered
+         + 2 * 64                    // scalar reductions
+         + 2 * (kMaxAlphas + 1) * N  // line-search stage costs and defects
+         + 2 * (kMaxAlphas + 1) + 2; // per-candidate sums
+}
+
+// Launch-time arguments of the kernels.
+struct KArgs {
+  const ProbRec* recs;
+  int32_t count;
+  int32_t first;        // first record of this launch (plain mode uses count = 1)
+  const float* data;
+  float* sol;
+  float* ws;
+  const float* dl;
+  float* adj;
+  float* grad;
+  int32_t* status;
+  int32_t* info;
+  int32_t sqp_iters, pcg_max_iter, n_alphas, init;
+  int32_t bwd_warm, bwd_max_iter;
+  float pcg_tol, pcg_abs_tol, ls_eta, bwd_tol;
+  float alphas[kMaxAlphas];
+};
+
+// One launch group: problems sharing a kernel instantiation.
+struct LaunchCfg {
+  int nx;          // template state size
+  int slots;       // rows per thread
+  int maxbt;       // launch bound of the instantiation
+  int reg;         // 1: Schur/preconditioner rows kept in registers
+  int bt;          // threads per workgroup
+  int grid;        // workgroups
+  size_t lds_bytes;
+};
+
+// Implemented in dmpc_kernels.hip.
+bool kernel_available(int nx, int slots, int maxbt, int reg);
+int launch_forward(const LaunchCfg& cfg, const KArgs& a, void* stream);
+int launch_backward(const LaunchCfg& cfg, const KArgs& a, void* stream);
+
+}  // namespace dmpc

@@ -1,0 +1,20 @@
+// Kernel instantiations for nx = 2 (see dmpc_device.h).
+#include "dmpc_device.h"
+
+namespace dmpc {
+
+#define DMPC_K(NX, SL, MB, RG) \
+  {NX, SL, MB, RG, forward_kernel<NX, SL, MB, (RG != 0)>, backward_kernel<NX, SL, MB, (RG != 0)>}
+
+// (rows per thread, launch bound, register-resident rows)
+static const KEntry kEntries[] = {
+    DMPC_K(2, 1, 256, 1), DMPC_K(2, 2, 256, 1), DMPC_K(2, 1, 512, 1), DMPC_K(2, 1, 1024, 1),
+    DMPC_K(2, 4, 256, 0), DMPC_K(2, 8, 256, 0), DMPC_K(2, 8, 512, 0),
+};
+
+const KEntry* kernel_entries_nx2(int* n) {
+  *n = (int)(sizeof(kEntries) / sizeof(kEntries[0]));
+  return kEntries;
+}
+
+}  // namespace dmpc

@@ -1,0 +1,146 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+function include/dmpc.h declares, and its host-only validation and workspace
+sizing behave as documented."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2510_06179_amd import _lib, batch
+from paper_2510_06179_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "dmpc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dmpc_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    names = _declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(_lib.EXPORTED)
+
+
+def test_version_and_status_strings():
+    lib = _lib.load()
+    assert lib.dmpc_version() >= 100
+    for code in range(5):
+        assert lib.dmpc_status_string(code)
+    assert lib.dmpc_status_string(0) == b"ok"
+
+
+def _validate(pk, opts=None):
+    lib = _lib.load()
+    o = opts or _lib.make_opts()
+    bad = ctypes.c_int32(-7)
+    d = np.ascontiguousarray(pk.descs)
+    rc = lib.dmpc_validate(d.ctypes.data_as(ctypes.c_void_p), len(d), pk.data_len, pk.sol_len,
+                           ctypes.byref(o), ctypes.byref(bad))
+    return rc, bad.value
+
+
+def test_validate_accepts_benchmark_batches():
+    for probs in (W.lq_batch(0), W.cartpole_batch(0, batch=4), W.bicycle_batch(0, batch=2),
+                  W.ltv_uneven_batch(0, batch=16)):
+        rc, bad = _validate(batch.pack(probs))
+        assert rc == _lib.DMPC_OK and bad == -1
+
+
+def test_validate_empty_batch():
+    pk = batch.pack([])
+    rc, _ = _validate(pk)
+    assert rc == _lib.DMPC_OK
+
+
+@pytest.mark.parametrize("field,value", [
+    ("T", 0), ("nx", 0), ("nx", 17), ("nu", 0), ("dyn", 7), ("cost", 5), ("reserved", 1),
+    ("dyn_off", -1), ("x0_off", 10 ** 9), ("sol_off", 10 ** 9), ("cost_phases", 2),
+])
+def test_validate_rejects_bad_descriptor(field, value):
+    pk = batch.pack(W.lq_batch(0, batch=3))
+    pk.descs[1][field] = value
+    rc, bad = _validate(pk)
+    assert rc == _lib.DMPC_ERR_INVALID_ARG
+    assert bad == 1
+
+
+def test_validate_model_shapes():
+    pk = batch.pack(W.cartpole_batch(0, batch=2))
+    pk.descs[0]["dyn"] = _lib.DYN_BICYCLE          # bicycle needs nx=8, nu=2
+    rc, bad = _validate(pk)
+    assert rc == _lib.DMPC_ERR_INVALID_ARG and bad == 0
+
+
+def test_validate_unsupported_state_size():
+    rng = np.random.default_rng(0)
+    pk = batch.pack([W.ltv_problem(rng, 5, 5, 2)])  # nx=5 has no kernel
+    rc, bad = _validate(pk)
+    assert rc == _lib.DMPC_ERR_UNSUPPORTED and bad == 0
+
+
+def test_validate_overlapping_solution_blocks():
+    pk = batch.pack(W.lq_batch(0, batch=3))
+    pk.descs[2]["sol_off"] = pk.descs[1]["sol_off"] + 1
+    rc, bad = _validate(pk)
+    assert rc == _lib.DMPC_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("kw", [
+    dict(sqp_iters=0), dict(alphas=()), dict(alphas=(1.0, 1.0)), dict(alphas=(0.5, 0.7)),
+    dict(alphas=(1.5,)), dict(ls_eta=1.0), dict(pcg_tol=-1.0), dict(init=3),
+    dict(block_threads=100), dict(pcg_max_iter=-2),
+])
+def test_validate_rejects_bad_options(kw):
+    pk = batch.pack(W.lq_batch(0, batch=2))
+    if kw.get("alphas") == ():
+        o = _lib.make_opts()
+        o.n_alphas = 0
+    else:
+        o = _lib.make_opts(**kw)
+    rc, _ = _validate(pk, o)
+    assert rc == _lib.DMPC_ERR_INVALID_ARG
+
+
+def test_workspace_size_is_additive():
+    lib = _lib.load()
+    o = _lib.make_opts()
+    sizes = []
+    pks = [batch.pack(W.lq_batch(0, batch=2)), batch.pack(W.cartpole_batch(0, batch=3))]
+    for pk in pks:
+        n = ctypes.c_size_t()
+        d = np.ascontiguousarray(pk.descs)
+        assert lib.dmpc_workspace_size(d.ctypes.data_as(ctypes.c_void_p), len(d), ctypes.byref(o),
+                                       ctypes.byref(n)) == 0
+        assert n.value > 0 and n.value % 256 == 0
+        sizes.append(n.value)
+    both = np.concatenate([pks[0].descs, pks[1].descs])
+    n = ctypes.c_size_t()
+    assert lib.dmpc_workspace_size(both.ctypes.data_as(ctypes.c_void_p), len(both), ctypes.byref(o),
+                                   ctypes.byref(n)) == 0
+    assert n.value == sum(sizes)
+
+
+def test_default_options_follow_the_paper():
+    o = _lib.make_opts()
+    assert [round(o.alphas[i], 6) for i in range(o.n_alphas)] == [1.0, 0.7, 0.3, 0.1, 0.01]
+    assert abs(o.ls_eta - 0.4) < 1e-7
+
+
+def test_pack_roundtrip():
+    probs = W.ltv_uneven_batch(3, batch=5)
+    pk = batch.pack(probs)
+    for k, p in enumerate(probs):
+        x, u, lam = batch.split_sol(pk, pk.sol0, k)
+        assert np.array_equal(x, p["xbar"].astype(np.float32))
+        g = batch.split_grad(pk, pk.data, k)
+        assert np.array_equal(g["A"], p["A"].astype(np.float32))
+        assert np.array_equal(g["Rd"], p["Rd"].astype(np.float32))
+        assert np.array_equal(g["x0"], p["x0"].astype(np.float32))
