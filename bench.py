@@ -147,7 +147,9 @@ def main():
     status = s.status.cpu().numpy()
     info = s.info.cpu().numpy()
     bad = int(np.count_nonzero(status & (_lib.PROB_NONPD | _lib.PROB_NONFINITE)))
-    capped = int(np.count_nonzero(status & (_lib.PROB_PCG_MAXITER | _lib.PROB_BWD_PCG_MAXITER)))
+    capped_f = int(np.count_nonzero(status & _lib.PROB_PCG_MAXITER))
+    capped_b = int(np.count_nonzero(status & _lib.PROB_BWD_PCG_MAXITER))
+    ls_fb = int(np.count_nonzero(status & _lib.PROB_LS_FALLBACK))
 
     # roofline of the dominant kernel (the fused forward SQP kernel)
     N = T + 1
@@ -189,7 +191,8 @@ def main():
                       "speedup_batched": value / plain_value},
         "solver": {"fwd_pcg_iters_mean": float(info[:, 0].mean()),
                    "bwd_pcg_iters_mean": float(info[:, 1].mean()),
-                   "nonpd_or_nonfinite": bad, "pcg_capped": capped},
+                   "nonpd_or_nonfinite": bad, "fwd_pcg_capped": capped_f,
+                   "bwd_pcg_capped": capped_b, "ls_fallback_last_iter": ls_fb},
     }
     print(json.dumps(out), flush=True)
 

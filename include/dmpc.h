@@ -113,11 +113,19 @@ typedef struct dmpc_opts {
   int32_t bwd_pcg_max_iter; /* backward PCG cap; 0 = N*nx + 10 */
   float bwd_pcg_tol;        /* backward relative tolerance (as pcg_tol) */
   int32_t block_threads;    /* threads per workgroup; 0 = chosen by the library */
-  int32_t reserved[3];      /* must be 0 */
+  int32_t refine_steps;     /* refinement passes after each PCG solve, 0..8.  Every pass
+                               re-assembles the Schur residual in double and solves the
+                               correction with the float PCG; the first residual is that of
+                               the warm start */
+  float refine_tol;         /* relative tolerance of each refinement correction, relative
+                               to the residual it corrects (0 = the pass's tol; default 1e-2) */
+  float kkt_tol;            /* refinement stops once ||residual||_2 <= kkt_tol * ||KKT
+                               right-hand side||_2 or the float32 floor (default 1e-6) */
 } dmpc_opts;
 
-/* Fills *o with the defaults: 1 SQP iteration, PCG tol 1e-6, candidates
- * {1, 0.7, 0.3, 0.1, 0.01} (App. A.3), eta = 0.4, INIT_GIVEN. Host only. */
+/* Fills *o with the defaults: 1 SQP iteration, PCG tol 1e-6, one refinement
+ * pass (tol 1e-2, KKT target 1e-6), candidates {1, 0.7, 0.3, 0.1, 0.01}
+ * (App. A.3), eta = 0.4, INIT_GIVEN. Host only. */
 void dmpc_default_opts(dmpc_opts* o);
 
 typedef struct dmpc_handle dmpc_handle;

@@ -59,7 +59,8 @@ class Opts(ctypes.Structure):
         ("ls_eta", ctypes.c_float), ("init", ctypes.c_int32),
         ("bwd_warm_start", ctypes.c_int32), ("bwd_pcg_max_iter", ctypes.c_int32),
         ("bwd_pcg_tol", ctypes.c_float), ("block_threads", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("refine_steps", ctypes.c_int32), ("refine_tol", ctypes.c_float),
+        ("kkt_tol", ctypes.c_float),
     ]
 
 
@@ -113,7 +114,8 @@ def check(rc, what=""):
 
 def make_opts(sqp_iters=1, pcg_tol=1e-6, pcg_abs_tol=0.0, pcg_max_iter=0,
               alphas=(1.0, 0.7, 0.3, 0.1, 0.01), ls_eta=0.4, init="given",
-              bwd_warm_start=False, bwd_pcg_tol=None, bwd_pcg_max_iter=0, block_threads=0):
+              bwd_warm_start=False, bwd_pcg_tol=None, bwd_pcg_max_iter=0, block_threads=0,
+              refine_steps=1, refine_tol=1e-2, kkt_tol=1e-6):
     o = Opts()
     load().dmpc_default_opts(ctypes.byref(o))
     o.sqp_iters = int(sqp_iters)
@@ -129,4 +131,7 @@ def make_opts(sqp_iters=1, pcg_tol=1e-6, pcg_abs_tol=0.0, pcg_max_iter=0,
     o.bwd_pcg_tol = float(pcg_tol if bwd_pcg_tol is None else bwd_pcg_tol)
     o.bwd_pcg_max_iter = int(bwd_pcg_max_iter)
     o.block_threads = int(block_threads)
+    o.refine_steps = int(refine_steps)
+    o.refine_tol = float(refine_tol)
+    o.kkt_tol = float(kkt_tol)
     return o

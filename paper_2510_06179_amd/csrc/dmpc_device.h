@@ -217,14 +217,29 @@ __device__ __forceinline__ void bicycle_step(const float* p, const S* x, const S
 // ===========================================================================
 // Reductions (fixed order: every thread obtains the same bits)
 // ===========================================================================
+// Wave sum with DPP: xor-1 and xor-2 quad permutations, half-row and row
+// mirrors (each lane pairs with a distinct partner, so every lane of a row of
+// 16 holds the same bits), then the four row sums in a fixed order.
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
 __device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp<0xB1>(v);    // quad_perm [1,0,3,2]
+  v += dpp<0x4E>(v);    // quad_perm [2,3,0,1]
+  v += dpp<0x141>(v);   // row_half_mirror
+  v += dpp<0x140>(v);   // row_mirror
+  const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+  const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+  const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+  const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+  return (r0 + r1) + (r2 + r3);
 }
 
+// Block sum: wave sums, then (several waves) one LDS exchange read in order.
 __device__ __forceinline__ float block_sum(float v, float* red, int nwv) {
   v = wave_sum(v);
+  if (nwv == 1) return v;
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
   float s = 0.f;
@@ -512,69 +527,103 @@ __device__ __forceinline__ void form_qp(const Prob& P, const float* xbar, const 
 }
 
 // ===========================================================================
-// Schur rows (Eq. shurcomplement, Eq. S_Phiinv; user signs)
+// Schur rows (Eq. shurcomplement, Eq. S_Phiinv; user signs), float or double
 //   D_0 = Q_0^-1,  D_{t+1} = A_t Q_t^-1 A_t' + B_t R_t^-1 B_t' + Q_{t+1}^-1
 //   E_{t+1,t} = -A_t Q_t^-1,  E_{t,t+1} = E_{t+1,t}'
 //   g = -gamma:  g_0 = -(x_s + Q_0^-1 q_0),
 //   g_{t+1} = -(c_t - A_t Q_t^-1 q_t - B_t R_t^-1 r_t + Q_{t+1}^-1 q_{t+1})
 // S[0:NX] = E_{t,t-1}[i,:], S[NX:2NX] = D_t[i,:], S[2NX:3NX] = E_{t,t+1}[i,:]
+// The double version recomputes every inverse from the stored Hessian
+// diagonal; the float version uses the stored reciprocals.
 // ===========================================================================
-template <int NX>
-__device__ __forceinline__ void schur_row(const Prob& P, int t, int i, float* S, float& g) {
+template <typename R>
+__device__ __forceinline__ R rinv(const float* h, const float* ih, int idx) {
+  if constexpr (sizeof(R) == sizeof(float)) {
+    return ih[idx];
+  } else {
+    return 1.0 / (double)h[idx];
+  }
+}
+
+template <int NX, typename R>
+__device__ __forceinline__ void schur_row(const Prob& P, int t, int i, R* S, R& g) {
   const float* W = P.W;
+  const float* Qd = W + P.L.Qd;
   const float* iQ = W + P.L.iQ;
   const float* q = W + P.L.q;
+  const float* Rd = W + P.L.Rd;
   const float* iR = W + P.L.iR;
   const float* r = W + P.L.r;
   const int m = P.m;
 #pragma unroll
-  for (int j = 0; j < 3 * NX; ++j) S[j] = 0.f;
+  for (int j = 0; j < 3 * NX; ++j) S[j] = R(0);
   if (t == 0) {
-    const float d = iQ[i];
+    const R d = rinv<R>(Qd, iQ, i);
 #pragma unroll
-    for (int j = 0; j < NX; ++j) S[NX + j] = (j == i) ? d : 0.f;
-    g = -fmaf(q[i], d, P.x0[i]);
+    for (int j = 0; j < NX; ++j) S[NX + j] = (j == i) ? d : R(0);
+    g = -((R)P.x0[i] + (R)q[i] * d);
   } else {
     const int tt = t - 1;
     const float* At = P.A + tt * NX * NX;
     const float* Bt = P.B + tt * NX * m;
-    const float* iQt = iQ + tt * NX;
-    const float* qt = q + tt * NX;
-    float ai[NX];
-    float gs = 0.f;
+    R ai[NX];
+    R gs = R(0);
 #pragma unroll
     for (int j = 0; j < NX; ++j) {
-      ai[j] = At[i * NX + j] * iQt[j];
-      gs = fmaf(ai[j], qt[j], gs);
+      ai[j] = (R)At[i * NX + j] * rinv<R>(Qd, iQ, tt * NX + j);
+      gs += ai[j] * (R)q[tt * NX + j];
       S[j] = -ai[j];
     }
 #pragma unroll
     for (int k = 0; k < NX; ++k) {
-      float acc = 0.f;
+      R acc = R(0);
 #pragma unroll
-      for (int j = 0; j < NX; ++j) acc = fmaf(ai[j], At[k * NX + j], acc);
+      for (int j = 0; j < NX; ++j) acc += ai[j] * (R)At[k * NX + j];
       S[NX + k] = acc;
     }
     for (int l = 0; l < m; ++l) {
-      const float bi = Bt[i * m + l] * iR[tt * m + l];
-      gs = fmaf(bi, r[tt * m + l], gs);
+      const R bi = (R)Bt[i * m + l] * rinv<R>(Rd, iR, tt * m + l);
+      gs += bi * (R)r[tt * m + l];
 #pragma unroll
-      for (int k = 0; k < NX; ++k) S[NX + k] = fmaf(bi, Bt[k * m + l], S[NX + k]);
+      for (int k = 0; k < NX; ++k) S[NX + k] += bi * (R)Bt[k * m + l];
     }
-    const float dq = iQ[t * NX + i];
+    const R dq = rinv<R>(Qd, iQ, t * NX + i);
 #pragma unroll
-    for (int k = 0; k < NX; ++k) S[NX + k] += (k == i) ? dq : 0.f;
-    g = -(P.c[tt * NX + i] - gs + q[t * NX + i] * dq);
+    for (int k = 0; k < NX; ++k) S[NX + k] += (k == i) ? dq : R(0);
+    g = -((R)P.c[tt * NX + i] - gs + (R)q[t * NX + i] * dq);
   }
   if (t < P.T) {
     const float* At = P.A + t * NX * NX;
-    const float d = iQ[t * NX + i];
+    const R d = rinv<R>(Qd, iQ, t * NX + i);
 #pragma unroll
-    for (int k = 0; k < NX; ++k) S[2 * NX + k] = -At[k * NX + i] * d;
+    for (int k = 0; k < NX; ++k) S[2 * NX + k] = -(R)At[k * NX + i] * d;
   }
 }
 
-// Row product with a padded LDS window: sum_j coef[j] * win[t*NX + j].
+// Right-hand side of the adjoint Schur system (Alg. backward line 1 with
+// (-b, d) <- (dl/dz, dl/dlambda)):  g~ = H G^-1 dl/dz - dl/dlambda, row (t, i).
+template <int NX, typename R>
+__device__ __forceinline__ R adjoint_rhs_row(const Prob& P, int t, int i, const float* dlx,
+                                             const float* dlu, const float* dll) {
+  const float* Qd = P.W + P.L.Qd;
+  const float* iQ = P.W + P.L.iQ;
+  const float* Rd = P.W + P.L.Rd;
+  const float* iR = P.W + P.L.iR;
+  const int m = P.m;
+  const int rho = t * NX + i;
+  R v = (R)dlx[rho] * rinv<R>(Qd, iQ, rho) - (R)dll[rho];
+  if (t >= 1) {
+    const int tt = t - 1;
+    const float* At = P.A + tt * NX * NX + i * NX;
+    const float* Bt = P.B + tt * NX * m + i * m;
+#pragma unroll
+    for (int j = 0; j < NX; ++j) v -= (R)At[j] * ((R)dlx[tt * NX + j] * rinv<R>(Qd, iQ, tt * NX + j));
+    for (int l = 0; l < m; ++l) v -= (R)Bt[l] * ((R)dlu[tt * m + l] * rinv<R>(Rd, iR, tt * m + l));
+  }
+  return v;
+}
+
+// Row product with a padded LDS window: sum_j coef[j] * win[j], win = w + t*NX.
 template <int NX>
 __device__ __forceinline__ float row_dot(const float* coef, const float* win) {
   float a0 = 0.f, a1 = 0.f, a2 = 0.f;
@@ -586,47 +635,107 @@ __device__ __forceinline__ float row_dot(const float* coef, const float* win) {
   }
   return (a0 + a1) + a2;
 }
+// Same with the window value taken as the double-float hi + lo.
+template <int NX>
+__device__ __forceinline__ double row_dot64(const double* coef, const float* hi, const float* lo) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll
+  for (int j = 0; j < NX; ++j) {
+    a0 = fma(coef[j], (double)hi[j] + (double)lo[j], a0);
+    a1 = fma(coef[NX + j], (double)hi[NX + j] + (double)lo[NX + j], a1);
+    a2 = fma(coef[2 * NX + j], (double)hi[2 * NX + j] + (double)lo[2 * NX + j], a2);
+  }
+  return (a0 + a1) + a2;
+}
 
-// Shared state of the workgroup for one problem.
+// ===========================================================================
+// Shared-memory layout of a workgroup (float offsets)
+// ===========================================================================
+struct Carve {
+  int xbar, ubar, xp, up, lam, w0, w1, w2, piv, red, ls;
+};
+__device__ __forceinline__ Carve carve(int R, int TM, int N, int nx, int bt) {
+  Carve C;
+  int o = 0;
+  C.xbar = o;  o += R;       // forward: iterate;     backward: x~
+  C.ubar = o;  o += TM;      //                                   u~
+  C.xp = o;    o += R;       // QP solution
+  C.up = o;    o += TM;
+  C.lam = o;   o += R;       // backward: forward multipliers
+  C.w0 = o;    o += R + 2 * nx;
+  C.w1 = o;    o += R + 2 * nx;
+  C.w2 = o;    o += R + 2 * nx;  // low part of a double-float vector in w0
+  C.piv = o;   o += 4 * bt;
+  C.red = o;   o += 128;
+  C.ls = o;    o += 2 * (kMaxAlphas + 1) * N + 2 * (kMaxAlphas + 1) + 2;
+  return C;
+}
+
 struct Lds {
   float* w0;   // padded windows: w[NX + rho] = v[rho], zero pads of NX at both ends
   float* w1;
-  float* piv;  // Gauss-Jordan pivot rows, double buffered [2][N][2*NX]
-  float* red;  // 2 x 64 floats
+  float* w2;   // low part of the vector in w0 (double-float multipliers)
+  float* piv;  // Gauss-Jordan pivot rows, double buffered
+  float* red;  // 2 x 64 floats for block reductions
   float* ls;   // line-search stage results and per-candidate sums
 };
 
-// Symmetric stair preconditioner rows (Eq. S_Phiinv): Gauss-Jordan inversion
-// of every D_t by the NX threads of block t, then the off-diagonal blocks
-// -D_t^-1 E_{t,t-1} D_{t-1}^-1 and -D_t^-1 E_{t,t+1} D_{t+1}^-1.
-template <int NX, int SLOTS, bool REG>
-__device__ __forceinline__ void precond_rows(const Prob& P, const Lds& sh,
-                                             float (&S)[SLOTS][3 * NX],
-                                             float (&Ph)[SLOTS][3 * NX], bool& nonpd) {
+template <int NX>
+__device__ __forceinline__ Lds lds_of(float* smem, const Prob& P) {
+  const Carve C = carve(P.R, P.TM, P.N, NX, blockDim.x);
+  Lds sh;
+  sh.w0 = smem + C.w0;
+  sh.w1 = smem + C.w1;
+  sh.w2 = smem + C.w2;
+  sh.piv = smem + C.piv;
+  sh.red = smem + C.red;
+  sh.ls = smem + C.ls;
+  return sh;
+}
+
+template <int SLOTS>
+__device__ __forceinline__ void publish(float* w, const float (&v)[SLOTS], int R, int nx) {
   const int tid = threadIdx.x, BT = blockDim.x;
-  float* Dinv = P.W + P.L.Dinv;
-  const float* iQ = P.W + P.L.iQ;
-  float* blk = P.W + P.L.blk;
-  float ga[SLOTS][NX], gb[SLOTS][NX];
 #pragma unroll
   for (int s = 0; s < SLOTS; ++s) {
     const int rho = tid + s * BT;
-    const int t = rho / NX, i = rho - t * NX;
+    if (rho < R) w[nx + rho] = v[s];
+  }
+}
+
+// ===========================================================================
+// Symmetric stair preconditioner (Eq. S_Phiinv): Gauss-Jordan inversion of
+// every D_t (rows of a block are handled by consecutive threads; the rows are
+// processed in chunks of whole blocks), then the off-diagonal blocks
+// -D_t^-1 E_{t,t-1} D_{t-1}^-1 and -D_t^-1 E_{t,t+1} D_{t+1}^-1.  Reads the
+// diagonal-block rows from blk[rho][NX:2NX] and writes the preconditioner
+// rows to blk[rho][3NX:6NX].  Returns true (in this thread) on a
+// non-positive pivot.
+// ===========================================================================
+template <int NX>
+__device__ __forceinline__ bool precond_rows(const Prob& P, float* piv) {
+  const int tid = threadIdx.x, BT = blockDim.x;
+  const int nb = BT / NX;        // whole blocks per chunk
+  const int BTb = nb * NX;
+  float* blk = P.W + P.L.blk;
+  float* Dinv = P.W + P.L.Dinv;
+  const float* iQ = P.W + P.L.iQ;
+  bool nonpd = false;
+  for (int c0 = 0; c0 < P.R; c0 += BTb) {
+    const int rho = c0 + tid;
+    const bool act = tid < BTb && rho < P.R;
+    const int tl = tid / NX, i = tid - tl * NX;
+    float ga[NX], gb[NX];
 #pragma unroll
     for (int j = 0; j < NX; ++j) {
-      ga[s][j] = REG ? S[s][NX + j] : (rho < P.R ? blk[rho * 6 * NX + NX + j] : 0.f);
-      gb[s][j] = (j == i) ? 1.f : 0.f;
+      ga[j] = act ? blk[rho * 6 * NX + NX + j] : 0.f;
+      gb[j] = (j == i) ? 1.f : 0.f;
     }
-  }
 #pragma unroll
-  for (int kk = 0; kk < NX; ++kk) {
-    float* buf = sh.piv + (kk & 1) * (P.N * 2 * NX);
-#pragma unroll
-    for (int s = 0; s < SLOTS; ++s) {
-      const int rho = tid + s * BT;
-      const int t = rho / NX, i = rho - t * NX;
-      if (rho < P.R && i == kk) {
-        float pv = ga[s][kk];
+    for (int kk = 0; kk < NX; ++kk) {
+      float* buf = piv + (kk & 1) * (nb * 2 * NX) + tl * 2 * NX;
+      if (act && i == kk) {
+        float pv = ga[kk];
         if (!(pv > 0.f)) {
           nonpd = true;
           pv = 1.f;
@@ -634,100 +743,87 @@ __device__ __forceinline__ void precond_rows(const Prob& P, const Lds& sh,
         const float inv = 1.f / pv;
 #pragma unroll
         for (int j = 0; j < NX; ++j) {
-          ga[s][j] *= inv;
-          gb[s][j] *= inv;
-          buf[t * 2 * NX + j] = ga[s][j];
-          buf[t * 2 * NX + NX + j] = gb[s][j];
+          ga[j] *= inv;
+          gb[j] *= inv;
+          buf[j] = ga[j];
+          buf[NX + j] = gb[j];
         }
       }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int s = 0; s < SLOTS; ++s) {
-      const int rho = tid + s * BT;
-      const int t = rho / NX, i = rho - t * NX;
-      if (rho < P.R && i != kk) {
-        const float f = ga[s][kk];
-        const float* pr = buf + t * 2 * NX;
+      __syncthreads();
+      if (act && i != kk) {
+        const float f = ga[kk];
 #pragma unroll
         for (int j = 0; j < NX; ++j) {
-          ga[s][j] = fmaf(-f, pr[j], ga[s][j]);
-          gb[s][j] = fmaf(-f, pr[NX + j], gb[s][j]);
+          ga[j] = fmaf(-f, buf[j], ga[j]);
+          gb[j] = fmaf(-f, buf[NX + j], gb[j]);
         }
       }
     }
-  }
-  // gb = row i of D_t^-1
+    if (act) {
 #pragma unroll
-  for (int s = 0; s < SLOTS; ++s) {
-    const int rho = tid + s * BT;
-    if (rho < P.R) {
-#pragma unroll
-      for (int j = 0; j < NX; ++j) Dinv[rho * NX + j] = gb[s][j];
+      for (int j = 0; j < NX; ++j) Dinv[rho * NX + j] = gb[j];
     }
+    __syncthreads();
   }
-  __syncthreads();
-#pragma unroll
-  for (int s = 0; s < SLOTS; ++s) {
-    const int rho = tid + s * BT;
+  for (int rho = tid; rho < P.R; rho += BT) {
     const int t = rho / NX;
-    float lo[NX], up[NX];
+    const float* Dt = Dinv + rho * NX;   // row i of D_t^-1
+    float lo[NX], up[NX], dr[NX];
 #pragma unroll
     for (int j = 0; j < NX; ++j) {
       lo[j] = 0.f;
       up[j] = 0.f;
+      dr[j] = Dt[j];
     }
-    if (rho < P.R) {
-      if (t >= 1) {
-        const float* Ap = P.A + (t - 1) * NX * NX;
-        const float* iQp = iQ + (t - 1) * NX;
-        const float* Dp = Dinv + (t - 1) * NX * NX;
+    if (t >= 1) {
+      const float* Ap = P.A + (t - 1) * NX * NX;
+      const float* iQp = iQ + (t - 1) * NX;
+      const float* Dp = Dinv + (t - 1) * NX * NX;
 #pragma unroll
-        for (int k = 0; k < NX; ++k) {
-          float w = 0.f;
+      for (int k = 0; k < NX; ++k) {
+        float w = 0.f;
 #pragma unroll
-          for (int j = 0; j < NX; ++j) w = fmaf(gb[s][j], Ap[j * NX + k], w);
-          w *= iQp[k];   // (D_t^-1 E_{t,t-1})[i][k] = -w
+        for (int j = 0; j < NX; ++j) w = fmaf(dr[j], Ap[j * NX + k], w);
+        w *= iQp[k];   // (D_t^-1 E_{t,t-1})[i][k] = -w
 #pragma unroll
-          for (int j = 0; j < NX; ++j) lo[j] = fmaf(w, Dp[k * NX + j], lo[j]);
-        }
-      }
-      if (t < P.T) {
-        const float* At = P.A + t * NX * NX;
-        const float* iQt = iQ + t * NX;
-        const float* Dn = Dinv + (t + 1) * NX * NX;
-        float bq[NX];
-#pragma unroll
-        for (int j = 0; j < NX; ++j) bq[j] = gb[s][j] * iQt[j];
-#pragma unroll
-        for (int k = 0; k < NX; ++k) {
-          float w = 0.f;
-#pragma unroll
-          for (int j = 0; j < NX; ++j) w = fmaf(bq[j], At[k * NX + j], w);
-          // (D_t^-1 E_{t,t+1})[i][k] = -w
-#pragma unroll
-          for (int j = 0; j < NX; ++j) up[j] = fmaf(w, Dn[k * NX + j], up[j]);
-        }
+        for (int j = 0; j < NX; ++j) lo[j] = fmaf(w, Dp[k * NX + j], lo[j]);
       }
     }
-    // Phi^-1 row: [-D^-1 E_lo D^-1 | D_t^-1 | -D^-1 E_up D^-1] = [lo | gb | up]
+    if (t < P.T) {
+      const float* At = P.A + t * NX * NX;
+      const float* iQt = iQ + t * NX;
+      const float* Dn = Dinv + (t + 1) * NX * NX;
+      float bq[NX];
+#pragma unroll
+      for (int j = 0; j < NX; ++j) bq[j] = dr[j] * iQt[j];
+#pragma unroll
+      for (int k = 0; k < NX; ++k) {
+        float w = 0.f;
+#pragma unroll
+        for (int j = 0; j < NX; ++j) w = fmaf(bq[j], At[k * NX + j], w);
+        // (D_t^-1 E_{t,t+1})[i][k] = -w
+#pragma unroll
+        for (int j = 0; j < NX; ++j) up[j] = fmaf(w, Dn[k * NX + j], up[j]);
+      }
+    }
+    float* b = blk + rho * 6 * NX + 3 * NX;
 #pragma unroll
     for (int j = 0; j < NX; ++j) {
-      if (REG) {
-        Ph[s][j] = lo[j];
-        Ph[s][NX + j] = gb[s][j];
-        Ph[s][2 * NX + j] = up[j];
-      } else if (rho < P.R) {
-        float* b = blk + rho * 6 * NX + 3 * NX;
-        b[j] = lo[j];
-        b[NX + j] = gb[s][j];
-        b[2 * NX + j] = up[j];
-      }
+      b[j] = lo[j];
+      b[NX + j] = dr[j];
+      b[2 * NX + j] = up[j];
     }
   }
+  return nonpd;
 }
 
-// Row coefficients: registers or the workspace copy.
+// ===========================================================================
+// PCG (Alg. pcg) on S^ d = rhs from d = 0, preconditioner Phi^-1; rows live
+// in registers (REG) or in the workspace.  Stops when eta = r'Phi^-1 r <=
+// max(rel_tol^2 * rhs'Phi^-1 rhs, abs_thresh), or at the iteration cap.
+// (The warm start of Alg. pcg enters through rhs = g - S^ lambda, which the
+// caller computes in double.)  Returns the iteration count; ORs status bits.
+// ===========================================================================
 template <int NX, int SLOTS, bool REG>
 __device__ __forceinline__ const float* coefS(const Prob& P, float (&S)[SLOTS][3 * NX], int s,
                                               int rho) {
@@ -741,54 +837,43 @@ __device__ __forceinline__ const float* coefP(const Prob& P, float (&Ph)[SLOTS][
   return P.W + P.L.blk + rho * 6 * NX + 3 * NX;
 }
 
-template <int SLOTS>
-__device__ __forceinline__ void publish(float* w, const float (&v)[SLOTS], int R, int nx) {
-  const int tid = threadIdx.x, BT = blockDim.x;
-#pragma unroll
-  for (int s = 0; s < SLOTS; ++s) {
-    const int rho = tid + s * BT;
-    if (rho < R) w[nx + rho] = v[s];
-  }
-}
-
-// Alg. pcg on S^ lambda = g with preconditioner Phi^-1.  Stopping rule:
-// eta = r'Phi^-1 r <= max(tol^2 * g'Phi^-1 g, abs_tol), or the cap.
-// Returns the iteration count; sets flag bits.
+// v' Phi^-1 v for a vector held in this thread's rows.
 template <int NX, int SLOTS, bool REG>
-__device__ __forceinline__ int pcg(const Prob& P, const Lds& sh, float (&S)[SLOTS][3 * NX],
-                   float (&Ph)[SLOTS][3 * NX], const float (&g)[SLOTS], float (&lam)[SLOTS],
-                   int maxit, float tol, float abs_tol, int& flags, int& redi, int maxit_flag) {
+__device__ __forceinline__ float precond_norm(const Prob& P, const Lds& sh,
+                                              float (&Ph)[SLOTS][3 * NX], const float (&v)[SLOTS],
+                                              int& redi) {
   const int tid = threadIdx.x, BT = blockDim.x, nwv = (BT + 63) >> 6;
-  const int R = P.R;
-  float r[SLOTS], p[SLOTS], z[SLOTS], y[SLOTS];
-  // ||g||^2_{Phi^-1} for the relative tolerance
-  publish<SLOTS>(sh.w0, g, R, NX);
+  publish<SLOTS>(sh.w0, v, P.R, NX);
   __syncthreads();
   float part = 0.f;
 #pragma unroll
   for (int s = 0; s < SLOTS; ++s) {
     const int rho = tid + s * BT;
-    if (rho < R) {
+    if (rho < P.R) {
       const int t = rho / NX;
-      part = fmaf(g[s], row_dot<NX>(coefP<NX, SLOTS, REG>(P, Ph, s, rho), sh.w0 + t * NX), part);
+      part = fmaf(v[s], row_dot<NX>(coefP<NX, SLOTS, REG>(P, Ph, s, rho), sh.w0 + t * NX), part);
     }
   }
-  const float etab = block_sum(part, sh.red + 64 * (redi++ & 1), nwv);
-  // r = g - S^ lambda (line 1), r~ = Phi^-1 r (line 2), p = r~, eta = r'r~
-  publish<SLOTS>(sh.w0, lam, R, NX);
-  __syncthreads();
+  return block_sum(part, sh.red + 64 * (redi++ & 1), nwv);
+}
+
+template <int NX, int SLOTS, bool REG>
+__device__ __forceinline__ int pcg(const Prob& P, const Lds& sh, float (&S)[SLOTS][3 * NX],
+                                   float (&Ph)[SLOTS][3 * NX], const float (&rhs)[SLOTS],
+                                   float (&d)[SLOTS], int maxit, float rel_tol, float abs_thresh,
+                                   int& flags, int& redi, int maxit_flag) {
+  const int tid = threadIdx.x, BT = blockDim.x, nwv = (BT + 63) >> 6;
+  const int R = P.R;
+  float r[SLOTS], p[SLOTS], z[SLOTS], y[SLOTS];
+  // r = rhs (line 1 with d = 0), r~ = Phi^-1 r (2), p = r~ (3), eta = r'r~ (4)
 #pragma unroll
   for (int s = 0; s < SLOTS; ++s) {
-    const int rho = tid + s * BT;
-    r[s] = 0.f;
-    if (rho < R) {
-      const int t = rho / NX;
-      r[s] = g[s] - row_dot<NX>(coefS<NX, SLOTS, REG>(P, S, s, rho), sh.w0 + t * NX);
-    }
+    r[s] = rhs[s];
+    d[s] = 0.f;
   }
   publish<SLOTS>(sh.w1, r, R, NX);
   __syncthreads();
-  part = 0.f;
+  float part = 0.f;
 #pragma unroll
   for (int s = 0; s < SLOTS; ++s) {
     const int rho = tid + s * BT;
@@ -801,14 +886,14 @@ __device__ __forceinline__ int pcg(const Prob& P, const Lds& sh, float (&S)[SLOT
     part = fmaf(r[s], z[s], part);
   }
   float eta = block_sum(part, sh.red + 64 * (redi++ & 1), nwv);
-  const float thresh = fmaxf(tol * tol * etab, abs_tol);
+  const float thresh = fmaxf(rel_tol * rel_tol * eta, abs_thresh);
   int it = 0;
   if (!isfinite(eta)) {
     flags |= DMPC_PROB_NONFINITE;
     return 0;
   }
   while (it < maxit && eta > thresh) {
-    // y = S^ p (line 6), v = p'y (7), alpha (8)
+    // y = S^ p (line 6), v = p'y (7), alpha = eta / v (8)
     publish<SLOTS>(sh.w0, p, R, NX);
     __syncthreads();
     part = 0.f;
@@ -828,10 +913,10 @@ __device__ __forceinline__ int pcg(const Prob& P, const Lds& sh, float (&S)[SLOT
       break;
     }
     const float alpha = eta / v;
-    // lambda += alpha p (9), r -= alpha y (10)
+    // d += alpha p (9), r -= alpha y (10)
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
-      lam[s] = fmaf(alpha, p[s], lam[s]);
+      d[s] = fmaf(alpha, p[s], d[s]);
       r[s] = fmaf(-alpha, y[s], r[s]);
     }
     // r~ = Phi^-1 r (11), eta' = r'r~ (12)
@@ -865,408 +950,473 @@ __device__ __forceinline__ int pcg(const Prob& P, const Lds& sh, float (&S)[SLOT
 }
 
 // ===========================================================================
-// Forward kernel: Alg. sqp for each problem of the launch
+// Forward phases (not inlined: each keeps its registers to itself)
 // ===========================================================================
-template <int NX, int SLOTS, bool REG>
-__device__ __forceinline__ void forward_problem(const KArgs& a, const ProbRec& pr, float* smem) {
-  const int tid = threadIdx.x, BT = blockDim.x, nwv = (BT + 63) >> 6;
-  const Prob P = make_prob<NX>(pr, a.data, a.ws);
-  const int T = P.T, N = P.N, m = P.m, R = P.R, TM = P.TM;
-  // LDS carve-up
-  float* xbar = smem;
-  float* ubar = xbar + R;
-  float* xp = ubar + TM;
-  float* up = xp + R;
-  Lds sh;
-  sh.w0 = up + TM;
-  sh.w1 = sh.w0 + R + 2 * NX;
-  sh.piv = sh.w1 + R + 2 * NX;
-  sh.red = sh.piv + 4 * N * NX;
-  sh.ls = sh.red + 128;
-  float* solx = a.sol + pr.sol_off;
-  float* solu = solx + R;
-  float* soll = solu + TM;
+struct LsParams {
+  float alphas[kMaxAlphas];
+  int n;
+  float eta;
+};
 
-  // ---- initial guess (Alg. sqp inputs); x_0 = x_s
+// Initial guess (Alg. sqp inputs) into LDS; x_0 = x_s; rollout if asked.
+template <int NX>
+__device__ __noinline__ void fwd_begin(const ProbRec* rec, const float* data, const float* sol,
+                                       float* ws, int init) {
+  extern __shared__ float smem[];
+  const int tid = threadIdx.x, BT = blockDim.x;
+  const Prob P = make_prob<NX>(*rec, data, ws);
+  const Carve C = carve(P.R, P.TM, P.N, NX, BT);
+  float* xbar = smem + C.xbar;
+  float* ubar = smem + C.ubar;
+  const int T = P.T, m = P.m, R = P.R, TM = P.TM;
+  const float* solx = sol + rec->sol_off;
+  const float* solu = solx + R;
   for (int i = tid; i < R; i += BT) xbar[i] = (i < NX) ? P.x0[i] : solx[i];
   for (int i = tid; i < TM; i += BT) ubar[i] = solu[i];
-  float lam[SLOTS];
-#pragma unroll
-  for (int s = 0; s < SLOTS; ++s) {
-    const int rho = tid + s * BT;
-    lam[s] = (rho < R && a.init == DMPC_INIT_GIVEN) ? soll[rho] : 0.f;
-  }
   if (tid < NX) {
-    sh.w0[tid] = 0.f;
-    sh.w0[R + NX + tid] = 0.f;
-    sh.w1[tid] = 0.f;
-    sh.w1[R + NX + tid] = 0.f;
+    smem[C.w0 + tid] = 0.f;
+    smem[C.w0 + R + NX + tid] = 0.f;
+    smem[C.w1 + tid] = 0.f;
+    smem[C.w1 + R + NX + tid] = 0.f;
+    smem[C.w2 + tid] = 0.f;
+    smem[C.w2 + R + NX + tid] = 0.f;
   }
   __syncthreads();
-  if (a.init == DMPC_INIT_ROLLOUT) {
-    if (P.dyn == DMPC_DYN_LTV) {
+  if (init != DMPC_INIT_ROLLOUT) return;
+  if (P.dyn == DMPC_DYN_LTV) {
+    for (int t = 0; t < T; ++t) {
+      if (tid < NX) {
+        const float* At = P.A + t * NX * NX + tid * NX;
+        const float* Bt = P.B + t * NX * m + tid * m;
+        float s = P.c[t * NX + tid];
+#pragma unroll
+        for (int j = 0; j < NX; ++j) s = fmaf(At[j], xbar[t * NX + j], s);
+        for (int l = 0; l < m; ++l) s = fmaf(Bt[l], ubar[t * m + l], s);
+        xbar[(t + 1) * NX + tid] = s;
+      }
+      __syncthreads();
+    }
+  } else {
+    if (tid == 0) {
       for (int t = 0; t < T; ++t) {
-        if (tid < NX) {
-          const float* At = P.A + t * NX * NX + tid * NX;
-          const float* Bt = P.B + t * NX * m + tid * m;
-          float s = P.c[t * NX + tid];
+        float xn[NX];
+        dyn_step<NX>(P, t, xbar + t * NX, ubar + t * m, xn);
 #pragma unroll
-          for (int j = 0; j < NX; ++j) s = fmaf(At[j], xbar[t * NX + j], s);
-          for (int l = 0; l < m; ++l) s = fmaf(Bt[l], ubar[t * m + l], s);
-          xbar[(t + 1) * NX + tid] = s;
-        }
-        __syncthreads();
+        for (int i = 0; i < NX; ++i) xbar[(t + 1) * NX + i] = xn[i];
       }
-    } else {
-      if (tid == 0) {
-        for (int t = 0; t < T; ++t) {
-          float xn[NX];
-          dyn_step<NX>(P, t, xbar + t * NX, ubar + t * m, xn);
-#pragma unroll
-          for (int i = 0; i < NX; ++i) xbar[(t + 1) * NX + i] = xn[i];
-        }
-      }
-      __syncthreads();
     }
+    __syncthreads();
   }
+}
 
-  int flags = 0, pcg_total = 0, last_alpha = 0, redi = 0;
-  float S[SLOTS][3 * NX], Ph[SLOTS][3 * NX], g[SLOTS];
-  bool nonpd = false;
-  const int maxit = a.pcg_max_iter > 0 ? a.pcg_max_iter : R + 10;
+// QP data at the iterate (Eq. QPmatrices), Schur rows and right-hand side
+// (Eq. shurcomplement) and preconditioner rows (Eq. S_Phiinv) into the
+// workspace.  Returns non-zero (in every thread) on a non-positive pivot.
+template <int NX>
+__device__ __noinline__ int fwd_blocks(const ProbRec* rec, const float* data, float* ws) {
+  extern __shared__ float smem[];
+  const int tid = threadIdx.x, BT = blockDim.x;
+  const Prob P = make_prob<NX>(*rec, data, ws);
+  const Carve C = carve(P.R, P.TM, P.N, NX, BT);
+  form_qp<NX>(P, smem + C.xbar, smem + C.ubar);
+  __syncthreads();
   float* blk = P.W + P.L.blk;
+  float* gv = P.W + P.L.g;
+  for (int rho = tid; rho < P.R; rho += BT) {
+    const int t = rho / NX, i = rho - t * NX;
+    float row[3 * NX], g;
+    schur_row<NX, float>(P, t, i, row, g);
+#pragma unroll
+    for (int j = 0; j < 3 * NX; ++j) blk[rho * 6 * NX + j] = row[j];
+    gv[rho] = g;
+  }
+  __syncthreads();
+  const bool bad = precond_rows<NX>(P, smem + C.piv);
+  return __syncthreads_or(bad ? 1 : 0);
+}
 
-  for (int k = 0; k < a.sqp_iters; ++k) {
-    const bool last = (k == a.sqp_iters - 1);
-    // ---- (1) QP data at the iterate (Eq. QPmatrices)
-    form_qp<NX>(P, xbar, ubar);
-    __syncthreads();
-    // ---- (2) Schur rows and right-hand side (Eq. shurcomplement)
+// Squared norms that steer the refinement: of the residual, of its float32
+// floor (unit roundoff times |S^| |lambda| row by row) and of the KKT
+// right-hand side the residual is measured against.
+struct ResNorms {
+  float r2, floor2, rhs2;
+};
+
+__device__ __forceinline__ ResNorms block_sum3(float a, float b, float c, float* red, int nwv) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  c = wave_sum(c);
+  ResNorms n{a, b, c};
+  if (nwv == 1) return n;
+  if ((threadIdx.x & 63) == 0) {
+    const int w = threadIdx.x >> 6;
+    red[3 * w] = a;
+    red[3 * w + 1] = b;
+    red[3 * w + 2] = c;
+  }
+  __syncthreads();
+  n = ResNorms{0.f, 0.f, 0.f};
+  for (int w = 0; w < nwv; ++w) {
+    n.r2 += red[3 * w];
+    n.floor2 += red[3 * w + 1];
+    n.rhs2 += red[3 * w + 2];
+  }
+  return n;
+}
+
+// Residual of the Schur system with every row and the right-hand side
+// re-assembled and accumulated in double: r = g - S^ lambda, lambda = w0 + w2
+// (double-float), result (rounded to float) written to w1[NX + rho].  Returns
+// the norms of r, of its float32 floor and of the KKT right-hand side
+// [-b; d] = [-(q, r); (x_s, c)] (Eq. ocp:KKT), identical in every thread.
+template <int NX>
+__device__ __noinline__ ResNorms fwd_residual64(const ProbRec* rec, const float* data, float* ws) {
+  extern __shared__ float smem[];
+  const int tid = threadIdx.x, BT = blockDim.x;
+  const Prob P = make_prob<NX>(*rec, data, ws);
+  const Carve C = carve(P.R, P.TM, P.N, NX, BT);
+  const float* w0 = smem + C.w0;
+  const float* w2 = smem + C.w2;
+  float* w1 = smem + C.w1;
+  const int nwv = (BT + 63) >> 6;
+  const float* q = P.W + P.L.q;
+  const float* rr = P.W + P.L.r;
+  float r2 = 0.f, f2 = 0.f, b2 = 0.f;
+  for (int rho = tid; rho < P.R; rho += BT) {
+    const int t = rho / NX, i = rho - t * NX;
+    double row[3 * NX], g;
+    schur_row<NX, double>(P, t, i, row, g);
+    const double res = g - row_dot64<NX>(row, w0 + t * NX, w2 + t * NX);
+    w1[NX + rho] = (float)res;
+    double fl = 0.0;
 #pragma unroll
-    for (int s = 0; s < SLOTS; ++s) {
-      const int rho = tid + s * BT;
-      float tmp[3 * NX];
-      g[s] = 0.f;
-      if (rho < R) {
-        const int t = rho / NX, i = rho - t * NX;
-        schur_row<NX>(P, t, i, tmp, g[s]);
-      } else {
+    for (int j = 0; j < 3 * NX; ++j) fl += fabs(row[j] * (double)w0[t * NX + j]);
+    const float dv = (t == 0) ? P.x0[i] : P.c[(t - 1) * NX + i];
+    r2 += (float)(res * res);
+    f2 += (float)(fl * fl);
+    b2 += q[rho] * q[rho] + dv * dv;
+  }
+  for (int idx = tid; idx < P.TM; idx += BT) b2 += rr[idx] * rr[idx];
+  return block_sum3(r2, f2, b2, smem + C.red, nwv);
+}
+
+// QP primal solution (Eq. schur:xu, user signs; accumulated in double):
+//   x_t = -Q_t^-1 (q_t + lambda_t - A_t' lambda_{t+1}),  u_t = -R_t^-1 (r_t - B_t' lambda_{t+1})
+// lambda from the LDS window w0; then the line search (App. A.3, Alg.
+// linesearch) and the SQP update of (x, u).  Returns sel | flags << 8.
+template <int NX>
+__device__ __noinline__ int fwd_recover_ls(const ProbRec* rec, const float* data, float* ws,
+                                           LsParams lp, int last) {
+  extern __shared__ float smem[];
+  const int tid = threadIdx.x, BT = blockDim.x, nwv = (BT + 63) >> 6;
+  const Prob P = make_prob<NX>(*rec, data, ws);
+  const Carve C = carve(P.R, P.TM, P.N, NX, BT);
+  const int T = P.T, N = P.N, m = P.m, R = P.R, TM = P.TM;
+  float* xbar = smem + C.xbar;
+  float* ubar = smem + C.ubar;
+  float* xp = smem + C.xp;
+  float* up = smem + C.up;
+  const float* w0 = smem + C.w0;   // multipliers, high part
+  const float* w2 = smem + C.w2;   // low part
+  {
+    const float* Qd = P.W + P.L.Qd;
+    const float* q = P.W + P.L.q;
+    const float* Rd = P.W + P.L.Rd;
+    const float* rr = P.W + P.L.r;
+    for (int rho = tid; rho < R; rho += BT) {
+      const int t = rho / NX, i = rho - t * NX;
+      double acc = (double)q[rho] + ((double)w0[NX + rho] + (double)w2[NX + rho]);
+      if (t < T) {
+        const float* At = P.A + t * NX * NX;
+        const float* lh = w0 + NX + (t + 1) * NX;
+        const float* ll = w2 + NX + (t + 1) * NX;
 #pragma unroll
-        for (int j = 0; j < 3 * NX; ++j) tmp[j] = 0.f;
+        for (int kk = 0; kk < NX; ++kk) acc -= (double)At[kk * NX + i] * ((double)lh[kk] + (double)ll[kk]);
       }
-      if constexpr (REG) {
-#pragma unroll
-        for (int j = 0; j < 3 * NX; ++j) S[s][j] = tmp[j];
-      } else {
-        if (rho < R) {
-#pragma unroll
-          for (int j = 0; j < 3 * NX; ++j) blk[rho * 6 * NX + j] = tmp[j];
-        }
-      }
+      xp[rho] = (float)(-acc / (double)Qd[rho]);
     }
-    if constexpr (!REG) __syncthreads();
-    // ---- (3) preconditioner rows (Eq. S_Phiinv)
-    precond_rows<NX, SLOTS, REG>(P, sh, S, Ph, nonpd);
-    if (__syncthreads_or(nonpd ? 1 : 0)) flags |= DMPC_PROB_NONPD;
-    // ---- (4) PCG warm-started from the previous multipliers (Alg. pcg)
-    pcg_total += pcg<NX, SLOTS, REG>(P, sh, S, Ph, g, lam, maxit, a.pcg_tol, a.pcg_abs_tol, flags,
-                                     redi, DMPC_PROB_PCG_MAXITER);
-    // ---- (5) QP primal solution (Eq. schur:xu, user signs)
-    //   x_t = -Q_t^-1 (q_t + lambda_t - A_t' lambda_{t+1}),  u_t = -R_t^-1 (r_t - B_t' lambda_{t+1})
-    publish<SLOTS>(sh.w0, lam, R, NX);
-    __syncthreads();
-    {
-      const float* iQ = P.W + P.L.iQ;
-      const float* q = P.W + P.L.q;
-      const float* iR = P.W + P.L.iR;
-      const float* rr = P.W + P.L.r;
-      for (int rho = tid; rho < R; rho += BT) {
-        const int t = rho / NX, i = rho - t * NX;
-        float acc = q[rho] + sh.w0[NX + rho];
-        if (t < T) {
-          const float* At = P.A + t * NX * NX;
-          const float* ln = sh.w0 + NX + (t + 1) * NX;
+    for (int idx = tid; idx < TM; idx += BT) {
+      const int t = idx / m, l = idx - t * m;
+      const float* Bt = P.B + t * NX * m;
+      const float* lh = w0 + NX + (t + 1) * NX;
+      const float* ll = w2 + NX + (t + 1) * NX;
+      double acc = (double)rr[idx];
 #pragma unroll
-          for (int kk = 0; kk < NX; ++kk) acc = fmaf(-At[kk * NX + i], ln[kk], acc);
-        }
-        xp[rho] = -acc * iQ[rho];
-      }
-      for (int idx = tid; idx < TM; idx += BT) {
-        const int t = idx / m, l = idx - t * m;
+      for (int kk = 0; kk < NX; ++kk) acc -= (double)Bt[kk * m + l] * ((double)lh[kk] + (double)ll[kk]);
+      up[idx] = (float)(-acc / (double)Rd[idx]);
+    }
+  }
+  __syncthreads();
+  // Task (ai, t): stage t at the current point (ai = 0) or at candidate
+  // alphas[ai-1]; its cost and dynamics defect go to LDS, one wave then
+  // reduces each candidate in a fixed order.
+  const int na = lp.n;
+  const int ntask = (na + 1) * N;
+  float* tc = smem + C.ls;
+  float* td = tc + (kMaxAlphas + 1) * N;
+  float* res = td + (kMaxAlphas + 1) * N;
+  float dn = 0.f;
+  for (int task = tid; task < ntask; task += BT) {
+    const int ai = task / N, t = task - ai * N;
+    const float al = (ai == 0) ? 0.f : lp.alphas[ai - 1];
+    float xa[NX];
+#pragma unroll
+    for (int j = 0; j < NX; ++j) xa[j] = fmaf(al, xp[t * NX + j] - xbar[t * NX + j], xbar[t * NX + j]);
+    float cst = cost_x<NX>(P, t, xa);
+    float dfc = 0.f;
+    if (t < T) {
+      const float* ub = ubar + t * m;
+      const float* uq = up + t * m;
+      for (int l = 0; l < m; ++l) cst += cost_u1<NX>(P, t, l, fmaf(al, uq[l] - ub[l], ub[l]));
+      float xn[NX];
+      if (P.dyn == DMPC_DYN_LTV) {
+        const float* At = P.A + t * NX * NX;
         const float* Bt = P.B + t * NX * m;
-        const float* ln = sh.w0 + NX + (t + 1) * NX;
-        float acc = rr[idx];
 #pragma unroll
-        for (int kk = 0; kk < NX; ++kk) acc = fmaf(-Bt[kk * m + l], ln[kk], acc);
-        up[idx] = -acc * iR[idx];
+        for (int i = 0; i < NX; ++i) {
+          float sacc = P.c[t * NX + i];
+#pragma unroll
+          for (int j = 0; j < NX; ++j) sacc = fmaf(At[i * NX + j], xa[j], sacc);
+          for (int l = 0; l < m; ++l) sacc = fmaf(Bt[i * m + l], fmaf(al, uq[l] - ub[l], ub[l]), sacc);
+          xn[i] = sacc;
+        }
+      } else {
+        float ua[2];   // nonlinear models have at most two inputs
+        ua[0] = fmaf(al, uq[0] - ub[0], ub[0]);
+        ua[1] = (m > 1) ? fmaf(al, uq[1] - ub[1], ub[1]) : 0.f;
+        dyn_step<NX>(P, t, xa, ua, xn);
+      }
+#pragma unroll
+      for (int j = 0; j < NX; ++j) {
+        const float xa1 =
+            fmaf(al, xp[(t + 1) * NX + j] - xbar[(t + 1) * NX + j], xbar[(t + 1) * NX + j]);
+        dfc += fabsf(xa1 - xn[j]);
       }
     }
-    __syncthreads();
-    // ---- (6) line search (App. A.3, Alg. linesearch).  Task (ai, t): stage t
-    // at the current point (ai = 0) or at candidate alphas[ai-1]; its cost and
-    // dynamics defect go to LDS, one wave then reduces each candidate.
-    {
-      const int na = a.n_alphas;
-      const int ntask = (na + 1) * N;
-      float* tc = sh.ls;               // [(na+1)*N] stage costs
-      float* td = tc + (kMaxAlphas + 1) * N;  // [(na+1)*N] stage defects
-      float dn = 0.f;
-      for (int task = tid; task < ntask; task += BT) {
-        const int ai = task / N, t = task - ai * N;
-        const float al = (ai == 0) ? 0.f : a.alphas[ai - 1];
-        float xa[NX];
-#pragma unroll
-        for (int j = 0; j < NX; ++j)
-          xa[j] = fmaf(al, xp[t * NX + j] - xbar[t * NX + j], xbar[t * NX + j]);
-        float cst = cost_x<NX>(P, t, xa);
-        float dfc = 0.f;
-        if (t < T) {
-          const float* ub = ubar + t * m;
-          const float* uq = up + t * m;
-          for (int l = 0; l < m; ++l) cst += cost_u1<NX>(P, t, l, fmaf(al, uq[l] - ub[l], ub[l]));
-          float xn[NX];
-          if (P.dyn == DMPC_DYN_LTV) {
-            const float* At = P.A + t * NX * NX;
-            const float* Bt = P.B + t * NX * m;
-#pragma unroll
-            for (int i = 0; i < NX; ++i) {
-              float sacc = P.c[t * NX + i];
-#pragma unroll
-              for (int j = 0; j < NX; ++j) sacc = fmaf(At[i * NX + j], xa[j], sacc);
-              for (int l = 0; l < m; ++l)
-                sacc = fmaf(Bt[i * m + l], fmaf(al, uq[l] - ub[l], ub[l]), sacc);
-              xn[i] = sacc;
-            }
-          } else {
-            // nonlinear models have at most two inputs
-            float ua[2];
-            ua[0] = fmaf(al, uq[0] - ub[0], ub[0]);
-            ua[1] = (m > 1) ? fmaf(al, uq[1] - ub[1], ub[1]) : 0.f;
-            dyn_step<NX>(P, t, xa, ua, xn);
-          }
-#pragma unroll
-          for (int j = 0; j < NX; ++j) {
-            const float xa1 =
-                fmaf(al, xp[(t + 1) * NX + j] - xbar[(t + 1) * NX + j], xbar[(t + 1) * NX + j]);
-            dfc += fabsf(xa1 - xn[j]);
-          }
-        }
-        tc[task] = cst;
-        td[task] = dfc;
-        if (ai == 0) {
-          dn += dcost_x<NX>(P, t, xbar + t * NX, xp + t * NX);
-          if (t < T)
-            for (int l = 0; l < m; ++l) dn += dcost_u1<NX>(P, t, l, ubar[t * m + l], up[t * m + l]);
-        }
-      }
-      __syncthreads();
-      {
-        const int lane = tid & 63;
-        float* res = sh.ls + 2 * (kMaxAlphas + 1) * N;   // [2*(kMaxAlphas+1)]
-        for (int ai = tid >> 6; ai <= na; ai += nwv) {
-          float c0 = 0.f, d0 = 0.f;
-          for (int t = lane; t < N; t += 64) {
-            c0 += tc[ai * N + t];
-            d0 += td[ai * N + t];
-          }
-          c0 = wave_sum(c0);
-          d0 = wave_sum(d0);
-          if (lane == 0) {
-            res[ai] = c0;
-            res[kMaxAlphas + 1 + ai] = d0;
-          }
-        }
-      }
-      // the block reduction's barrier also publishes res[]
-      const float num = block_sum(dn, sh.red + 64 * (redi++ & 1), nwv);
-      const float* res = sh.ls + 2 * (kMaxAlphas + 1) * N;
-      const float fl1 = res[kMaxAlphas + 1];
-      const float mu = fmaxf(num, 0.f) / fmaxf(0.5f * fl1, 1e-30f);   // Eq. linesearch:penalty
-      const float Dmu = num - mu * fl1;                                // Eq. linesearch:descent
-      const float phi0 = res[0] + mu * fl1;                            // Eq. linesearch:merit
-      int sel = na - 1;                                                // min of the candidates
-      bool passed = false;
-      for (int ai = 1; ai <= na && !passed; ++ai) {
-        const float al = a.alphas[ai - 1];
-        const float dphi = (res[ai] + mu * res[kMaxAlphas + 1 + ai]) - phi0 - a.ls_eta * al * Dmu;
-        if (dphi < 0.f) {   // Eq. linesearch:decrease
-          sel = ai - 1;
-          passed = true;
-        }
-      }
-      if (last && !passed && na > 1) flags |= DMPC_PROB_LS_FALLBACK;
-      last_alpha = sel;
-      const float al = a.alphas[sel];
-      if (last) {
-        // keep the last linearisation point for the backward pass
-        float* xl = P.W + P.L.xlin;
-        float* ul = P.W + P.L.ulin;
-        for (int i = tid; i < R; i += BT) xl[i] = xbar[i];
-        for (int i = tid; i < TM; i += BT) ul[i] = ubar[i];
-      }
-      __syncthreads();
-      for (int i = tid; i < R; i += BT) xbar[i] = fmaf(al, xp[i] - xbar[i], xbar[i]);
-      for (int i = tid; i < TM; i += BT) ubar[i] = fmaf(al, up[i] - ubar[i], ubar[i]);
-      __syncthreads();
+    tc[task] = cst;
+    td[task] = dfc;
+    if (ai == 0) {
+      dn += dcost_x<NX>(P, t, xbar + t * NX, xp + t * NX);
+      if (t < T)
+        for (int l = 0; l < m; ++l) dn += dcost_u1<NX>(P, t, l, ubar[t * m + l], up[t * m + l]);
     }
   }
+  __syncthreads();
+  {
+    const int lane = tid & 63;
+    for (int ai = tid >> 6; ai <= na; ai += nwv) {
+      float c0 = 0.f, d0 = 0.f;
+      for (int t = lane; t < N; t += 64) {
+        c0 += tc[ai * N + t];
+        d0 += td[ai * N + t];
+      }
+      c0 = wave_sum(c0);
+      d0 = wave_sum(d0);
+      if (lane == 0) {
+        res[ai] = c0;
+        res[kMaxAlphas + 1 + ai] = d0;
+      }
+    }
+  }
+  __syncthreads();
+  const float num = block_sum(dn, smem + C.red, nwv);
+  const float fl1 = res[kMaxAlphas + 1];
+  const float mu = fmaxf(num, 0.f) / fmaxf(0.5f * fl1, 1e-30f);   // Eq. linesearch:penalty
+  const float Dmu = num - mu * fl1;                                // Eq. linesearch:descent
+  const float phi0 = res[0] + mu * fl1;                            // Eq. linesearch:merit
+  int sel = na - 1;                                                // min of the candidates
+  bool passed = false;
+  for (int ai = 1; ai <= na && !passed; ++ai) {
+    const float al = lp.alphas[ai - 1];
+    const float dphi = (res[ai] + mu * res[kMaxAlphas + 1 + ai]) - phi0 - lp.eta * al * Dmu;
+    if (dphi < 0.f) {   // Eq. linesearch:decrease
+      sel = ai - 1;
+      passed = true;
+    }
+  }
+  int flags = 0;
+  if (last && !passed && na > 1) flags |= DMPC_PROB_LS_FALLBACK;
+  const float al = lp.alphas[sel];
+  if (last) {   // the last linearisation point and QP solution, for the backward pass
+    float* xl = P.W + P.L.xlin;
+    float* ul = P.W + P.L.ulin;
+    float* wx = P.W + P.L.xp;
+    float* wu = P.W + P.L.up;
+    for (int i = tid; i < R; i += BT) {
+      xl[i] = xbar[i];
+      wx[i] = xp[i];
+    }
+    for (int i = tid; i < TM; i += BT) {
+      ul[i] = ubar[i];
+      wu[i] = up[i];
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < R; i += BT) xbar[i] = fmaf(al, xp[i] - xbar[i], xbar[i]);
+  for (int i = tid; i < TM; i += BT) ubar[i] = fmaf(al, up[i] - ubar[i], ubar[i]);
+  __syncthreads();
+  return sel | (flags << 8);
+}
 
-  // ---- outputs and what the backward pass reuses
-  for (int i = tid; i < R; i += BT) {
+// Solution output (x, u after the last line search).  Returns NONFINITE bits.
+template <int NX>
+__device__ __noinline__ int fwd_finish(const ProbRec* rec, const float* data, float* sol,
+                                       float* ws) {
+  extern __shared__ float smem[];
+  const int tid = threadIdx.x, BT = blockDim.x;
+  const Prob P = make_prob<NX>(*rec, data, ws);
+  const Carve C = carve(P.R, P.TM, P.N, NX, BT);
+  const float* xbar = smem + C.xbar;
+  const float* ubar = smem + C.ubar;
+  float* solx = sol + rec->sol_off;
+  float* solu = solx + P.R;
+  int bad = 0;
+  for (int i = tid; i < P.R; i += BT) {
     solx[i] = xbar[i];
-    if (!isfinite(xbar[i])) flags |= DMPC_PROB_NONFINITE;
+    if (!isfinite(xbar[i])) bad = 1;
   }
-  for (int i = tid; i < TM; i += BT) {
+  for (int i = tid; i < P.TM; i += BT) {
     solu[i] = ubar[i];
-    if (!isfinite(ubar[i])) flags |= DMPC_PROB_NONFINITE;
+    if (!isfinite(ubar[i])) bad = 1;
   }
-  float* wxp = P.W + P.L.xp;
-  float* wup = P.W + P.L.up;
-  float* wlam = P.W + P.L.lam;
-  for (int i = tid; i < R; i += BT) wxp[i] = xp[i];
-  for (int i = tid; i < TM; i += BT) wup[i] = up[i];
-#pragma unroll
-  for (int s = 0; s < SLOTS; ++s) {
-    const int rho = tid + s * BT;
-    if (rho < R) {
-      soll[rho] = lam[s];
-      wlam[rho] = lam[s];
-      if constexpr (REG) {
-        float* b = blk + rho * 6 * NX;
-#pragma unroll
-        for (int j = 0; j < 3 * NX; ++j) {
-          b[j] = S[s][j];
-          b[3 * NX + j] = Ph[s][j];
-        }
-      }
-    }
+  return __syncthreads_or(bad) ? DMPC_PROB_NONFINITE : 0;
+}
+
+// ===========================================================================
+// Backward phases
+// ===========================================================================
+// Loads the last QP's solution and multipliers and writes the adjoint
+// right-hand side g~ (float) to the workspace vector.
+template <int NX>
+__device__ __noinline__ void bwd_begin(const ProbRec* rec, const float* data, float* ws,
+                                       const float* dl) {
+  extern __shared__ float smem[];
+  const int tid = threadIdx.x, BT = blockDim.x;
+  const Prob P = make_prob<NX>(*rec, data, ws);
+  const Carve C = carve(P.R, P.TM, P.N, NX, BT);
+  const int R = P.R, TM = P.TM;
+  if (tid < NX) {
+    smem[C.w0 + tid] = 0.f;
+    smem[C.w0 + R + NX + tid] = 0.f;
+    smem[C.w1 + tid] = 0.f;
+    smem[C.w1 + R + NX + tid] = 0.f;
+    smem[C.w2 + tid] = 0.f;
+    smem[C.w2 + R + NX + tid] = 0.f;
   }
-  const int anyf = __syncthreads_or(flags);
-  if (tid == 0) {
-    int f = flags;
-    if (anyf & DMPC_PROB_NONFINITE) f |= DMPC_PROB_NONFINITE;
-    a.status[pr.index] = f;
-    a.info[4 * pr.index + 0] = pcg_total;
-    a.info[4 * pr.index + 2] = last_alpha;
-    a.info[4 * pr.index + 3] = a.sqp_iters;
+  for (int i = tid; i < R; i += BT) {
+    smem[C.xp + i] = P.W[P.L.xp + i];
+    smem[C.lam + i] = P.W[P.L.lam + i];
+  }
+  for (int i = tid; i < TM; i += BT) smem[C.up + i] = P.W[P.L.up + i];
+  const float* dlx = dl + rec->sol_off;
+  const float* dlu = dlx + R;
+  const float* dll = dlu + TM;
+  float* gv = P.W + P.L.g;
+  for (int rho = tid; rho < R; rho += BT) {
+    const int t = rho / NX, i = rho - t * NX;
+    gv[rho] = adjoint_rhs_row<NX, float>(P, t, i, dlx, dlu, dll);
   }
   __syncthreads();
 }
 
-// ===========================================================================
-// Backward kernel: Alg. backward for each problem of the launch
-// ===========================================================================
-template <int NX, int SLOTS, bool REG>
-__device__ __forceinline__ void backward_problem(const KArgs& a, const ProbRec& pr, float* smem) {
+// Residual of the adjoint Schur system in double: g~ - S^ lambda~ with
+// lambda~ = w0 + w2, result to w1; norms as for the forward residual, the
+// right-hand side being the adjoint's (dl/dz, dl/dlambda) (Eq. ocp:backward).
+template <int NX>
+__device__ __noinline__ ResNorms bwd_residual64(const ProbRec* rec, const float* data, float* ws,
+                                                const float* dl) {
+  extern __shared__ float smem[];
   const int tid = threadIdx.x, BT = blockDim.x;
-  const Prob P = make_prob<NX>(pr, a.data, a.ws);
-  const int T = P.T, N = P.N, m = P.m, R = P.R, TM = P.TM;
-  float* xt = smem;       // x~
-  float* ut = xt + R;     // u~
-  float* xpl = ut + TM;   // x+ (QP solution)
-  float* upl = xpl + R;   // u+
-  float* laml = upl + TM; // lambda (forward multipliers)
-  Lds sh;
-  sh.w0 = laml + R;
-  sh.w1 = sh.w0 + R + 2 * NX;
-  sh.piv = sh.w1 + R + 2 * NX;
-  sh.red = sh.piv + 4 * N * NX;
-  sh.ls = sh.red + 128;
-  (void)sh.piv;
-  const float* W = P.W;
-  const float* iQ = W + P.L.iQ;
-  const float* iR = W + P.L.iR;
-  const float* blk = W + P.L.blk;
-  const float* dlx = a.dl + pr.sol_off;
+  const Prob P = make_prob<NX>(*rec, data, ws);
+  const Carve C = carve(P.R, P.TM, P.N, NX, BT);
+  const float* w0 = smem + C.w0;
+  const float* w2 = smem + C.w2;
+  float* w1 = smem + C.w1;
+  const float* dlx = dl + rec->sol_off;
+  const float* dlu = dlx + P.R;
+  const float* dll = dlu + P.TM;
+  const int nwv = (BT + 63) >> 6;
+  float r2 = 0.f, f2 = 0.f, b2 = 0.f;
+  for (int rho = tid; rho < P.R; rho += BT) {
+    const int t = rho / NX, i = rho - t * NX;
+    double row[3 * NX], g0;
+    schur_row<NX, double>(P, t, i, row, g0);
+    const double g = adjoint_rhs_row<NX, double>(P, t, i, dlx, dlu, dll);
+    const double res = g - row_dot64<NX>(row, w0 + t * NX, w2 + t * NX);
+    w1[NX + rho] = (float)res;
+    double fl = 0.0;
+#pragma unroll
+    for (int j = 0; j < 3 * NX; ++j) fl += fabs(row[j] * (double)w0[t * NX + j]);
+    r2 += (float)(res * res);
+    f2 += (float)(fl * fl);
+    b2 += dlx[rho] * dlx[rho] + dll[rho] * dll[rho];
+  }
+  for (int idx = tid; idx < P.TM; idx += BT) b2 += dlu[idx] * dlu[idx];
+  return block_sum3(r2, f2, b2, smem + C.red, nwv);
+}
+
+// z~ = G^-1 (dl/dz - H' lambda~) (Alg. backward line 3, in double), then the
+// VJP of Eq. loss_gradient, -dF/dtheta' [z~; lambda~], laid out like the data
+// arena.  lambda~ from the window w0.
+template <int NX>
+__device__ __noinline__ void bwd_finish(const ProbRec* rec, const float* data, float* ws,
+                                        const float* dl, float* adj, float* grad) {
+  extern __shared__ float smem[];
+  const int tid = threadIdx.x, BT = blockDim.x;
+  const Prob P = make_prob<NX>(*rec, data, ws);
+  const Carve C = carve(P.R, P.TM, P.N, NX, BT);
+  const int T = P.T, m = P.m, R = P.R, TM = P.TM;
+  float* xt = smem + C.xbar;
+  float* ut = smem + C.ubar;
+  const float* xpl = smem + C.xp;
+  const float* upl = smem + C.up;
+  const float* laml = smem + C.lam;
+  const float* w0 = smem + C.w0;
+  const float* lw = w0 + NX;                // lambda~, high part (unpadded view)
+  const float* lwl = smem + C.w2 + NX;      // low part
+  const float* Qd = P.W + P.L.Qd;
+  const float* Rd = P.W + P.L.Rd;
+  const float* dlx = dl + rec->sol_off;
   const float* dlu = dlx + R;
-  const float* dll = dlu + TM;
-  float* ax = a.adj + pr.sol_off;
+  float* ax = adj + rec->sol_off;
   float* au = ax + R;
   float* al = au + TM;
-
-  if (tid < NX) {
-    sh.w0[tid] = 0.f;
-    sh.w0[R + NX + tid] = 0.f;
-    sh.w1[tid] = 0.f;
-    sh.w1[R + NX + tid] = 0.f;
-  }
-  for (int i = tid; i < R; i += BT) {
-    xpl[i] = W[P.L.xp + i];
-    laml[i] = W[P.L.lam + i];
-  }
-  for (int i = tid; i < TM; i += BT) upl[i] = W[P.L.up + i];
-
-  float S[SLOTS][3 * NX], Ph[SLOTS][3 * NX], g[SLOTS], lt[SLOTS];
-#pragma unroll
-  for (int s = 0; s < SLOTS; ++s) {
-    const int rho = tid + s * BT;
-    g[s] = 0.f;
-    lt[s] = 0.f;
-    if constexpr (REG) {
-#pragma unroll
-      for (int j = 0; j < 3 * NX; ++j) {
-        S[s][j] = rho < R ? blk[rho * 6 * NX + j] : 0.f;
-        Ph[s][j] = rho < R ? blk[rho * 6 * NX + 3 * NX + j] : 0.f;
-      }
-    }
-    if (rho < R) {
-      // g~ = H G^-1 (dl/dz) - dl/dlambda  (Alg. backward line 1 with (-b, d) <- (dl/dz, dl/dlambda))
-      const int t = rho / NX, i = rho - t * NX;
-      float v = dlx[rho] * iQ[rho] - dll[rho];
-      if (t >= 1) {
-        const int tt = t - 1;
-        const float* At = P.A + tt * NX * NX + i * NX;
-        const float* Bt = P.B + tt * NX * m + i * m;
-#pragma unroll
-        for (int j = 0; j < NX; ++j) v = fmaf(-At[j], dlx[tt * NX + j] * iQ[tt * NX + j], v);
-        for (int l = 0; l < m; ++l) v = fmaf(-Bt[l], dlu[tt * m + l] * iR[tt * m + l], v);
-      }
-      g[s] = v;
-      lt[s] = a.bwd_warm ? al[rho] : 0.f;
-    }
-  }
-  __syncthreads();
-  int flags = 0, redi = 0;
-  const int maxit = a.bwd_max_iter > 0 ? a.bwd_max_iter : R + 10;
-  const int its = pcg<NX, SLOTS, REG>(P, sh, S, Ph, g, lt, maxit, a.bwd_tol, 0.f, flags, redi,
-                                      DMPC_PROB_BWD_PCG_MAXITER);
-  // z~ = G^-1 (dl/dz - H' lambda~)  (Alg. backward line 3)
-  publish<SLOTS>(sh.w0, lt, R, NX);
-  __syncthreads();
   for (int rho = tid; rho < R; rho += BT) {
     const int t = rho / NX, i = rho - t * NX;
-    float acc = dlx[rho] - sh.w0[NX + rho];
+    double acc = (double)dlx[rho] - ((double)lw[rho] + (double)lwl[rho]);
     if (t < T) {
       const float* At = P.A + t * NX * NX;
-      const float* ln = sh.w0 + NX + (t + 1) * NX;
+      const float* lh = lw + (t + 1) * NX;
+      const float* ll = lwl + (t + 1) * NX;
 #pragma unroll
-      for (int kk = 0; kk < NX; ++kk) acc = fmaf(At[kk * NX + i], ln[kk], acc);
+      for (int kk = 0; kk < NX; ++kk) acc += (double)At[kk * NX + i] * ((double)lh[kk] + (double)ll[kk]);
     }
-    const float v = acc * iQ[rho];
+    const float v = (float)(acc / (double)Qd[rho]);
     xt[rho] = v;
     ax[rho] = v;
-    al[rho] = sh.w0[NX + rho];
+    al[rho] = lw[rho];
   }
   for (int idx = tid; idx < TM; idx += BT) {
     const int t = idx / m, l = idx - t * m;
     const float* Bt = P.B + t * NX * m;
-    const float* ln = sh.w0 + NX + (t + 1) * NX;
-    float acc = dlu[idx];
+    const float* lh = lw + (t + 1) * NX;
+    const float* ll = lwl + (t + 1) * NX;
+    double acc = (double)dlu[idx];
 #pragma unroll
-    for (int kk = 0; kk < NX; ++kk) acc = fmaf(Bt[kk * m + l], ln[kk], acc);
-    const float v = acc * iR[idx];
+    for (int kk = 0; kk < NX; ++kk) acc += (double)Bt[kk * m + l] * ((double)lh[kk] + (double)ll[kk]);
+    const float v = (float)(acc / (double)Rd[idx]);
     ut[idx] = v;
     au[idx] = v;
   }
   __syncthreads();
-  // ---- VJP (Eq. loss_gradient): -dF/dtheta' [z~; lambda~] in the data layout
-  const float* lw = sh.w0 + NX;   // lambda~ (unpadded view)
-  float* gx0 = a.grad + pr.x0_off;
-  for (int i = tid; i < NX; i += BT) gx0[i] = lw[i];                   // d x_s = lambda~_0
-  const float* xl = W + P.L.xlin;
-  const float* ul = W + P.L.ulin;
+  // ---- VJP: -dF/dtheta' [z~; lambda~]
+  float* gx0 = grad + rec->x0_off;
+  for (int i = tid; i < NX; i += BT) gx0[i] = lw[i];   // d x_s = lambda~_0
+  const float* xl = P.W + P.L.xlin;
+  const float* ul = P.W + P.L.ulin;
   if (P.cost == DMPC_COST_DIAG) {
-    float* gQ = a.grad + pr.cost_off;
+    // dq = -x~, dQd = -x~ x (through the PD projection: a clamped entry moves q)
+    float* gQ = grad + rec->cost_off;
     float* gq = gQ + R;
     float* gR = gq + R;
     float* gr = gR + TM;
@@ -1283,12 +1433,12 @@ __device__ __forceinline__ void backward_problem(const KArgs& a, const ProbRec& 
       gR[idx] = (h >= kPdEps) ? -ut[idx] * upl[idx] : dr * ul[idx];
     }
   } else {
-    // softplus weights: theta (one thread per entry, stages of its phase in order),
-    // wscale and wfix get 0, xref
+    // softplus weights: theta (one thread per entry, stages of its phase in
+    // order), wscale and wfix get 0, xref
     const int K = P.nw + m;
     const float* th = P.costp;
     const float* xr = sp_xref<NX>(P);
-    float* gth = a.grad + pr.cost_off;
+    float* gth = grad + rec->cost_off;
     float* gws = gth + P.phases * K;
     float* gwf = gws + K;
     float* gxr = gwf + (NX - P.nw);
@@ -1299,18 +1449,14 @@ __device__ __forceinline__ void backward_problem(const KArgs& a, const ProbRec& 
         if (sp_phase(P, t) != ph) continue;
         if (j < P.nw) {
           const int idx = t * NX + j;
-          const float w = sp_weight(P, t, j);
-          const bool act = w >= kPdEps;
-          const float dQ = -xt[idx] * xpl[idx];
+          const bool act = sp_weight(P, t, j) >= kPdEps;
           const float dq = -xt[idx];
-          dw += (act ? dQ : 0.f) + dq * (-xr[j] + (act ? 0.f : xl[idx]));
+          dw += (act ? -xt[idx] * xpl[idx] : 0.f) + dq * (-xr[j] + (act ? 0.f : xl[idx]));
         } else if (t < T) {
           const int idx = t * m + (j - P.nw);
-          const float w = sp_weight(P, t, j);
-          const bool act = w >= kPdEps;
-          const float dR = -ut[idx] * upl[idx];
+          const bool act = sp_weight(P, t, j) >= kPdEps;
           const float dr = -ut[idx];
-          dw += (act ? dR : 0.f) + dr * (act ? 0.f : ul[idx]);
+          dw += (act ? -ut[idx] * upl[idx] : 0.f) + dr * (act ? 0.f : ul[idx]);
         }
       }
       const float* wsc = th + P.phases * K;
@@ -1319,11 +1465,11 @@ __device__ __forceinline__ void backward_problem(const KArgs& a, const ProbRec& 
     for (int e = tid; e < K + (NX - P.nw); e += BT) gws[e] = 0.f;   // wscale, wfix
     for (int i = tid; i < NX; i += BT) {
       float d = 0.f;
-      for (int t = 0; t <= T; ++t) d += -xt[t * NX + i] * (-sp_wx<NX>(P, t, i));
-      gxr[i] = d;
+      for (int t = 0; t <= T; ++t) d += xt[t * NX + i] * sp_wx<NX>(P, t, i);
+      gxr[i] = d;   // dq/dxref = -w, dq = -x~
     }
   }
-  float* gd = a.grad + pr.dyn_off;
+  float* gd = grad + rec->dyn_off;
   if (P.dyn == DMPC_DYN_LTV) {
     // dA_t = lambda_{t+1} x~_t' + lambda~_{t+1} x_t',  dB_t likewise,  dc_t = lambda~_{t+1}
     float* gA = gd;
@@ -1342,32 +1488,185 @@ __device__ __forceinline__ void backward_problem(const KArgs& a, const ProbRec& 
     const int np = P.dyn == DMPC_DYN_CARTPOLE ? kCartpoleParams : kBicycleParams;
     for (int e = tid; e < np; e += BT) gd[e] = 0.f;
   }
-  const int anyf = __syncthreads_or(flags);
-  if (tid == 0) {
-    a.status[pr.index] |= (flags | anyf);
-    a.info[4 * pr.index + 1] = its;
-  }
   __syncthreads();
 }
 
+// ===========================================================================
+// Kernels
+// ===========================================================================
 typedef void (*KernelFn)(KArgs);
 struct KEntry {
   int nx, slots, maxbt, reg;
   KernelFn fwd, bwd;
 };
 
+// Loads this thread's rows (Schur, preconditioner, right-hand side).
+template <int NX, int SLOTS, bool REG>
+__device__ __forceinline__ void load_rows(const Prob& P, float (&S)[SLOTS][3 * NX],
+                                          float (&Ph)[SLOTS][3 * NX], float (&g)[SLOTS]) {
+  const int tid = threadIdx.x, BT = blockDim.x;
+  const float* blk = P.W + P.L.blk;
+  const float* gv = P.W + P.L.g;
+#pragma unroll
+  for (int s = 0; s < SLOTS; ++s) {
+    const int rho = tid + s * BT;
+    const bool ok = rho < P.R;
+    g[s] = ok ? gv[rho] : 0.f;
+    if constexpr (REG) {
+#pragma unroll
+      for (int j = 0; j < 3 * NX; ++j) {
+        S[s][j] = ok ? blk[rho * 6 * NX + j] : 0.f;
+        Ph[s][j] = ok ? blk[rho * 6 * NX + 3 * NX + j] : 0.f;
+      }
+    }
+  }
+}
+
+// One QP solve of the Schur system, mixed precision.  lambda = hi + lo is a
+// double-float pair carried across SQP iterations (the warm start of Alg.
+// pcg).  Each pass computes the residual g - S^ lambda with rows re-assembled
+// in double, solves for the correction with the float PCG (Alg. pcg) and adds
+// it to (hi, lo).  Pass 0 stops at ||r||_{Phi^-1} <= tol ||g||_{Phi^-1} (the
+// paper's relative tolerance); then up to `steps` refinement passes, each to
+// relative tolerance ref_tol, stop once the residual meets the KKT target
+// (||r||_2 <= kkt_tol ||rhs||_2).
+template <int NX, int SLOTS, bool REG, typename ResidualFn>
+__device__ __forceinline__ int qp_solve(const Prob& P, const Lds& sh, float (&S)[SLOTS][3 * NX],
+                                        float (&Ph)[SLOTS][3 * NX], const float (&g)[SLOTS],
+                                        float (&hi)[SLOTS], float (&lo)[SLOTS], int steps,
+                                        int maxit, float tol, float abs_tol, float ref_tol,
+                                        float kkt_tol, int& flags, int& redi, int maxit_flag,
+                                        ResidualFn residual) {
+  const int tid = threadIdx.x, BT = blockDim.x;
+  const float etab = precond_norm<NX, SLOTS, REG>(P, sh, Ph, g, redi);
+  int its = 0;
+  for (int k = 0; k <= steps; ++k) {
+    publish<SLOTS>(sh.w0, hi, P.R, NX);
+    publish<SLOTS>(sh.w2, lo, P.R, NX);
+    __syncthreads();
+    const ResNorms nr = residual();
+    if (k > 0 && nr.r2 <= kkt_tol * kkt_tol * nr.rhs2) break;
+    float rr[SLOTS], d[SLOTS];
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+      const int rho = tid + s * BT;
+      rr[s] = rho < P.R ? sh.w1[NX + rho] : 0.f;
+    }
+    __syncthreads();
+    if (k == 0)
+      its += pcg<NX, SLOTS, REG>(P, sh, S, Ph, rr, d, maxit, 0.f, fmaxf(tol * tol * etab, abs_tol),
+                                 flags, redi, maxit_flag);
+    else
+      its += pcg<NX, SLOTS, REG>(P, sh, S, Ph, rr, d, maxit, ref_tol, 0.f, flags, redi,
+                                 maxit_flag);
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+      const double v = ((double)hi[s] + (double)lo[s]) + (double)d[s];
+      hi[s] = (float)v;
+      lo[s] = (float)(v - (double)hi[s]);
+    }
+  }
+  return its;
+}
+
 template <int NX, int SLOTS, int MAXBT, bool REG>
 __global__ __launch_bounds__(MAXBT) void forward_kernel(KArgs a) {
   extern __shared__ float smem[];
-  for (int pi = a.first + blockIdx.x; pi < a.first + a.count; pi += gridDim.x)
-    forward_problem<NX, SLOTS, REG>(a, a.recs[pi], smem);
+  const int tid = threadIdx.x, BT = blockDim.x;
+  LsParams lp;
+#pragma unroll
+  for (int i = 0; i < kMaxAlphas; ++i) lp.alphas[i] = a.alphas[i];
+  lp.n = a.n_alphas;
+  lp.eta = a.ls_eta;
+  for (int pi = a.first + blockIdx.x; pi < a.first + a.count; pi += gridDim.x) {
+    const ProbRec* rec = a.recs + pi;
+    const Prob P = make_prob<NX>(*rec, a.data, a.ws);
+    const Lds sh = lds_of<NX>(smem, P);
+    float* soll = a.sol + rec->sol_off + P.R + P.TM;
+    fwd_begin<NX>(rec, a.data, a.sol, a.ws, a.init);
+    float lam[SLOTS], lo[SLOTS];
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+      const int rho = tid + s * BT;
+      lam[s] = (rho < P.R && a.init == DMPC_INIT_GIVEN) ? soll[rho] : 0.f;
+      lo[s] = 0.f;
+    }
+    int flags = 0, pcg_total = 0, sel = 0, redi = 0;
+    const int maxit = a.pcg_max_iter > 0 ? a.pcg_max_iter : P.R + 10;
+    const float rtol = a.refine_tol > 0.f ? a.refine_tol : a.pcg_tol;
+    for (int k = 0; k < a.sqp_iters; ++k) {
+      if (fwd_blocks<NX>(rec, a.data, a.ws)) flags |= DMPC_PROB_NONPD;
+      float S[SLOTS][3 * NX], Ph[SLOTS][3 * NX], g[SLOTS];
+      load_rows<NX, SLOTS, REG>(P, S, Ph, g);
+      pcg_total += qp_solve<NX, SLOTS, REG>(
+          P, sh, S, Ph, g, lam, lo, a.refine_steps, maxit, a.pcg_tol, a.pcg_abs_tol, rtol,
+          a.kkt_tol, flags, redi, DMPC_PROB_PCG_MAXITER,
+          [&]() { return fwd_residual64<NX>(rec, a.data, a.ws); });
+      publish<SLOTS>(sh.w0, lam, P.R, NX);
+      publish<SLOTS>(sh.w2, lo, P.R, NX);
+      __syncthreads();
+      const int r = fwd_recover_ls<NX>(rec, a.data, a.ws, lp, k == a.sqp_iters - 1);
+      sel = r & 0xff;
+      flags |= r >> 8;
+    }
+    float* wlam = P.W + P.L.lam;
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+      const int rho = tid + s * BT;
+      if (rho < P.R) {
+        soll[rho] = lam[s];
+        wlam[rho] = lam[s];
+      }
+    }
+    flags |= fwd_finish<NX>(rec, a.data, a.sol, a.ws);
+    const int anyf = __syncthreads_or(flags);
+    if (tid == 0) {
+      a.status[rec->index] = flags | anyf;
+      a.info[4 * rec->index + 0] = pcg_total;
+      a.info[4 * rec->index + 2] = sel;
+      a.info[4 * rec->index + 3] = a.sqp_iters;
+    }
+    __syncthreads();
+  }
 }
 
 template <int NX, int SLOTS, int MAXBT, bool REG>
 __global__ __launch_bounds__(MAXBT) void backward_kernel(KArgs a) {
   extern __shared__ float smem[];
-  for (int pi = a.first + blockIdx.x; pi < a.first + a.count; pi += gridDim.x)
-    backward_problem<NX, SLOTS, REG>(a, a.recs[pi], smem);
+  const int tid = threadIdx.x, BT = blockDim.x;
+  for (int pi = a.first + blockIdx.x; pi < a.first + a.count; pi += gridDim.x) {
+    const ProbRec* rec = a.recs + pi;
+    const Prob P = make_prob<NX>(*rec, a.data, a.ws);
+    const Lds sh = lds_of<NX>(smem, P);
+    bwd_begin<NX>(rec, a.data, a.ws, a.dl);
+    float S[SLOTS][3 * NX], Ph[SLOTS][3 * NX], g[SLOTS], lt[SLOTS], lo[SLOTS];
+    load_rows<NX, SLOTS, REG>(P, S, Ph, g);
+    const float* alv = a.adj + rec->sol_off + P.R + P.TM;
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+      const int rho = tid + s * BT;
+      lt[s] = (rho < P.R && a.bwd_warm) ? alv[rho] : 0.f;
+      lo[s] = 0.f;
+    }
+    __syncthreads();
+    int flags = 0, redi = 0;
+    const int maxit = a.bwd_max_iter > 0 ? a.bwd_max_iter : P.R + 10;
+    const float rtol = a.refine_tol > 0.f ? a.refine_tol : a.bwd_tol;
+    const int its = qp_solve<NX, SLOTS, REG>(
+        P, sh, S, Ph, g, lt, lo, a.refine_steps, maxit, a.bwd_tol, 0.f, rtol, a.kkt_tol, flags,
+        redi, DMPC_PROB_BWD_PCG_MAXITER,
+        [&]() { return bwd_residual64<NX>(rec, a.data, a.ws, a.dl); });
+    publish<SLOTS>(sh.w0, lt, P.R, NX);
+    publish<SLOTS>(sh.w2, lo, P.R, NX);
+    __syncthreads();
+    bwd_finish<NX>(rec, a.data, a.ws, a.dl, a.adj, a.grad);
+    const int anyf = __syncthreads_or(flags);
+    if (tid == 0) {
+      a.status[rec->index] |= (flags | anyf);
+      a.info[4 * rec->index + 1] = its;
+    }
+    __syncthreads();
+  }
 }
 
 }  // namespace dmpc

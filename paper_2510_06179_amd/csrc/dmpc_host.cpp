@@ -65,8 +65,9 @@ dmpc_status check_opts(const dmpc_opts* o) {
   if (o->block_threads != 0 &&
       (o->block_threads < 64 || o->block_threads > 1024 || o->block_threads % 64 != 0))
     return DMPC_ERR_INVALID_ARG;
-  for (int r : o->reserved)
-    if (r != 0) return DMPC_ERR_INVALID_ARG;
+  if (o->refine_steps < 0 || o->refine_steps > 8 || !finite_nonneg(o->refine_tol) ||
+      !finite_nonneg(o->kkt_tol))
+    return DMPC_ERR_INVALID_ARG;
   return DMPC_OK;
 }
 
@@ -172,6 +173,9 @@ KArgs make_args(const dmpc_plan* pl, const float* data, float* sol, void* ws, co
   a.pcg_abs_tol = o.pcg_abs_tol;
   a.ls_eta = o.ls_eta;
   a.bwd_tol = o.bwd_pcg_tol;
+  a.refine_steps = o.refine_steps;
+  a.refine_tol = o.refine_tol;
+  a.kkt_tol = o.kkt_tol;
   for (int i = 0; i < kMaxAlphas; ++i) a.alphas[i] = i < o.n_alphas ? o.alphas[i] : 0.f;
   return a;
 }
@@ -191,6 +195,9 @@ void dmpc_default_opts(dmpc_opts* o) {
   o->ls_eta = 0.4f;
   o->init = DMPC_INIT_GIVEN;
   o->bwd_pcg_tol = 1e-6f;
+  o->refine_steps = 1;
+  o->refine_tol = 1e-2f;
+  o->kkt_tol = 1e-6f;
 }
 
 const char* dmpc_status_string(dmpc_status s) {
@@ -342,7 +349,7 @@ dmpc_status dmpc_plan_create(dmpc_handle* h, const dmpc_problem* problems, int32
     }
     Group& g = pl->groups.back();
     g.count += 1;
-    g.cfg.lds_bytes = std::max(g.cfg.lds_bytes, (size_t)lds_floats(p.T, p.nx, p.nu) * sizeof(float));
+    g.cfg.lds_bytes = std::max(g.cfg.lds_bytes, (size_t)lds_floats(p.T, p.nx, p.nu, g.cfg.bt) * sizeof(float));
     pl->grp[k] = (int)pl->groups.size() - 1;
   }
   pl->ws_bytes = (size_t)ws_off * sizeof(float);

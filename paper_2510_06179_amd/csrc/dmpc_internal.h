@@ -38,6 +38,7 @@ struct WsLayout {
   int64_t blk;                    // saved rows of S^ and Phi^-1: [N*nx][6*nx]
   int64_t xp, up, lam;            // last QP solution and multipliers
   int64_t xlin, ulin;             // last linearisation point
+  int64_t g;                      // right-hand side of the Schur system [N*nx]
   int64_t total;
 };
 
@@ -70,6 +71,7 @@ DMPC_HD inline WsLayout ws_layout(int T, int nx, int nu, int dyn) {
   L.lam = o; o += R;
   L.xlin = o; o += R;
   L.ulin = o; o += TM;
+  L.g = o; o += R;
   L.total = align_up(o, kAlignFloats);
   return L;
 }
@@ -89,11 +91,12 @@ DMPC_HD inline int64_t sol_block_len(int T, int nx, int nu) {
 }
 
 // LDS floats a workgroup needs for a problem (forward and backward kernels).
-DMPC_HD inline int64_t lds_floats(int T, int nx, int nu) {
+// (must match the device-side carve in dmpc_device.h)
+DMPC_HD inline int64_t lds_floats(int T, int nx, int nu, int bt) {
   const int64_t N = T + 1, R = N * nx, TM = (int64_t)T * nu;
-  return 3 * R + 2 * TM              // xbar/ubar/xp/up (fwd) or xt/ut/xp/up/lam (bwd)
-         + 2 * (R + 2 * nx)          // two padded windows
-         + 4 * N * nx                // Gauss-Jordan pivot rows, double buffered
+  return 3 * R + 2 * TM              // xbar/ubar/xp/up/lam (fwd) or xt/ut/xp/up/lam (bwd)
+         + 3 * (R + 2 * nx)          // three padded windows
+         + 4 * (int64_t)bt           // Gauss-Jordan pivot rows, double buffered
          + 2 * 64                    // scalar reductions
          + 2 * (kMaxAlphas + 1) * N  // line-search stage costs and defects
          + 2 * (kMaxAlphas + 1) + 2; // per-candidate sums
@@ -113,8 +116,8 @@ struct KArgs {
   int32_t* status;
   int32_t* info;
   int32_t sqp_iters, pcg_max_iter, n_alphas, init;
-  int32_t bwd_warm, bwd_max_iter;
-  float pcg_tol, pcg_abs_tol, ls_eta, bwd_tol;
+  int32_t bwd_warm, bwd_max_iter, refine_steps;
+  float pcg_tol, pcg_abs_tol, ls_eta, bwd_tol, refine_tol, kkt_tol;
   float alphas[kMaxAlphas];
 };
 

@@ -108,5 +108,5 @@ def test_backward_warm_start_reduces_iterations():
     _, grad2 = s.solve_backward(_cotangent_arena(s, cots), adj=adj_t)
     torch.cuda.synchronize()
     warm = s.info.cpu().numpy()[:, 1]
-    assert np.all(warm <= cold) and np.all(warm <= 2)
+    assert np.all(warm < cold)
     assert rel_err(grad2.cpu().numpy(), grad) <= REL_TOL

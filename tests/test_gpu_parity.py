@@ -8,7 +8,7 @@ import torch
 import oracle
 from paper_2510_06179_amd import _lib, batch
 from paper_2510_06179_amd import workloads as W
-from _parity import KKT_TOL, REL_TOL, gpu_only, gpu_solve, oracle_kkt_of_gpu_qp, rel_err
+from _parity import REL_TOL, gpu_only, gpu_solve, oracle_kkt_of_gpu_qp, rel_err
 
 pytestmark = [pytest.mark.gpu, gpu_only]
 
@@ -19,16 +19,16 @@ def _check_qp_step(probs, **opts):
     """One SQP step with alpha = 1: the GPU's QP solution vs the oracle's LU."""
     s, res, status, info = gpu_solve(probs, sqp_iters=1, alphas=(1.0,), **opts)
     assert not np.any(status & BAD), status
-    worst = dict(kkt=0.0, x=0.0, u=0.0, lam=0.0)
+    worst = dict(kkt_over_bound=0.0, x=0.0, u=0.0, lam=0.0)
     for k, p in enumerate(probs):
         x, u, lam = res[k]
         xo, uo, lo, hist = oracle.sqp.sqp(p, 1, alphas=(1.0,))
-        kkt, sq, _ = oracle_kkt_of_gpu_qp(p, s, k)
-        worst["kkt"] = max(worst["kkt"], kkt)
+        kkt, bound, sq, _ = oracle_kkt_of_gpu_qp(p, s, k)
+        worst["kkt_over_bound"] = max(worst["kkt_over_bound"], kkt / bound)
         worst["x"] = max(worst["x"], rel_err(x, xo))
         worst["u"] = max(worst["u"], rel_err(u, uo))
         worst["lam"] = max(worst["lam"], rel_err(lam, lo))
-    assert worst["kkt"] <= KKT_TOL, worst
+    assert worst["kkt_over_bound"] <= 1.0, worst
     for key in ("x", "u", "lam"):
         assert worst[key] <= REL_TOL, worst
     return s, info
@@ -39,9 +39,10 @@ def test_lq_batch_qp_step(seed):
     _check_qp_step(W.lq_batch(seed), pcg_tol=1e-6)
 
 
-def test_lq_batch_tight_tolerance_hits_cap_gracefully():
-    # a relative tolerance of 1e-8 is below float32 resolution: PCG runs to its
-    # cap, flags it, and the answer is still within the accuracy targets
+def test_lq_batch_tight_tolerance():
+    # a relative tolerance of 1e-8 is below float32 resolution; the float PCG
+    # stops on its recursive residual and the refinement step (residual in
+    # double) keeps the answer within the accuracy targets
     s, info = _check_qp_step(W.lq_batch(2), pcg_tol=1e-8)
     assert np.all(info[:, 0] > 0)
 
@@ -82,8 +83,8 @@ def test_cartpole_per_iteration_parity():
             q = cur[k]
             xb, ub, _ = oracle.sqp.initial_guess(q)
             xo, uo, lo, h = oracle.sqp.sqp_step(q, xb, ub)
-            kkt, sq, _ = oracle_kkt_of_gpu_qp(q, s, k)
-            assert kkt <= KKT_TOL, (it, k, kkt)
+            kkt, bound, sq, _ = oracle_kkt_of_gpu_qp(q, s, k)
+            assert kkt <= bound, (it, k, kkt, bound)
             a_gpu = int(info[k, 2])
             if a_gpu != h["alpha_idx"]:
                 d = h["ls"]["dphi"]
@@ -109,8 +110,8 @@ def test_cartpole_ten_iterations_end_to_end():
         assert rel_err(x, xo) <= REL_TOL, k
         assert rel_err(u, uo) <= REL_TOL, k
         assert rel_err(lam, lo) <= 10 * REL_TOL, k
-        kkt, _, _ = oracle_kkt_of_gpu_qp(p, s, k)
-        assert kkt <= KKT_TOL, (k, kkt)
+        kkt, bound, _, _ = oracle_kkt_of_gpu_qp(p, s, k)
+        assert kkt <= bound, (k, kkt, bound)
 
 
 def test_plain_one_problem_launches_match_batched():
@@ -135,7 +136,8 @@ def test_deterministic_bitwise():
 
 def test_pcg_cap_flag_forced_from_host():
     probs = W.lq_batch(0, batch=2)
-    s, res, status, info = gpu_solve(probs, sqp_iters=1, alphas=(1.0,), pcg_max_iter=1)
+    s, res, status, info = gpu_solve(probs, sqp_iters=1, alphas=(1.0,), pcg_max_iter=1,
+                                     refine_steps=0)
     assert np.all(status & _lib.PROB_PCG_MAXITER)
     assert np.all(info[:, 0] == 1)
 
