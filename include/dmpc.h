@@ -123,8 +123,8 @@ typedef struct dmpc_opts {
                                right-hand side||_2 or the float32 floor (default 1e-6) */
 } dmpc_opts;
 
-/* Fills *o with the defaults: 1 SQP iteration, PCG tol 1e-6, one refinement
- * pass (tol 1e-2, KKT target 1e-6), candidates {1, 0.7, 0.3, 0.1, 0.01}
+/* Fills *o with the defaults: 1 SQP iteration, PCG tol 1e-6, up to three
+ * refinement passes (tol 1e-2, KKT target 1e-6), candidates {1, 0.7, 0.3, 0.1, 0.01}
  * (App. A.3), eta = 0.4, INIT_GIVEN. Host only. */
 void dmpc_default_opts(dmpc_opts* o);
 

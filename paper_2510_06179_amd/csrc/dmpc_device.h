@@ -31,126 +31,141 @@
 namespace dmpc {
 
 // ===========================================================================
-// Forward-mode dual numbers (Jacobians of the nonlinear models)
+// Forward-mode dual numbers (Jacobians of the nonlinear models), base type R
 // ===========================================================================
-template <int K>
-struct Dual {
-  float v;
-  float d[K];
+template <typename T>
+struct Ident {
+  typedef T type;
 };
 
-template <int K>
-__device__ __forceinline__ Dual<K> mkconst(float a) {
-  Dual<K> r;
+template <int K, typename R>
+struct Dual {
+  R v;
+  R d[K];
+};
+
+template <int K, typename R>
+__device__ __forceinline__ Dual<K, R> mkconst(R a) {
+  Dual<K, R> r;
   r.v = a;
 #pragma unroll
-  for (int k = 0; k < K; ++k) r.d[k] = 0.f;
+  for (int k = 0; k < K; ++k) r.d[k] = R(0);
   return r;
 }
-template <int K>
-__device__ __forceinline__ Dual<K> operator+(const Dual<K>& a, const Dual<K>& b) {
-  Dual<K> r;
+template <int K, typename R>
+__device__ __forceinline__ Dual<K, R> operator+(const Dual<K, R>& a, const Dual<K, R>& b) {
+  Dual<K, R> r;
   r.v = a.v + b.v;
 #pragma unroll
   for (int k = 0; k < K; ++k) r.d[k] = a.d[k] + b.d[k];
   return r;
 }
-template <int K>
-__device__ __forceinline__ Dual<K> operator-(const Dual<K>& a, const Dual<K>& b) {
-  Dual<K> r;
+template <int K, typename R>
+__device__ __forceinline__ Dual<K, R> operator-(const Dual<K, R>& a, const Dual<K, R>& b) {
+  Dual<K, R> r;
   r.v = a.v - b.v;
 #pragma unroll
   for (int k = 0; k < K; ++k) r.d[k] = a.d[k] - b.d[k];
   return r;
 }
-template <int K>
-__device__ __forceinline__ Dual<K> operator-(const Dual<K>& a) {
-  Dual<K> r;
+template <int K, typename R>
+__device__ __forceinline__ Dual<K, R> operator-(const Dual<K, R>& a) {
+  Dual<K, R> r;
   r.v = -a.v;
 #pragma unroll
   for (int k = 0; k < K; ++k) r.d[k] = -a.d[k];
   return r;
 }
-template <int K>
-__device__ __forceinline__ Dual<K> operator*(const Dual<K>& a, const Dual<K>& b) {
-  Dual<K> r;
+template <int K, typename R>
+__device__ __forceinline__ Dual<K, R> operator*(const Dual<K, R>& a, const Dual<K, R>& b) {
+  Dual<K, R> r;
   r.v = a.v * b.v;
 #pragma unroll
   for (int k = 0; k < K; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
   return r;
 }
-template <int K>
-__device__ __forceinline__ Dual<K> operator/(const Dual<K>& a, const Dual<K>& b) {
-  Dual<K> r;
-  const float ib = 1.f / b.v;
+template <int K, typename R>
+__device__ __forceinline__ Dual<K, R> operator/(const Dual<K, R>& a, const Dual<K, R>& b) {
+  Dual<K, R> r;
+  const R ib = R(1) / b.v;
   r.v = a.v * ib;
 #pragma unroll
   for (int k = 0; k < K; ++k) r.d[k] = (a.d[k] - r.v * b.d[k]) * ib;
   return r;
 }
-template <int K>
-__device__ __forceinline__ Dual<K> operator+(const Dual<K>& a, float b) {
-  Dual<K> r = a;
+template <int K, typename R>
+__device__ __forceinline__ Dual<K, R> operator+(const Dual<K, R>& a, typename Ident<R>::type b) {
+  Dual<K, R> r = a;
   r.v += b;
   return r;
 }
-template <int K>
-__device__ __forceinline__ Dual<K> operator+(float b, const Dual<K>& a) { return a + b; }
-template <int K>
-__device__ __forceinline__ Dual<K> operator-(const Dual<K>& a, float b) {
-  Dual<K> r = a;
+template <int K, typename R>
+__device__ __forceinline__ Dual<K, R> operator+(typename Ident<R>::type b, const Dual<K, R>& a) {
+  return a + b;
+}
+template <int K, typename R>
+__device__ __forceinline__ Dual<K, R> operator-(const Dual<K, R>& a, typename Ident<R>::type b) {
+  Dual<K, R> r = a;
   r.v -= b;
   return r;
 }
-template <int K>
-__device__ __forceinline__ Dual<K> operator-(float b, const Dual<K>& a) {
-  Dual<K> r = -a;
+template <int K, typename R>
+__device__ __forceinline__ Dual<K, R> operator-(typename Ident<R>::type b, const Dual<K, R>& a) {
+  Dual<K, R> r = -a;
   r.v += b;
   return r;
 }
-template <int K>
-__device__ __forceinline__ Dual<K> operator*(const Dual<K>& a, float b) {
-  Dual<K> r;
+template <int K, typename R>
+__device__ __forceinline__ Dual<K, R> operator*(const Dual<K, R>& a, typename Ident<R>::type b) {
+  Dual<K, R> r;
   r.v = a.v * b;
 #pragma unroll
   for (int k = 0; k < K; ++k) r.d[k] = a.d[k] * b;
   return r;
 }
-template <int K>
-__device__ __forceinline__ Dual<K> operator*(float b, const Dual<K>& a) { return a * b; }
-template <int K>
-__device__ __forceinline__ Dual<K> operator/(const Dual<K>& a, float b) { return a * (1.f / b); }
+template <int K, typename R>
+__device__ __forceinline__ Dual<K, R> operator*(typename Ident<R>::type b, const Dual<K, R>& a) {
+  return a * b;
+}
+template <int K, typename R>
+__device__ __forceinline__ Dual<K, R> operator/(const Dual<K, R>& a, typename Ident<R>::type b) {
+  return a * (R(1) / b);
+}
 
-template <int K>
-__device__ __forceinline__ Dual<K> chain(const Dual<K>& a, float fv, float dfv) {
-  Dual<K> r;
+template <int K, typename R>
+__device__ __forceinline__ Dual<K, R> chain(const Dual<K, R>& a, R fv, R dfv) {
+  Dual<K, R> r;
   r.v = fv;
 #pragma unroll
   for (int k = 0; k < K; ++k) r.d[k] = dfv * a.d[k];
   return r;
 }
-__device__ __forceinline__ float sin_(float a) { return sinf(a); }
-__device__ __forceinline__ float cos_(float a) { return cosf(a); }
-__device__ __forceinline__ float atan_(float a) { return atanf(a); }
-__device__ __forceinline__ float tanh_(float a) { return tanhf(a); }
-__device__ __forceinline__ float sqrt_(float a) { return sqrtf(a); }
-template <int K>
-__device__ __forceinline__ Dual<K> sin_(const Dual<K>& a) { return chain(a, sinf(a.v), cosf(a.v)); }
-template <int K>
-__device__ __forceinline__ Dual<K> cos_(const Dual<K>& a) { return chain(a, cosf(a.v), -sinf(a.v)); }
-template <int K>
-__device__ __forceinline__ Dual<K> atan_(const Dual<K>& a) {
-  return chain(a, atanf(a.v), 1.f / (1.f + a.v * a.v));
+__device__ __forceinline__ double sin_(double a) { return sin(a); }
+__device__ __forceinline__ double cos_(double a) { return cos(a); }
+__device__ __forceinline__ double atan_(double a) { return atan(a); }
+__device__ __forceinline__ double tanh_(double a) { return tanh(a); }
+__device__ __forceinline__ double sqrt_(double a) { return sqrt(a); }
+template <int K, typename R>
+__device__ __forceinline__ Dual<K, R> sin_(const Dual<K, R>& a) {
+  return chain(a, sin_(a.v), cos_(a.v));
 }
-template <int K>
-__device__ __forceinline__ Dual<K> tanh_(const Dual<K>& a) {
-  const float t = tanhf(a.v);
-  return chain(a, t, 1.f - t * t);
+template <int K, typename R>
+__device__ __forceinline__ Dual<K, R> cos_(const Dual<K, R>& a) {
+  return chain(a, cos_(a.v), -sin_(a.v));
 }
-template <int K>
-__device__ __forceinline__ Dual<K> sqrt_(const Dual<K>& a) {
-  const float s = sqrtf(a.v);
-  return chain(a, s, 0.5f / s);
+template <int K, typename R>
+__device__ __forceinline__ Dual<K, R> atan_(const Dual<K, R>& a) {
+  return chain(a, atan_(a.v), R(1) / (R(1) + a.v * a.v));
+}
+template <int K, typename R>
+__device__ __forceinline__ Dual<K, R> tanh_(const Dual<K, R>& a) {
+  const R t = tanh_(a.v);
+  return chain(a, t, R(1) - t * t);
+}
+template <int K, typename R>
+__device__ __forceinline__ Dual<K, R> sqrt_(const Dual<K, R>& a) {
+  const R q = sqrt_(a.v);
+  return chain(a, q, R(0.5) / q);
 }
 
 // ===========================================================================
@@ -165,7 +180,7 @@ __device__ __forceinline__ void cartpole_step(const float* par, const S* x, cons
   const float M = mp + mc;
   const S s = sin_(x[2]);
   const S c = cos_(x[2]);
-  const S den = M + mp * (1.f - c * c);
+  const S den = M + mp * (1.0 - c * c);
   const S d2 = ((mp * g) * s * c - (mp * L) * s * x[3] * x[3]) / (den * L);
   const S d4 = ((mp * g) * s * c - (mp * L) * s * x[3] + u[0]) / den;
   xn[0] = x[0] + dt * x[1];
@@ -202,7 +217,7 @@ __device__ __forceinline__ void bicycle_step(const float* p, const S* x, const S
   const S d_v = (Fx * cb + Fy * sb) / m;
   const S d_beta = (Fy * cb - Fx * sb) / (m * vs) - r;
   const S d_om = (tau - rw * Fxr) / Iw;
-  const S d_psi = r - kap * v * cos_(dpsi + beta) / (1.f - kap * e);
+  const S d_psi = r - kap * v * cos_(dpsi + beta) / (1.0 - kap * e);
   const S d_e = v * sin_(dpsi + beta);
   xn[0] = r + dt * d_r;
   xn[1] = v + dt * d_v;
@@ -234,6 +249,23 @@ __device__ __forceinline__ float wave_sum(float v) {
   const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
   const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
   return (r0 + r1) + (r2 + r3);
+}
+
+// Double wave sum (butterfly: partners add the same two values, so every
+// lane gets the same bits).
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double block_sum_d(double v, double* red, int nwv) {
+  v = wave_sum_d(v);
+  if (nwv == 1) return v;
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < nwv; ++w) s += red[w];
+  return s;
 }
 
 // Block sum: wave sums, then (several waves) one LDS exchange read in order.
@@ -323,126 +355,135 @@ __device__ __forceinline__ const float* sp_xref(const Prob& P) {
   return P.costp + P.phases * K + K + (NX - P.nw);
 }
 
-// Stage costs at a point (the true costs, as used by the merit function).
+// Stage costs at a point (the true costs, as used by the merit function),
+// evaluated in double.
 template <int NX>
-__device__ __forceinline__ float cost_x(const Prob& P, int t, const float* x) {
-  float s = 0.f;
+__device__ __forceinline__ double cost_x(const Prob& P, int t, const double* x) {
+  double s = 0.0;
   if (P.cost == DMPC_COST_DIAG) {
     const float* Qd = P.costp + t * NX;
     const float* q = P.costp + P.N * NX + t * NX;
 #pragma unroll
-    for (int i = 0; i < NX; ++i) s += 0.5f * Qd[i] * x[i] * x[i] + q[i] * x[i];
+    for (int i = 0; i < NX; ++i) s += 0.5 * (double)Qd[i] * x[i] * x[i] + (double)q[i] * x[i];
   } else {
     const float* xr = sp_xref<NX>(P);
 #pragma unroll
     for (int i = 0; i < NX; ++i) {
-      const float d = x[i] - xr[i];
-      s += 0.5f * sp_wx<NX>(P, t, i) * d * d;
+      const double d = x[i] - (double)xr[i];
+      s += 0.5 * (double)sp_wx<NX>(P, t, i) * d * d;
     }
   }
   return s;
 }
 template <int NX>
-__device__ __forceinline__ float cost_u1(const Prob& P, int t, int l, float u) {
+__device__ __forceinline__ double cost_u1(const Prob& P, int t, int l, double u) {
   if (P.cost == DMPC_COST_DIAG) {
     const float* Rd = P.costp + 2 * P.N * NX + t * P.m;
     const float* r = Rd + P.TM;
-    return 0.5f * Rd[l] * u * u + r[l] * u;
+    return 0.5 * (double)Rd[l] * u * u + (double)r[l] * u;
   }
-  return 0.5f * sp_weight(P, t, P.nw + l) * u * u;
+  return 0.5 * (double)sp_weight(P, t, P.nw + l) * u * u;
 }
 // directional derivative of the stage costs: grad c(xb)'(xq - xb)
 template <int NX>
-__device__ __forceinline__ float dcost_x(const Prob& P, int t, const float* xb, const float* xq) {
-  float s = 0.f;
+__device__ __forceinline__ double dcost_x(const Prob& P, int t, const float* xb, const float* xq) {
+  double s = 0.0;
   if (P.cost == DMPC_COST_DIAG) {
     const float* Qd = P.costp + t * NX;
     const float* q = P.costp + P.N * NX + t * NX;
 #pragma unroll
-    for (int i = 0; i < NX; ++i) s += (Qd[i] * xb[i] + q[i]) * (xq[i] - xb[i]);
+    for (int i = 0; i < NX; ++i)
+      s += ((double)Qd[i] * xb[i] + (double)q[i]) * ((double)xq[i] - (double)xb[i]);
   } else {
     const float* xr = sp_xref<NX>(P);
 #pragma unroll
-    for (int i = 0; i < NX; ++i) s += sp_wx<NX>(P, t, i) * (xb[i] - xr[i]) * (xq[i] - xb[i]);
+    for (int i = 0; i < NX; ++i)
+      s += (double)sp_wx<NX>(P, t, i) * ((double)xb[i] - (double)xr[i]) *
+           ((double)xq[i] - (double)xb[i]);
   }
   return s;
 }
 template <int NX>
-__device__ __forceinline__ float dcost_u1(const Prob& P, int t, int l, float ub, float uq) {
+__device__ __forceinline__ double dcost_u1(const Prob& P, int t, int l, float ub, float uq) {
   if (P.cost == DMPC_COST_DIAG) {
     const float* Rd = P.costp + 2 * P.N * NX + t * P.m;
     const float* r = Rd + P.TM;
-    return (Rd[l] * ub + r[l]) * (uq - ub);
+    return ((double)Rd[l] * ub + (double)r[l]) * ((double)uq - (double)ub);
   }
-  return sp_weight(P, t, P.nw + l) * ub * (uq - ub);
+  return (double)sp_weight(P, t, P.nw + l) * ub * ((double)uq - (double)ub);
 }
 
-// Next state of the true dynamics (used by the rollout and the merit).
+// Next state of the true dynamics, in double (rollout and merit function).
 template <int NX>
-__device__ __forceinline__ void dyn_step(const Prob& P, int t, const float* x, const float* u,
-                                         float* xn) {
+__device__ __forceinline__ void dyn_step(const Prob& P, int t, const double* x, const double* u,
+                                         double* xn) {
   if (P.dyn == DMPC_DYN_LTV) {
     const float* At = P.A + t * NX * NX;
     const float* Bt = P.B + t * NX * P.m;
     const float* ct = P.c + t * NX;
 #pragma unroll
     for (int i = 0; i < NX; ++i) {
-      float s = ct[i];
+      double s = ct[i];
 #pragma unroll
-      for (int j = 0; j < NX; ++j) s = fmaf(At[i * NX + j], x[j], s);
-      for (int l = 0; l < P.m; ++l) s = fmaf(Bt[i * P.m + l], u[l], s);
+      for (int j = 0; j < NX; ++j) s += (double)At[i * NX + j] * x[j];
+      for (int l = 0; l < P.m; ++l) s += (double)Bt[i * P.m + l] * u[l];
       xn[i] = s;
     }
     return;
   }
   if constexpr (NX == 4) {
     if (P.dyn == DMPC_DYN_CARTPOLE) {
-      cartpole_step<float>(P.dynp, x, u, xn);
+      cartpole_step<double>(P.dynp, x, u, xn);
       return;
     }
   }
   if constexpr (NX == 8) {
     if (P.dyn == DMPC_DYN_BICYCLE) {
-      bicycle_step<float>(P.dynp, x, u, xn);
+      bicycle_step<double>(P.dynp, x, u, xn);
       return;
     }
   }
 #pragma unroll
-  for (int i = 0; i < NX; ++i) xn[i] = __builtin_nanf("");
+  for (int i = 0; i < NX; ++i) xn[i] = __builtin_nan("");
 }
 
-// Jacobians of a nonlinear model at (xb, ub) by forward-mode duals; writes
-// A_t [NX][NX], B_t [NX][MU], c_t = phi(xb, ub) - A xb - B ub.
+// Jacobians of a nonlinear model at (xb, ub) by forward-mode duals in double;
+// writes A_t [NX][NX], B_t [NX][MU] rounded to float and the offset
+// c_t = phi(xb, ub) - A xb - B ub with the rounded A, B (so that the affine
+// model passes through phi at the linearisation point), formed in double.
 template <int NX, int MU, typename F>
 __device__ __forceinline__ void linearize_model(F step, const float* par, const float* xb,
                                                 const float* ub, float* A, float* B, float* c) {
   constexpr int K = NX + MU;
-  Dual<K> x[NX], u[MU], xn[NX];
+  typedef Dual<K, double> D;
+  D x[NX], u[MU], xn[NX];
 #pragma unroll
   for (int j = 0; j < NX; ++j) {
-    x[j] = mkconst<K>(xb[j]);
-    x[j].d[j] = 1.f;
+    x[j] = mkconst<K, double>((double)xb[j]);
+    x[j].d[j] = 1.0;
   }
 #pragma unroll
   for (int l = 0; l < MU; ++l) {
-    u[l] = mkconst<K>(ub[l]);
-    u[l].d[NX + l] = 1.f;
+    u[l] = mkconst<K, double>((double)ub[l]);
+    u[l].d[NX + l] = 1.0;
   }
   step(par, x, u, xn);
 #pragma unroll
   for (int i = 0; i < NX; ++i) {
-    float s = xn[i].v;
+    double s = xn[i].v;
 #pragma unroll
     for (int j = 0; j < NX; ++j) {
-      A[i * NX + j] = xn[i].d[j];
-      s -= xn[i].d[j] * xb[j];
+      const float a = (float)xn[i].d[j];
+      A[i * NX + j] = a;
+      s -= (double)a * (double)xb[j];
     }
 #pragma unroll
     for (int l = 0; l < MU; ++l) {
-      B[i * MU + l] = xn[i].d[NX + l];
-      s -= xn[i].d[NX + l] * ub[l];
+      const float b = (float)xn[i].d[NX + l];
+      B[i * MU + l] = b;
+      s -= (double)b * (double)ub[l];
     }
-    c[i] = s;
+    c[i] = (float)s;
   }
 }
 
@@ -654,20 +695,21 @@ __device__ __forceinline__ double row_dot64(const double* coef, const float* hi,
 struct Carve {
   int xbar, ubar, xp, up, lam, w0, w1, w2, piv, red, ls;
 };
+__device__ __forceinline__ int a4(int v) { return (v + 3) & ~3; }
 __device__ __forceinline__ Carve carve(int R, int TM, int N, int nx, int bt) {
   Carve C;
   int o = 0;
-  C.xbar = o;  o += R;       // forward: iterate;     backward: x~
-  C.ubar = o;  o += TM;      //                                   u~
-  C.xp = o;    o += R;       // QP solution
-  C.up = o;    o += TM;
-  C.lam = o;   o += R;       // backward: forward multipliers
-  C.w0 = o;    o += R + 2 * nx;
-  C.w1 = o;    o += R + 2 * nx;
-  C.w2 = o;    o += R + 2 * nx;  // low part of a double-float vector in w0
+  C.xbar = o;  o += a4(R);            // forward: iterate;     backward: x~
+  C.ubar = o;  o += a4(TM);           //                                   u~
+  C.xp = o;    o += a4(R);            // QP solution
+  C.up = o;    o += a4(TM);
+  C.lam = o;   o += a4(R);            // backward: forward multipliers
+  C.w0 = o;    o += a4(R + 2 * nx);
+  C.w1 = o;    o += a4(R + 2 * nx);
+  C.w2 = o;    o += a4(R + 2 * nx);   // low part of a double-float vector in w0
   C.piv = o;   o += 4 * bt;
   C.red = o;   o += 128;
-  C.ls = o;    o += 2 * (kMaxAlphas + 1) * N + 2 * (kMaxAlphas + 1) + 2;
+  C.ls = o;    o += 4 * (kMaxAlphas + 1) * N + 4 * (kMaxAlphas + 1);   // doubles
   return C;
 }
 
@@ -998,11 +1040,18 @@ __device__ __noinline__ void fwd_begin(const ProbRec* rec, const float* data, co
     }
   } else {
     if (tid == 0) {
-      for (int t = 0; t < T; ++t) {
-        float xn[NX];
-        dyn_step<NX>(P, t, xbar + t * NX, ubar + t * m, xn);
+      double xc[NX], xn[NX], uc[2];
 #pragma unroll
-        for (int i = 0; i < NX; ++i) xbar[(t + 1) * NX + i] = xn[i];
+      for (int i = 0; i < NX; ++i) xc[i] = xbar[i];
+      for (int t = 0; t < T; ++t) {
+        uc[0] = ubar[t * m];
+        uc[1] = (m > 1) ? ubar[t * m + 1] : 0.f;
+        dyn_step<NX>(P, t, xc, uc, xn);
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+          xbar[(t + 1) * NX + i] = (float)xn[i];
+          xc[i] = (double)(float)xn[i];
+        }
       }
     }
     __syncthreads();
@@ -1148,49 +1197,52 @@ __device__ __noinline__ int fwd_recover_ls(const ProbRec* rec, const float* data
   }
   __syncthreads();
   // Task (ai, t): stage t at the current point (ai = 0) or at candidate
-  // alphas[ai-1]; its cost and dynamics defect go to LDS, one wave then
-  // reduces each candidate in a fixed order.
+  // alphas[ai-1]; its cost and dynamics defect (double) go to LDS, one wave
+  // then reduces each candidate in a fixed order.
   const int na = lp.n;
   const int ntask = (na + 1) * N;
-  float* tc = smem + C.ls;
-  float* td = tc + (kMaxAlphas + 1) * N;
-  float* res = td + (kMaxAlphas + 1) * N;
-  float dn = 0.f;
+  double* tc = (double*)(smem + C.ls);
+  double* td = tc + (kMaxAlphas + 1) * N;
+  double* res = td + (kMaxAlphas + 1) * N;
+  double dn = 0.0;
   for (int task = tid; task < ntask; task += BT) {
     const int ai = task / N, t = task - ai * N;
-    const float al = (ai == 0) ? 0.f : lp.alphas[ai - 1];
-    float xa[NX];
+    const double al = (ai == 0) ? 0.0 : (double)lp.alphas[ai - 1];
+    double xa[NX];
 #pragma unroll
-    for (int j = 0; j < NX; ++j) xa[j] = fmaf(al, xp[t * NX + j] - xbar[t * NX + j], xbar[t * NX + j]);
-    float cst = cost_x<NX>(P, t, xa);
-    float dfc = 0.f;
+    for (int j = 0; j < NX; ++j)
+      xa[j] = (double)xbar[t * NX + j] + al * ((double)xp[t * NX + j] - (double)xbar[t * NX + j]);
+    double cst = cost_x<NX>(P, t, xa);
+    double dfc = 0.0;
     if (t < T) {
       const float* ub = ubar + t * m;
       const float* uq = up + t * m;
-      for (int l = 0; l < m; ++l) cst += cost_u1<NX>(P, t, l, fmaf(al, uq[l] - ub[l], ub[l]));
-      float xn[NX];
+      for (int l = 0; l < m; ++l)
+        cst += cost_u1<NX>(P, t, l, (double)ub[l] + al * ((double)uq[l] - (double)ub[l]));
+      double xn[NX];
       if (P.dyn == DMPC_DYN_LTV) {
         const float* At = P.A + t * NX * NX;
         const float* Bt = P.B + t * NX * m;
 #pragma unroll
         for (int i = 0; i < NX; ++i) {
-          float sacc = P.c[t * NX + i];
+          double sacc = P.c[t * NX + i];
 #pragma unroll
-          for (int j = 0; j < NX; ++j) sacc = fmaf(At[i * NX + j], xa[j], sacc);
-          for (int l = 0; l < m; ++l) sacc = fmaf(Bt[i * m + l], fmaf(al, uq[l] - ub[l], ub[l]), sacc);
+          for (int j = 0; j < NX; ++j) sacc += (double)At[i * NX + j] * xa[j];
+          for (int l = 0; l < m; ++l)
+            sacc += (double)Bt[i * m + l] * ((double)ub[l] + al * ((double)uq[l] - (double)ub[l]));
           xn[i] = sacc;
         }
       } else {
-        float ua[2];   // nonlinear models have at most two inputs
-        ua[0] = fmaf(al, uq[0] - ub[0], ub[0]);
-        ua[1] = (m > 1) ? fmaf(al, uq[1] - ub[1], ub[1]) : 0.f;
+        double ua[2];   // nonlinear models have at most two inputs
+        ua[0] = (double)ub[0] + al * ((double)uq[0] - (double)ub[0]);
+        ua[1] = (m > 1) ? (double)ub[1] + al * ((double)uq[1] - (double)ub[1]) : 0.0;
         dyn_step<NX>(P, t, xa, ua, xn);
       }
 #pragma unroll
       for (int j = 0; j < NX; ++j) {
-        const float xa1 =
-            fmaf(al, xp[(t + 1) * NX + j] - xbar[(t + 1) * NX + j], xbar[(t + 1) * NX + j]);
-        dfc += fabsf(xa1 - xn[j]);
+        const double xa1 = (double)xbar[(t + 1) * NX + j] +
+                           al * ((double)xp[(t + 1) * NX + j] - (double)xbar[(t + 1) * NX + j]);
+        dfc += fabs(xa1 - xn[j]);
       }
     }
     tc[task] = cst;
@@ -1205,13 +1257,13 @@ __device__ __noinline__ int fwd_recover_ls(const ProbRec* rec, const float* data
   {
     const int lane = tid & 63;
     for (int ai = tid >> 6; ai <= na; ai += nwv) {
-      float c0 = 0.f, d0 = 0.f;
+      double c0 = 0.0, d0 = 0.0;
       for (int t = lane; t < N; t += 64) {
         c0 += tc[ai * N + t];
         d0 += td[ai * N + t];
       }
-      c0 = wave_sum(c0);
-      d0 = wave_sum(d0);
+      c0 = wave_sum_d(c0);
+      d0 = wave_sum_d(d0);
       if (lane == 0) {
         res[ai] = c0;
         res[kMaxAlphas + 1 + ai] = d0;
@@ -1219,16 +1271,16 @@ __device__ __noinline__ int fwd_recover_ls(const ProbRec* rec, const float* data
     }
   }
   __syncthreads();
-  const float num = block_sum(dn, smem + C.red, nwv);
-  const float fl1 = res[kMaxAlphas + 1];
-  const float mu = fmaxf(num, 0.f) / fmaxf(0.5f * fl1, 1e-30f);   // Eq. linesearch:penalty
-  const float Dmu = num - mu * fl1;                                // Eq. linesearch:descent
-  const float phi0 = res[0] + mu * fl1;                            // Eq. linesearch:merit
+  const double num = block_sum_d(dn, (double*)(smem + C.red), nwv);
+  const double fl1 = res[kMaxAlphas + 1];
+  const double mu = fmax(num, 0.0) / fmax(0.5 * fl1, 1e-30);      // Eq. linesearch:penalty
+  const double Dmu = num - mu * fl1;                               // Eq. linesearch:descent
+  const double phi0 = res[0] + mu * fl1;                           // Eq. linesearch:merit
   int sel = na - 1;                                                // min of the candidates
   bool passed = false;
   for (int ai = 1; ai <= na && !passed; ++ai) {
-    const float al = lp.alphas[ai - 1];
-    const float dphi = (res[ai] + mu * res[kMaxAlphas + 1 + ai]) - phi0 - lp.eta * al * Dmu;
+    const double al = lp.alphas[ai - 1];
+    const double dphi = (res[ai] + mu * res[kMaxAlphas + 1 + ai]) - phi0 - (double)lp.eta * al * Dmu;
     if (dphi < 0.f) {   // Eq. linesearch:decrease
       sel = ai - 1;
       passed = true;
@@ -1619,9 +1671,9 @@ __global__ __launch_bounds__(MAXBT) void forward_kernel(KArgs a) {
       }
     }
     flags |= fwd_finish<NX>(rec, a.data, a.sol, a.ws);
-    const int anyf = __syncthreads_or(flags);
+    // every flag source is uniform over the workgroup (block reductions)
     if (tid == 0) {
-      a.status[rec->index] = flags | anyf;
+      a.status[rec->index] = flags;
       a.info[4 * rec->index + 0] = pcg_total;
       a.info[4 * rec->index + 2] = sel;
       a.info[4 * rec->index + 3] = a.sqp_iters;
@@ -1660,9 +1712,8 @@ __global__ __launch_bounds__(MAXBT) void backward_kernel(KArgs a) {
     publish<SLOTS>(sh.w2, lo, P.R, NX);
     __syncthreads();
     bwd_finish<NX>(rec, a.data, a.ws, a.dl, a.adj, a.grad);
-    const int anyf = __syncthreads_or(flags);
     if (tid == 0) {
-      a.status[rec->index] |= (flags | anyf);
+      a.status[rec->index] |= flags;
       a.info[4 * rec->index + 1] = its;
     }
     __syncthreads();

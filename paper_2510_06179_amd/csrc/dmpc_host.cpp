@@ -195,7 +195,7 @@ void dmpc_default_opts(dmpc_opts* o) {
   o->ls_eta = 0.4f;
   o->init = DMPC_INIT_GIVEN;
   o->bwd_pcg_tol = 1e-6f;
-  o->refine_steps = 1;
+  o->refine_steps = 3;
   o->refine_tol = 1e-2f;
   o->kkt_tol = 1e-6f;
 }

@@ -91,15 +91,17 @@ DMPC_HD inline int64_t sol_block_len(int T, int nx, int nu) {
 }
 
 // LDS floats a workgroup needs for a problem (forward and backward kernels).
-// (must match the device-side carve in dmpc_device.h)
+// (must match the device-side carve in dmpc_device.h: every region rounded up
+// to 4 floats)
+DMPC_HD inline int64_t a4h(int64_t v) { return (v + 3) / 4 * 4; }
 DMPC_HD inline int64_t lds_floats(int T, int nx, int nu, int bt) {
   const int64_t N = T + 1, R = N * nx, TM = (int64_t)T * nu;
-  return 3 * R + 2 * TM              // xbar/ubar/xp/up/lam (fwd) or xt/ut/xp/up/lam (bwd)
-         + 3 * (R + 2 * nx)          // three padded windows
-         + 4 * (int64_t)bt           // Gauss-Jordan pivot rows, double buffered
-         + 2 * 64                    // scalar reductions
-         + 2 * (kMaxAlphas + 1) * N  // line-search stage costs and defects
-         + 2 * (kMaxAlphas + 1) + 2; // per-candidate sums
+  return 3 * a4h(R) + 2 * a4h(TM)        // iterate / QP solution / multipliers
+         + 3 * a4h(R + 2 * nx)           // three padded windows
+         + 4 * (int64_t)bt               // Gauss-Jordan pivot rows, double buffered
+         + 128                           // reductions
+         + 4 * (kMaxAlphas + 1) * N      // line-search stage costs and defects (double)
+         + 4 * (kMaxAlphas + 1);         // per-candidate sums (double)
 }
 
 // Launch-time arguments of the kernels.
