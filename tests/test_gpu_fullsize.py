@@ -1,0 +1,105 @@
+"""Parity at the benchmark sizes, in the launch configuration bench.py times:
+the whole batch runs on the GPU and a sample of problems is checked one by
+one against the FP64 oracle (KKT residual of the last QP, gradients)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2510_06179_amd import _lib, batch
+from paper_2510_06179_amd import workloads as W
+from _parity import REL_TOL, gpu_only, gpu_solve, oracle_kkt_of_gpu_qp, rel_err, saved_qp
+
+pytestmark = [pytest.mark.gpu, gpu_only]
+
+BAD = _lib.PROB_NONPD | _lib.PROB_NONFINITE
+
+
+def _dl(s, cots):
+    return torch.from_numpy(batch.sol_like(
+        s.packed, [(c["gx"], c["gu"], c["glam"]) for c in cots])).to(s.device)
+
+
+def test_cartpole_full_batch_sampled():
+    # the benchmark workload: 1024 cart-pole OCPs, 10 SQP iterations, fwd + bwd
+    probs = W.cartpole_batch(0, batch=1024)
+    cots = W.loss_cotangents(probs, seed=0)
+    s, res, status, info = gpu_solve(probs, sqp_iters=10, pcg_tol=1e-6, bwd_pcg_tol=1e-6)
+    assert not np.any(status & BAD)
+    adj, grad = s.solve_backward(_dl(s, cots))
+    torch.cuda.synchronize()
+    grad = grad.cpu().numpy()
+    for k in np.random.default_rng(0).choice(1024, size=8, replace=False):
+        p = probs[k]
+        kkt, bound, sq, qpd = oracle_kkt_of_gpu_qp(p, s, k)
+        assert kkt <= bound, (k, kkt, bound)
+        sol = oracle.qp.solve_qp(qpd, p["x0"])
+        g_o, _ = oracle.backward.vjp(p, sq["xlin"], sq["ulin"], qpd, sol, cots[k]["gx"],
+                                     cots[k]["gu"])
+        g = batch.split_grad(s.packed, grad, k)
+        for key in ("Qd", "q", "Rd", "r", "x0"):
+            assert rel_err(g[key], g_o[key]) <= REL_TOL, (k, key)
+
+
+def test_uneven_ltv_full_batch_sampled():
+    # 4096 LTV OCPs of uneven horizon and size in one call, 8 SQP iterations
+    probs = W.ltv_uneven_batch(0, batch=4096)
+    s, res, status, info = gpu_solve(probs, sqp_iters=8, pcg_tol=1e-6)
+    assert not np.any(status & BAD)
+    # one problem of every (T, nx) class
+    seen = {}
+    for k, p in enumerate(probs):
+        seen.setdefault((p["T"], p["nx"]), k)
+    for (T, nx), k in sorted(seen.items()):
+        p = probs[k]
+        kkt, bound, sq, qpd = oracle_kkt_of_gpu_qp(p, s, k)
+        assert kkt <= bound, (T, nx, k, kkt, bound)
+
+
+def test_bicycle_per_iteration_parity():
+    probs = W.bicycle_batch(0, batch=8)
+    s, res, status, info = gpu_solve(probs, sqp_iters=1, pcg_tol=1e-6)
+    cur = [dict(p) for p in probs]
+    for it in range(3):
+        assert not np.any(status & BAD)
+        for k, p in enumerate(probs):
+            x, u, lam = res[k]
+            q = cur[k]
+            xb, ub, _ = oracle.sqp.initial_guess(q)
+            xo, uo, lo, h = oracle.sqp.sqp_step(q, xb, ub)
+            kkt, bound, sq, _ = oracle_kkt_of_gpu_qp(q, s, k)
+            assert kkt <= bound, (it, k, kkt, bound)
+            a_gpu = int(info[k, 2])
+            if a_gpu != h["alpha_idx"]:
+                d = h["ls"]["dphi"]
+                scale = 1e-6 * (abs(h["ls"]["phi0"]) + 1.0)
+                assert abs(d[a_gpu]) <= scale or abs(d[h["alpha_idx"]]) <= scale, (it, k)
+            else:
+                assert rel_err(x, xo) <= REL_TOL and rel_err(u, uo) <= REL_TOL, (it, k)
+            q = dict(q)
+            q["xbar"], q["ubar"], q["lam"], q["init"] = x, u, lam, "given"
+            cur[k] = q
+        s, res, status, info = gpu_solve(cur, sqp_iters=1, pcg_tol=1e-6, init="given")
+
+
+def test_bicycle_theta_gradients():
+    # differentiation workload: softplus cost weights theta in R^32, 10 SQP
+    # iterations, adjoint to dtheta, dxref, dx0
+    probs = W.bicycle_batch(1, batch=16)
+    cots = W.loss_cotangents(probs, seed=1)
+    s, res, status, info = gpu_solve(probs, sqp_iters=10, pcg_tol=1e-6, bwd_pcg_tol=1e-6)
+    assert not np.any(status & BAD)
+    adj, grad = s.solve_backward(_dl(s, cots))
+    torch.cuda.synchronize()
+    grad = grad.cpu().numpy()
+    for k in range(0, 16, 2):
+        p = probs[k]
+        sq = saved_qp(s, k)
+        qpd = oracle.qp.qp_data(p, sq["xlin"], sq["ulin"])
+        sol = oracle.qp.solve_qp(qpd, p["x0"])
+        g_o, _ = oracle.backward.vjp(p, sq["xlin"], sq["ulin"], qpd, sol, cots[k]["gx"],
+                                     cots[k]["gu"])
+        g = batch.split_grad(s.packed, grad, k)
+        for key in ("theta", "xref", "x0"):
+            assert rel_err(g[key], g_o[key]) <= REL_TOL, (k, key, rel_err(g[key], g_o[key]))
+        assert np.all(g["wscale"] == 0) and np.all(g["wfix"] == 0)
