@@ -97,6 +97,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--plain-sample", type=int, default=64)
+    ap.add_argument("--block-threads", type=int, default=0,
+                    help="force the threads per workgroup (0: the library's choice)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); "
@@ -111,7 +113,8 @@ def main():
 
     probs = W.cartpole_batch(0, batch=B, T=T)
     cots = W.loss_cotangents(probs, seed=0)
-    s = BatchSolver(probs, sqp_iters=SQP, pcg_tol=PCG_TOL, bwd_pcg_tol=PCG_TOL)
+    s = BatchSolver(probs, sqp_iters=SQP, pcg_tol=PCG_TOL, bwd_pcg_tol=PCG_TOL,
+                    block_threads=args.block_threads)
     dl = torch.from_numpy(batch.sol_like(s.packed, [(c["gx"], c["gu"], c["glam"]) for c in cots])).to(s.device)
     sol = s.sol0.clone()
     adj = torch.zeros_like(sol)
@@ -158,8 +161,9 @@ def main():
     achieved = fwd_flops / fwd_s
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": FP32_VECTOR_PEAK / 1e12,
             "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK, "traffic": None,
-            "kernel": "forward_kernel<4,1,256,reg> (fused SQP: assembly, preconditioner, PCG, "
-                      "recovery, line search)",
+            "kernel": "forward_kernel (fused SQP: QP data, Schur assembly, preconditioner, "
+                      "PCG with double-residual refinement, recovery, line search)",
+            "launch": s.describe(),
             "kernel_ms": float(np.mean(fwd_ms)), "backward_kernel_ms": float(np.mean(bwd_ms))}
 
     # plain one-problem-per-launch GPU form on a sample of the same batch

@@ -202,6 +202,11 @@ dmpc_status dmpc_solve_backward_one(dmpc_plan* plan, int32_t index, const float*
  * Used to inspect the last QP (Alg. sqp returns the QP matrices). */
 dmpc_status dmpc_workspace_offsets(const dmpc_plan* plan, int32_t index, int64_t* out);
 
+/* Writes a NUL-terminated JSON description of the plan's launch groups (state
+ * size, rows per thread, threads per workgroup, register residency, problem
+ * count) into the host buffer buf of size len (truncated if too small). */
+dmpc_status dmpc_plan_describe(const dmpc_plan* plan, char* buf, size_t len);
+
 /* Human-readable name of a return code (static string). */
 const char* dmpc_status_string(dmpc_status s);
 

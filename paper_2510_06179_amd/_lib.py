@@ -29,7 +29,7 @@ EXPORTED = (
     "dmpc_default_opts", "dmpc_create", "dmpc_destroy", "dmpc_validate", "dmpc_workspace_size",
     "dmpc_plan_create", "dmpc_plan_workspace_size", "dmpc_plan_destroy", "dmpc_solve",
     "dmpc_solve_backward", "dmpc_solve_one", "dmpc_solve_backward_one", "dmpc_status_string",
-    "dmpc_version", "dmpc_workspace_offsets",
+    "dmpc_version", "dmpc_workspace_offsets", "dmpc_plan_describe",
 )
 
 
@@ -97,6 +97,7 @@ def load():
         "dmpc_status_string": (ctypes.c_char_p, [i32]),
         "dmpc_version": (i32, []),
         "dmpc_workspace_offsets": (i32, [vp, i32, P(i64)]),
+        "dmpc_plan_describe": (i32, [vp, ctypes.c_char_p, ctypes.c_size_t]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

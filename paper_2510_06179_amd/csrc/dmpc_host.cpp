@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <string>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -112,41 +114,46 @@ dmpc_status check_problem(const dmpc_problem& p, int64_t data_len, int64_t sol_l
   return DMPC_OK;
 }
 
-// Kernel mapping of one problem: rows R = (T+1)*nx spread over the threads.
+// Kernel mapping of one problem: its R = (T+1)*nx rows are spread over the
+// threads of a workgroup, `slots` rows per thread.  Among the instantiated
+// variants that hold the rows, the one with the fewest estimated instructions
+// per PCG iteration is taken: every wave repeats the per-iteration overhead
+// (reductions, divide, barriers), every row costs its two row products;
+// workspace-resident rows cost three times a register-resident one.
+struct Variant {
+  int slots, maxbt, reg;
+};
+const Variant kVariants[] = {
+    {1, 64, 1},  {2, 64, 1},  {4, 64, 1},  {8, 64, 1},  {1, 128, 1}, {2, 128, 1}, {4, 128, 1},
+    {8, 128, 1}, {1, 256, 1}, {2, 256, 1}, {4, 256, 1}, {1, 512, 1}, {2, 512, 1}, {1, 1024, 1},
+    {4, 256, 0}, {8, 256, 0}, {8, 512, 0},
+};
+
 bool choose_cfg(const dmpc_problem& p, int force_bt, LaunchCfg* c) {
   const int64_t R = (int64_t)(p.T + 1) * p.nx;
-  c->nx = p.nx;
-  auto rup = [](int64_t v) { return (int)((v + 63) / 64 * 64); };
-  if (force_bt > 0) {
-    const int bt = force_bt;
-    struct Opt { int slots, maxbt, reg; };
-    const Opt opts[] = {{1, 256, 1}, {1, 512, 1}, {1, 1024, 1}, {2, 256, 1},
-                        {4, 256, 0}, {8, 256, 0}, {8, 512, 0}};
-    for (const Opt& o : opts) {
-      if (bt <= o.maxbt && R <= (int64_t)o.slots * bt) {
-        c->slots = o.slots;
-        c->maxbt = o.maxbt;
-        c->reg = o.reg;
-        c->bt = bt;
-        return true;
-      }
+  const double per_row = 6.0 * p.nx + 10.0, per_wave = 100.0;
+  double best = 1e300;
+  bool found = false;
+  for (const Variant& v : kVariants) {
+    if (!kernel_available(p.nx, v.slots, v.maxbt, v.reg)) continue;
+    int bt;
+    if (force_bt > 0) {
+      bt = force_bt;
+      if (bt > v.maxbt || R > (int64_t)v.slots * bt) continue;
+    } else {
+      bt = (int)((R + 64LL * v.slots - 1) / (64LL * v.slots) * 64);
+      if (bt > v.maxbt) continue;
     }
-    return false;
+    const int waves = bt / 64;
+    const double cost =
+        waves * (per_wave + v.slots * per_row * (v.reg ? 1.0 : 3.0)) + 1e-3 * v.maxbt;
+    if (cost < best) {
+      best = cost;
+      *c = LaunchCfg{p.nx, v.slots, v.maxbt, v.reg, bt, 0, 0};
+      found = true;
+    }
   }
-  if (R <= 256) {
-    *c = LaunchCfg{p.nx, 1, 256, 1, std::max(64, rup(R)), 0, 0};
-  } else if (R <= 512) {
-    *c = LaunchCfg{p.nx, 1, 512, 1, rup(R), 0, 0};
-  } else if (R <= 1024) {
-    *c = LaunchCfg{p.nx, 4, 256, 0, rup((R + 3) / 4), 0, 0};
-  } else if (R <= 2048) {
-    *c = LaunchCfg{p.nx, 8, 256, 0, rup((R + 7) / 8), 0, 0};
-  } else if (R <= 4096) {
-    *c = LaunchCfg{p.nx, 8, 512, 0, rup((R + 7) / 8), 0, 0};
-  } else {
-    return false;
-  }
-  return true;
+  return found;
 }
 
 KArgs make_args(const dmpc_plan* pl, const float* data, float* sol, void* ws, const float* dl,
@@ -396,6 +403,24 @@ dmpc_status dmpc_workspace_offsets(const dmpc_plan* plan, int32_t index, int64_t
   const WsLayout L = ws_layout(r.T, r.nx, r.nu, r.dyn);
   const int64_t v[7] = {L.xlin, L.ulin, L.xp, L.up, L.lam, L.Qd, L.Rd};
   for (int i = 0; i < 7; ++i) out[i] = r.ws_off + v[i];
+  return DMPC_OK;
+}
+
+dmpc_status dmpc_plan_describe(const dmpc_plan* plan, char* buf, size_t len) {
+  if (!plan || !buf || len == 0) return DMPC_ERR_INVALID_ARG;
+  std::string s = "[";
+  for (size_t g = 0; g < plan->groups.size(); ++g) {
+    const LaunchCfg& c = plan->groups[g].cfg;
+    char tmp[192];
+    std::snprintf(tmp, sizeof(tmp),
+                  "%s{\"nx\": %d, \"slots\": %d, \"block_threads\": %d, \"launch_bound\": %d, "
+                  "\"register_rows\": %d, \"problems\": %d, \"lds_bytes\": %zu}",
+                  g ? ", " : "", c.nx, c.slots, c.bt, c.maxbt, c.reg, plan->groups[g].count,
+                  c.lds_bytes);
+    s += tmp;
+  }
+  s += "]";
+  std::snprintf(buf, len, "%s", s.c_str());
   return DMPC_OK;
 }
 

@@ -6,9 +6,11 @@ namespace dmpc {
 #define DMPC_K(NX, SL, MB, RG) \
   {NX, SL, MB, RG, forward_kernel<NX, SL, MB, (RG != 0)>, backward_kernel<NX, SL, MB, (RG != 0)>}
 
-// (rows per thread, launch bound, register-resident rows)
+// (rows per thread, launch bound, rows of S^ and Phi^-1 held in registers)
 static const KEntry kEntries[] = {
-    DMPC_K(16, 1, 256, 1), DMPC_K(16, 2, 256, 1), DMPC_K(16, 1, 512, 1), DMPC_K(16, 1, 1024, 1),
+    DMPC_K(16, 1, 64, 1), DMPC_K(16, 2, 64, 1), DMPC_K(16, 1, 128, 1), DMPC_K(16, 2, 128, 1),
+    DMPC_K(16, 1, 256, 1), DMPC_K(16, 2, 256, 1), DMPC_K(16, 1, 512, 1), DMPC_K(16, 2, 512, 1),
+    DMPC_K(16, 1, 1024, 1),
     DMPC_K(16, 4, 256, 0), DMPC_K(16, 8, 256, 0), DMPC_K(16, 8, 512, 0),
 };
 

@@ -118,6 +118,13 @@ class BatchSolver:
         keys = ["xlin", "ulin", "xp", "up", "lam", "Qd", "Rd"]
         return {k: ws[o:o + s[0] * s[1]].view(*s) for k, o, s in zip(keys, out, shp)}
 
+    def describe(self):
+        """Launch groups of the plan (list of dicts)."""
+        import json
+        buf = ctypes.create_string_buffer(8192)
+        _lib.check(self.lib.dmpc_plan_describe(self.plan, buf, len(buf)), "describe")
+        return json.loads(buf.value.decode())
+
     def close(self):
         if getattr(self, "plan", None):
             self.lib.dmpc_plan_destroy(self.plan)
