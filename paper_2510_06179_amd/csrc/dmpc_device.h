@@ -290,6 +290,9 @@ struct Prob {
   const float* A;      // linearised dynamics (arena for LTV, workspace otherwise)
   const float* B;
   const float* c;
+  const double* Ad;    // the same in double (nonlinear models; null for LTV)
+  const double* Bd;
+  const double* cd;
   float* W;            // problem workspace base
   WsLayout L;
 };
@@ -315,12 +318,40 @@ __device__ __forceinline__ Prob make_prob(const ProbRec& pr, const float* data, 
     P.A = P.dynp;
     P.B = P.A + pr.T * NX * NX;
     P.c = P.B + pr.T * NX * pr.nu;
+    P.Ad = P.Bd = P.cd = nullptr;
   } else {
     P.A = P.W + P.L.A;
     P.B = P.W + P.L.B;
     P.c = P.W + P.L.c;
+    P.Ad = (const double*)(P.W + P.L.Ad);
+    P.Bd = (const double*)(P.W + P.L.Bd);
+    P.cd = (const double*)(P.W + P.L.cd);
   }
   return P;
+}
+
+// Linearised dynamics entries in precision R: the double copy where one
+// exists (nonlinear models), else the float data (exact for LTV inputs).
+template <typename R>
+__device__ __forceinline__ R ldA(const Prob& P, int idx) {
+  if constexpr (sizeof(R) == sizeof(double)) {
+    if (P.Ad) return P.Ad[idx];
+  }
+  return (R)P.A[idx];
+}
+template <typename R>
+__device__ __forceinline__ R ldB(const Prob& P, int idx) {
+  if constexpr (sizeof(R) == sizeof(double)) {
+    if (P.Bd) return P.Bd[idx];
+  }
+  return (R)P.B[idx];
+}
+template <typename R>
+__device__ __forceinline__ R ldc(const Prob& P, int idx) {
+  if constexpr (sizeof(R) == sizeof(double)) {
+    if (P.cd) return P.cd[idx];
+  }
+  return (R)P.c[idx];
 }
 
 __device__ __forceinline__ float softplusf(float v) {
@@ -453,7 +484,8 @@ __device__ __forceinline__ void dyn_step(const Prob& P, int t, const double* x, 
 // model passes through phi at the linearisation point), formed in double.
 template <int NX, int MU, typename F>
 __device__ __forceinline__ void linearize_model(F step, const float* par, const float* xb,
-                                                const float* ub, float* A, float* B, float* c) {
+                                                const float* ub, float* A, float* B, float* c,
+                                                double* Ad, double* Bd, double* cd) {
   constexpr int K = NX + MU;
   typedef Dual<K, double> D;
   D x[NX], u[MU], xn[NX];
@@ -473,17 +505,18 @@ __device__ __forceinline__ void linearize_model(F step, const float* par, const 
     double s = xn[i].v;
 #pragma unroll
     for (int j = 0; j < NX; ++j) {
-      const float a = (float)xn[i].d[j];
-      A[i * NX + j] = a;
-      s -= (double)a * (double)xb[j];
+      A[i * NX + j] = (float)xn[i].d[j];
+      Ad[i * NX + j] = xn[i].d[j];
+      s -= xn[i].d[j] * (double)xb[j];
     }
 #pragma unroll
     for (int l = 0; l < MU; ++l) {
-      const float b = (float)xn[i].d[NX + l];
-      B[i * MU + l] = b;
-      s -= (double)b * (double)ub[l];
+      B[i * MU + l] = (float)xn[i].d[NX + l];
+      Bd[i * MU + l] = xn[i].d[NX + l];
+      s -= xn[i].d[NX + l] * (double)ub[l];
     }
     c[i] = (float)s;
+    cd[i] = s;
   }
 }
 
@@ -552,16 +585,20 @@ __device__ __forceinline__ void form_qp(const Prob& P, const float* xbar, const 
     float* A = W + P.L.A;
     float* B = W + P.L.B;
     float* c = W + P.L.c;
+    double* Ad = (double*)(W + P.L.Ad);
+    double* Bd = (double*)(W + P.L.Bd);
+    double* cd = (double*)(W + P.L.cd);
     for (int t = tid; t < P.T; t += BT) {
       if constexpr (NX == 4) {
         if (P.dyn == DMPC_DYN_CARTPOLE)
           linearize_model<4, 1>(CartpoleStepF<4>(), P.dynp, xbar + t * 4, ubar + t, A + t * 16,
-                                B + t * 4, c + t * 4);
+                                B + t * 4, c + t * 4, Ad + t * 16, Bd + t * 4, cd + t * 4);
       }
       if constexpr (NX == 8) {
         if (P.dyn == DMPC_DYN_BICYCLE)
           linearize_model<8, 2>(BicycleStepF<8>(), P.dynp, xbar + t * 8, ubar + t * 2,
-                                A + t * 64, B + t * 16, c + t * 8);
+                                A + t * 64, B + t * 16, c + t * 8, Ad + t * 64, Bd + t * 16,
+                                cd + t * 8);
       }
     }
   }
@@ -605,13 +642,12 @@ __device__ __forceinline__ void schur_row(const Prob& P, int t, int i, R* S, R& 
     g = -((R)P.x0[i] + (R)q[i] * d);
   } else {
     const int tt = t - 1;
-    const float* At = P.A + tt * NX * NX;
-    const float* Bt = P.B + tt * NX * m;
+    const int a0 = tt * NX * NX, b0 = tt * NX * m;
     R ai[NX];
     R gs = R(0);
 #pragma unroll
     for (int j = 0; j < NX; ++j) {
-      ai[j] = (R)At[i * NX + j] * rinv<R>(Qd, iQ, tt * NX + j);
+      ai[j] = ldA<R>(P, a0 + i * NX + j) * rinv<R>(Qd, iQ, tt * NX + j);
       gs += ai[j] * (R)q[tt * NX + j];
       S[j] = -ai[j];
     }
@@ -619,25 +655,25 @@ __device__ __forceinline__ void schur_row(const Prob& P, int t, int i, R* S, R& 
     for (int k = 0; k < NX; ++k) {
       R acc = R(0);
 #pragma unroll
-      for (int j = 0; j < NX; ++j) acc += ai[j] * (R)At[k * NX + j];
+      for (int j = 0; j < NX; ++j) acc += ai[j] * ldA<R>(P, a0 + k * NX + j);
       S[NX + k] = acc;
     }
     for (int l = 0; l < m; ++l) {
-      const R bi = (R)Bt[i * m + l] * rinv<R>(Rd, iR, tt * m + l);
+      const R bi = ldB<R>(P, b0 + i * m + l) * rinv<R>(Rd, iR, tt * m + l);
       gs += bi * (R)r[tt * m + l];
 #pragma unroll
-      for (int k = 0; k < NX; ++k) S[NX + k] += bi * (R)Bt[k * m + l];
+      for (int k = 0; k < NX; ++k) S[NX + k] += bi * ldB<R>(P, b0 + k * m + l);
     }
     const R dq = rinv<R>(Qd, iQ, t * NX + i);
 #pragma unroll
     for (int k = 0; k < NX; ++k) S[NX + k] += (k == i) ? dq : R(0);
-    g = -((R)P.c[tt * NX + i] - gs + (R)q[t * NX + i] * dq);
+    g = -(ldc<R>(P, tt * NX + i) - gs + (R)q[t * NX + i] * dq);
   }
   if (t < P.T) {
-    const float* At = P.A + t * NX * NX;
+    const int a0 = t * NX * NX;
     const R d = rinv<R>(Qd, iQ, t * NX + i);
 #pragma unroll
-    for (int k = 0; k < NX; ++k) S[2 * NX + k] = -(R)At[k * NX + i] * d;
+    for (int k = 0; k < NX; ++k) S[2 * NX + k] = -ldA<R>(P, a0 + k * NX + i) * d;
   }
 }
 
@@ -655,11 +691,12 @@ __device__ __forceinline__ R adjoint_rhs_row(const Prob& P, int t, int i, const 
   R v = (R)dlx[rho] * rinv<R>(Qd, iQ, rho) - (R)dll[rho];
   if (t >= 1) {
     const int tt = t - 1;
-    const float* At = P.A + tt * NX * NX + i * NX;
-    const float* Bt = P.B + tt * NX * m + i * m;
+    const int a0 = tt * NX * NX + i * NX, b0 = tt * NX * m + i * m;
 #pragma unroll
-    for (int j = 0; j < NX; ++j) v -= (R)At[j] * ((R)dlx[tt * NX + j] * rinv<R>(Qd, iQ, tt * NX + j));
-    for (int l = 0; l < m; ++l) v -= (R)Bt[l] * ((R)dlu[tt * m + l] * rinv<R>(Rd, iR, tt * m + l));
+    for (int j = 0; j < NX; ++j)
+      v -= ldA<R>(P, a0 + j) * ((R)dlx[tt * NX + j] * rinv<R>(Qd, iQ, tt * NX + j));
+    for (int l = 0; l < m; ++l)
+      v -= ldB<R>(P, b0 + l) * ((R)dlu[tt * m + l] * rinv<R>(Rd, iR, tt * m + l));
   }
   return v;
 }
@@ -1176,22 +1213,24 @@ __device__ __noinline__ int fwd_recover_ls(const ProbRec* rec, const float* data
       const int t = rho / NX, i = rho - t * NX;
       double acc = (double)q[rho] + ((double)w0[NX + rho] + (double)w2[NX + rho]);
       if (t < T) {
-        const float* At = P.A + t * NX * NX;
+        const int a0 = t * NX * NX;
         const float* lh = w0 + NX + (t + 1) * NX;
         const float* ll = w2 + NX + (t + 1) * NX;
 #pragma unroll
-        for (int kk = 0; kk < NX; ++kk) acc -= (double)At[kk * NX + i] * ((double)lh[kk] + (double)ll[kk]);
+        for (int kk = 0; kk < NX; ++kk)
+          acc -= ldA<double>(P, a0 + kk * NX + i) * ((double)lh[kk] + (double)ll[kk]);
       }
       xp[rho] = (float)(-acc / (double)Qd[rho]);
     }
     for (int idx = tid; idx < TM; idx += BT) {
       const int t = idx / m, l = idx - t * m;
-      const float* Bt = P.B + t * NX * m;
+      const int b0 = t * NX * m;
       const float* lh = w0 + NX + (t + 1) * NX;
       const float* ll = w2 + NX + (t + 1) * NX;
       double acc = (double)rr[idx];
 #pragma unroll
-      for (int kk = 0; kk < NX; ++kk) acc -= (double)Bt[kk * m + l] * ((double)lh[kk] + (double)ll[kk]);
+      for (int kk = 0; kk < NX; ++kk)
+        acc -= ldB<double>(P, b0 + kk * m + l) * ((double)lh[kk] + (double)ll[kk]);
       up[idx] = (float)(-acc / (double)Rd[idx]);
     }
   }
@@ -1437,11 +1476,12 @@ __device__ __noinline__ void bwd_finish(const ProbRec* rec, const float* data, f
     const int t = rho / NX, i = rho - t * NX;
     double acc = (double)dlx[rho] - ((double)lw[rho] + (double)lwl[rho]);
     if (t < T) {
-      const float* At = P.A + t * NX * NX;
+      const int a0 = t * NX * NX;
       const float* lh = lw + (t + 1) * NX;
       const float* ll = lwl + (t + 1) * NX;
 #pragma unroll
-      for (int kk = 0; kk < NX; ++kk) acc += (double)At[kk * NX + i] * ((double)lh[kk] + (double)ll[kk]);
+      for (int kk = 0; kk < NX; ++kk)
+        acc += ldA<double>(P, a0 + kk * NX + i) * ((double)lh[kk] + (double)ll[kk]);
     }
     const float v = (float)(acc / (double)Qd[rho]);
     xt[rho] = v;
@@ -1450,12 +1490,13 @@ __device__ __noinline__ void bwd_finish(const ProbRec* rec, const float* data, f
   }
   for (int idx = tid; idx < TM; idx += BT) {
     const int t = idx / m, l = idx - t * m;
-    const float* Bt = P.B + t * NX * m;
+    const int b0 = t * NX * m;
     const float* lh = lw + (t + 1) * NX;
     const float* ll = lwl + (t + 1) * NX;
     double acc = (double)dlu[idx];
 #pragma unroll
-    for (int kk = 0; kk < NX; ++kk) acc += (double)Bt[kk * m + l] * ((double)lh[kk] + (double)ll[kk]);
+    for (int kk = 0; kk < NX; ++kk)
+      acc += ldB<double>(P, b0 + kk * m + l) * ((double)lh[kk] + (double)ll[kk]);
     const float v = (float)(acc / (double)Rd[idx]);
     ut[idx] = v;
     au[idx] = v;

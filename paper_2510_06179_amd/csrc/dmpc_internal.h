@@ -34,6 +34,7 @@ struct ProbRec {
 struct WsLayout {
   int64_t Qd, iQ, q, Rd, iR, r;   // projected Hessian diagonals, inverses, linear terms
   int64_t A, B, c;                // linearised dynamics (nonlinear models only)
+  int64_t Ad, Bd, cd;             // the same in double (float offsets, 8-byte aligned)
   int64_t Dinv;                   // diagonal Schur blocks inverted [N][nx][nx]
   int64_t blk;                    // saved rows of S^ and Phi^-1: [N*nx][6*nx]
   int64_t xp, up, lam;            // last QP solution and multipliers
@@ -59,8 +60,12 @@ DMPC_HD inline WsLayout ws_layout(int T, int nx, int nu, int dyn) {
     L.A = o; o += (int64_t)T * nx * nx;
     L.B = o; o += (int64_t)T * nx * nu;
     L.c = o; o += (int64_t)T * nx;
+    o = align_up(o, 4);
+    L.Ad = o; o += 2 * (int64_t)T * nx * nx;
+    L.Bd = o; o += 2 * (int64_t)T * nx * nu;
+    L.cd = o; o += 2 * (int64_t)T * nx;
   } else {
-    L.A = L.B = L.c = -1;
+    L.A = L.B = L.c = L.Ad = L.Bd = L.cd = -1;
   }
   o = align_up(o, 4);
   L.Dinv = o; o += N * nx * nx;
