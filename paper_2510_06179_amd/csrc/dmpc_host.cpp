@@ -37,7 +37,7 @@ struct dmpc_plan {
   dmpc_opts opts;
 };
 
-namespace {
+namespace dmpc {
 
 const int kStateSizes[] = {2, 3, 4, 8, 12, 16};
 
@@ -156,12 +156,24 @@ bool choose_cfg(const dmpc_problem& p, int force_bt, LaunchCfg* c) {
   return found;
 }
 
+}  // namespace dmpc
+
+namespace {
+
 KArgs make_args(const dmpc_plan* pl, const float* data, float* sol, void* ws, const float* dl,
                 float* adj, float* grad, int32_t* status, int32_t* info) {
+  return dmpc::make_kargs(pl->opts, pl->d_recs, data, sol, ws, dl, adj, grad, status, info);
+}
+
+}  // namespace
+
+namespace dmpc {
+
+KArgs make_kargs(const dmpc_opts& o, const ProbRec* recs, const float* data, float* sol, void* ws,
+                 const float* dl, float* adj, float* grad, int32_t* status, int32_t* info) {
   KArgs a;
   std::memset(&a, 0, sizeof(a));
-  const dmpc_opts& o = pl->opts;
-  a.recs = pl->d_recs;
+  a.recs = recs;
   a.data = data;
   a.sol = sol;
   a.ws = (float*)ws;

@@ -139,7 +139,15 @@ struct LaunchCfg {
   size_t lds_bytes;
 };
 
-// Implemented in dmpc_kernels.hip.
+// Implemented in dmpc_host.cpp (shared with the serving runtime).
+bool nx_supported(int nx);
+dmpc_status check_opts(const dmpc_opts* o);
+dmpc_status check_problem(const dmpc_problem& p, int64_t data_len, int64_t sol_len);
+bool choose_cfg(const dmpc_problem& p, int force_bt, LaunchCfg* c);
+KArgs make_kargs(const dmpc_opts& o, const ProbRec* recs, const float* data, float* sol, void* ws,
+                 const float* dl, float* adj, float* grad, int32_t* status, int32_t* info);
+
+// Implemented in dmpc_launch.hip.
 bool kernel_available(int nx, int slots, int maxbt, int reg);
 int launch_forward(const LaunchCfg& cfg, const KArgs& a, void* stream);
 int launch_backward(const LaunchCfg& cfg, const KArgs& a, void* stream);
