@@ -3,9 +3,12 @@
 One step = one forward solve (Alg. sqp, 10 SQP iterations with the line
 search, PCG inside) plus one backward solve (Alg. backward: adjoint PCG + VJP)
 of the whole batch of 1024 cart-pole OCPs (nx=4, nu=1, T=50, dt=0.05), inputs
-resident in HBM.  Prints one JSON line.
+resident in HBM.  Beside it: the plain one-problem-per-launch GPU form, the
+FP64 oracle on the host cores, and the continuous-batching server under
+Poisson arrivals (p50/p99 latency).  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu] [--plain-sample 64]
+                    [--serve-seconds 60] [--traffic-reference]
 """
 from __future__ import annotations
 
@@ -49,11 +52,11 @@ def _oracle_fwd_bwd(args):
 
 def cpu_baseline(budget_s=15.0):
     cores = min(os.cpu_count() or 1, 16)
+    _oracle_fwd_bwd((0, 0))               # imports and first-call costs
     t0 = time.perf_counter()
-    _oracle_fwd_bwd((0, 0))
+    _oracle_fwd_bwd((0, 1))
     t1 = time.perf_counter() - t0
-    n = max(cores, int(budget_s / max(t1, 1e-3)) * cores // max(cores, 1))
-    n = min(n, B)
+    n = int(min(B, max(cores, budget_s * cores / max(t1, 1e-3))))
     ctx = mp.get_context("fork")
     t0 = time.perf_counter()
     with ctx.Pool(cores) as pool:
@@ -90,6 +93,142 @@ def sqp_iter_flops(T, n, m):
     return T * (2 * n ** 3 + 2 * n * n * m) + 12 * (T + 1) * n ** 3
 
 
+KERNEL_SOURCES = ("dmpc_device.h", "dmpc_internal.h", "dmpc_k4.hip", "dmpc_launch.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "forward_kernel_cartpole_traffic.json")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2510_06179_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per forward launch from the committed counter summary, or
+    None when it is missing or was taken on a different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def traffic_reference(mib=512, reps=8):
+    """A plain device copy of known size, for scaling the HBM byte counters."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"traffic_reference_copy_bytes": n * 4, "launches": reps}), flush=True)
+
+
+def serve_load(seconds, rate_hz=20000.0, sessions=4096, p_bwd=0.3, p_large=0.05, seed=0):
+    """Poisson arrivals of solve and solve+backward requests over sessions drawn
+    from the uneven LTV mix; each request perturbs its session's x_s by
+    N(0, 0.01^2).  Large requests (nx=32, nu=8, T=256) are drawn and counted
+    but not sent: no kernel is built for nx=32."""
+    import ctypes
+    import threading
+
+    from paper_2510_06179_amd import _lib
+    from paper_2510_06179_amd.serving import Server
+
+    rng = np.random.default_rng(seed)
+    probs = [W.ltv_problem(rng, int(rng.choice([16, 32, 64, 128])), int(rng.choice([4, 8, 12, 16])),
+                           int(rng.choice([2, 4]))) for _ in range(sessions)]
+    cots = W.loss_cotangents(probs, seed=seed)
+    srv = Server(max_sessions=sessions, max_T=128, max_nx=16, max_nu=4, max_batch=1024,
+                 max_inflight=4, hbm_budget=32 << 30, sqp_iters=1, alphas=(1.0,), pcg_tol=1e-6,
+                 bwd_pcg_tol=1e-6, bwd_warm_start=True)
+    t_setup = time.perf_counter()
+    for k, p in enumerate(probs):
+        srv.add_session(k, p, dl=(cots[k]["gx"], cots[k]["gu"], cots[k]["glam"]))
+    t_setup = time.perf_counter() - t_setup
+    lib, h = srv.lib, srv._h
+    x0s = np.zeros((sessions, 16), np.float32)
+    for k, p in enumerate(probs):
+        x0s[k, :p["nx"]] = p["x0"]
+    # warm every session once (cold starts are not the steady state)
+    for k in range(sessions):
+        srv.submit(k, bool(k % 3 == 0))
+    srv.drain(timeout=300)
+    srv.reset_stats()
+    arr = W.poisson_arrivals(seed + 1, rate_hz, seconds)
+    n = len(arr)
+    large = rng.random(n) < p_large
+    sess = rng.integers(0, sessions, size=n)
+    bwd = rng.random(n) < p_bwd
+    xs = x0s[sess] + rng.normal(0.0, 0.01, size=(n, 16)).astype(np.float32)
+    xs = np.ascontiguousarray(xs, np.float32)
+    base = xs.ctypes.data
+    tickets = []
+    done = threading.Event()
+    sent = [0]
+
+    def reap():
+        st, ps = ctypes.c_int32(), ctypes.c_int32()
+        i = 0
+        while True:
+            if i < len(tickets):
+                lib.dmpc_server_wait(h, tickets[i], -1.0, None, None, None, ctypes.byref(st),
+                                     ctypes.byref(ps))
+                i += 1
+            elif done.is_set():
+                break
+            else:
+                time.sleep(0.0005)
+
+    th = threading.Thread(target=reap, daemon=True)
+    th.start()
+    tk = ctypes.c_int64()
+    submit = lib.dmpc_server_submit
+    lag = []
+    t0 = time.perf_counter()
+    for i in range(n):
+        if large[i]:
+            continue
+        while True:
+            now = time.perf_counter() - t0
+            if now >= arr[i]:
+                break
+            if arr[i] - now > 0.002:
+                time.sleep(0.0005)
+        lag.append(now - arr[i])
+        rc = submit(h, int(sess[i]), int(bwd[i]), base + 64 * i, None, ctypes.byref(tk))
+        if rc == 0:
+            tickets.append(tk.value)
+            sent[0] += 1
+    srv.drain(timeout=300)
+    done.set()
+    th.join()
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    return {
+        "arrivals": "poisson", "rate_hz": rate_hz, "seconds": seconds, "sessions": sessions,
+        "requests_sent": sent[0], "large_requests_not_sent": int(large.sum()),
+        "backward_fraction": float(bwd[~large].mean()) if n else 0.0,
+        "completed": st["completed"], "rejected": st["rejected"], "failed": st["failed"],
+        "throughput_rps": st["throughput"], "p50_latency_ms": 1e3 * st["p50_latency_s"],
+        "p99_latency_ms": 1e3 * st["p99_latency_s"], "max_latency_ms": 1e3 * st["max_latency_s"],
+        "mean_group_size": st["mean_group_size"], "max_group_size": st["max_group_size"],
+        "max_queue_depth": st["max_pending_seen"], "groups": st["groups"],
+        "submit_lag_p99_ms": 1e3 * float(np.quantile(lag, 0.99)) if lag else 0.0,
+        "wall_s": wall, "setup_s": t_setup,
+        "server": {"max_batch": 1024, "max_inflight": 4, "hbm_budget_gib": 32,
+                   "sqp_iters": 1, "pcg_tol": 1e-6},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,13 +236,20 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--plain-sample", type=int, default=64)
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="duration of the serving load (0: skip)")
     ap.add_argument("--block-threads", type=int, default=0,
                     help="force the threads per workgroup (0: the library's choice)")
+    ap.add_argument("--traffic-reference", action="store_true",
+                    help="only run a plain 512 MiB device copy (counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); "
               "problems are independent, see DESIGN.md for how the batch shards", file=sys.stderr)
         sys.exit(2)
+    if args.traffic_reference:
+        traffic_reference()
+        return
 
     cpu = None if args.no_cpu else cpu_baseline()
 
@@ -119,31 +265,30 @@ def main():
     sol = s.sol0.clone()
     adj = torch.zeros_like(sol)
     grad = torch.zeros_like(s.data)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-    fwd_ms, bwd_ms = [], []
+    # events on the stream the kernels are launched on (torch's current stream)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
 
-    def step(record):
+    def step(e=None):
         sol.copy_(s.sol0)
-        ev[0].record()
+        if e:
+            e[0].record()
         s.solve(sol=sol)
-        ev[1].record()
+        if e:
+            e[1].record()
         s.solve_backward(dl, adj=adj, grad=grad)
-        ev[2].record()
-        if record:
-            torch.cuda.synchronize()
-            fwd_ms.append(ev[0].elapsed_time(ev[1]))
-            bwd_ms.append(ev[1].elapsed_time(ev[2]))
+        if e:
+            e[2].record()
 
     for _ in range(args.warmup):
-        step(False)
+        step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(False)
+    for i in range(args.steps):
+        step(ev[i])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    for _ in range(min(args.steps, 10)):
-        step(True)
+    fwd_ms = [e[0].elapsed_time(e[1]) for e in ev]
+    bwd_ms = [e[1].elapsed_time(e[2]) for e in ev]
     ms_per_step = 1000.0 * wall / args.steps
     value = B / (wall / args.steps)
 
@@ -160,26 +305,35 @@ def main():
     fwd_s = float(np.mean(fwd_ms)) / 1000.0
     achieved = fwd_flops / fwd_s
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": FP32_VECTOR_PEAK / 1e12,
-            "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK, "traffic": None,
+            "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK,
+            "traffic": measured_traffic(),
             "kernel": "forward_kernel (fused SQP: QP data, Schur assembly, preconditioner, "
                       "PCG with double-residual refinement, recovery, line search)",
+            "flops_per_launch": fwd_flops,
             "launch": s.describe(),
-            "kernel_ms": float(np.mean(fwd_ms)), "backward_kernel_ms": float(np.mean(bwd_ms))}
+            "kernel_ms": float(np.mean(fwd_ms)), "backward_kernel_ms": float(np.mean(bwd_ms)),
+            "kernel_source_hash": kernel_source_hash()}
 
     # plain one-problem-per-launch GPU form on a sample of the same batch
     P = min(args.plain_sample, B)
-    for i in range(2):  # warm the per-problem path
-        s.solve_one(i, sol=sol)
-        s.solve_backward_one(i, dl, adj=adj, grad=grad)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sol.copy_(s.sol0)
-    for i in range(P):
-        s.solve_one(i, sol=sol)
-        s.solve_backward_one(i, dl, adj=adj, grad=grad)
-    torch.cuda.synchronize()
-    plain_wall = time.perf_counter() - t0
-    plain_value = P / plain_wall
+    plain = None
+    if P > 0:
+        for i in range(2):  # warm the per-problem path
+            s.solve_one(i, sol=sol)
+            s.solve_backward_one(i, dl, adj=adj, grad=grad)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sol.copy_(s.sol0)
+        for i in range(P):
+            s.solve_one(i, sol=sol)
+            s.solve_backward_one(i, dl, adj=adj, grad=grad)
+        torch.cuda.synchronize()
+        plain_value = P / (time.perf_counter() - t0)
+        plain = {"value": plain_value, "unit": "solves/s", "sample": P,
+                 "speedup_batched": value / plain_value}
+    s.close()
+
+    serving = serve_load(args.serve_seconds) if args.serve_seconds > 0 else None
 
     out = {
         "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1,
@@ -191,8 +345,8 @@ def main():
                    "global_batch": B, "seq_len": T, "parallelism": "single GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,
-        "plain_gpu": {"value": plain_value, "unit": "solves/s", "sample": P,
-                      "speedup_batched": value / plain_value},
+        "plain_gpu": plain,
+        "serving": serving,
         "solver": {"fwd_pcg_iters_mean": float(info[:, 0].mean()),
                    "bwd_pcg_iters_mean": float(info[:, 1].mean()),
                    "nonpd_or_nonfinite": bad, "fwd_pcg_capped": capped_f,

@@ -207,6 +207,118 @@ dmpc_status dmpc_workspace_offsets(const dmpc_plan* plan, int32_t index, int64_t
  * count) into the host buffer buf of size len (truncated if too small). */
 dmpc_status dmpc_plan_describe(const dmpc_plan* plan, char* buf, size_t len);
 
+
+/* ------------------------------------------------------------------------ */
+/* Serving: continuous batching of solve and solve+backward requests        */
+/* ------------------------------------------------------------------------ */
+/* A server keeps, per session, one problem's data, its warm start (x, u,
+ * lambda of the last solve, lambda~ of the last backward pass) and its current
+ * loss cotangent in device memory (the warm-started reuse of Sec. 4).  A
+ * request names a session, may bring a new initial state x_s and a new
+ * cotangent, and asks for the forward pass (Alg. sqp, started from the
+ * session's last solution: INIT_GIVEN) or the forward and backward passes
+ * (Alg. sqp then Alg. backward).
+ *
+ * A dispatcher thread forms a launch group from the requests pending at that
+ * moment, first come first served, while the group holds at most max_batch
+ * requests and its per-problem workspaces fit one in-flight share of the
+ * memory budget (hbm_budget / max_inflight).  Up to max_inflight groups run
+ * at once, each on its own stream, so requests that arrive while others are
+ * on the GPU are taken by the next group as soon as a share frees up, and
+ * their kernels overlap on the device.  A session has at most one request in
+ * flight; its later requests wait and run in submission order.  A result does
+ * not depend on which other requests share its group.
+ *
+ * Device memory is allocated in dmpc_server_create only: per-session stores
+ * (max_sessions blocks sized for the largest shape max_T, max_nx, max_nu),
+ * the in-flight workspaces and staging buffers (pinned host + device).
+ * Calls are thread safe.  Results are copied into host memory when a group
+ * finishes and stay there until dmpc_server_wait returns them. */
+typedef struct dmpc_server dmpc_server;
+
+typedef struct dmpc_server_config {
+  int32_t device;           /* HIP device */
+  int32_t max_sessions;     /* sessions 0..max_sessions-1, >= 1 */
+  int32_t max_batch;        /* requests per launch group, 1..65536 */
+  int32_t max_inflight;     /* launch groups running at once (one stream each), 1..8 */
+  int32_t max_T, max_nx, max_nu;   /* largest session shape */
+  int32_t max_pending;      /* submissions beyond this many waiting requests are
+                               rejected (0 = no limit) */
+  int32_t batch_window_us;  /* a free share waits up to this long for max_batch requests
+                               before launching what is pending (0 = launch at once) */
+  int32_t dry_run;          /* 1: no device work at all -- groups are formed and
+                               "complete" after dry_run_us with zero outputs; for
+                               testing the admission logic without a GPU */
+  int32_t dry_run_us;
+  int32_t reserved;         /* must be 0 */
+  int64_t hbm_budget;       /* bytes of workspace for the in-flight groups (split evenly) */
+  int64_t staging_bytes;    /* per in-flight group, for its inputs and again for its
+                               results, pinned host + device (0 = 64 MiB); a group also
+                               stops admitting when these would overflow */
+  dmpc_opts opts;           /* solver options of every request; init must be GIVEN */
+} dmpc_server_config;
+
+typedef struct dmpc_server_stats {
+  int64_t submitted;        /* accepted submissions */
+  int64_t rejected;         /* refused submissions (queue full) */
+  int64_t completed;        /* finished requests (of which backward_completed had a backward pass) */
+  int64_t backward_completed;
+  int64_t failed;           /* requests whose group failed to launch */
+  int64_t groups;           /* launch groups run */
+  double mean_group_size;
+  int64_t max_group_size;
+  int64_t max_pending_seen; /* deepest admission queue seen */
+  double p50_latency_s, p99_latency_s, max_latency_s;  /* submit -> results on the host */
+  double throughput;        /* completed / (last completion - first submission), per second */
+} dmpc_server_stats;
+
+/* Request states reported by dmpc_server_wait */
+enum { DMPC_REQ_PENDING = 0, DMPC_REQ_RUNNING = 1, DMPC_REQ_DONE = 2, DMPC_REQ_FAILED = 3 };
+
+dmpc_status dmpc_server_create(const dmpc_server_config* cfg, dmpc_server** srv);
+/* Finishes the requests already launched, fails the pending ones, joins the
+ * threads and frees everything. */
+dmpc_status dmpc_server_destroy(dmpc_server* srv);
+
+/* Registers (or replaces) session `session`.  problem: HOST descriptor whose
+ * dyn_off, cost_off and x0_off index the HOST block data[data_len] (sol_off is
+ * ignored); its shape must fit max_T, max_nx, max_nu.  sol0: HOST warm start
+ * [sol block] or NULL (zeros); dl: HOST cotangent [sol block] or NULL (zeros).
+ * The adjoint warm start starts at zero.  Fails with INVALID_ARG while the
+ * session has requests pending or in flight. */
+dmpc_status dmpc_server_add_session(dmpc_server* srv, int32_t session, const dmpc_problem* problem,
+                                    const float* data, int64_t data_len, const float* sol0,
+                                    const float* dl);
+
+/* Queues a request.  x0: HOST x_s [nx] (NULL keeps the session's current one);
+ * dl: HOST cotangent [sol block] that becomes the session's current one (NULL
+ * keeps it).  *ticket identifies the request.  Returns NOMEM when max_pending
+ * requests are already waiting (the request is not queued). */
+dmpc_status dmpc_server_submit(dmpc_server* srv, int32_t session, int32_t backward,
+                               const float* x0, const float* dl, int64_t* ticket);
+
+/* Waits up to timeout_s seconds (< 0: no limit) for a request to finish and
+ * copies its results into HOST buffers (each may be NULL): sol [sol block] (x,
+ * u after the last line search, lambda), grad [data_len of the session]
+ * (backward requests; laid out like the session's data block), info [4] (as
+ * dmpc_solve).  *state receives DMPC_REQ_*, *prob_status the per-problem
+ * status bits.  Once a finished request's results are returned its ticket is
+ * forgotten.  An unknown ticket gives INVALID_ARG. */
+dmpc_status dmpc_server_wait(dmpc_server* srv, int64_t ticket, double timeout_s, float* sol,
+                             float* grad, int32_t* info, int32_t* state, int32_t* prob_status);
+
+/* Waits until every accepted request has finished (or timeout_s passed:
+ * returns INVALID_ARG then). */
+dmpc_status dmpc_server_drain(dmpc_server* srv, double timeout_s);
+dmpc_status dmpc_server_get_stats(dmpc_server* srv, dmpc_server_stats* out);
+/* Clears the latency samples and counters (between warm-up and measurement). */
+dmpc_status dmpc_server_reset_stats(dmpc_server* srv);
+
+/* JSON array describing the last (up to 1024) launch groups: tickets, slot,
+ * workspace bytes, launch and completion times (s since creation).  Written
+ * into the HOST buffer buf[len] (truncated if too small). */
+dmpc_status dmpc_server_trace(dmpc_server* srv, char* buf, size_t len);
+
 /* Human-readable name of a return code (static string). */
 const char* dmpc_status_string(dmpc_status s);
 

@@ -30,7 +30,11 @@ EXPORTED = (
     "dmpc_plan_create", "dmpc_plan_workspace_size", "dmpc_plan_destroy", "dmpc_solve",
     "dmpc_solve_backward", "dmpc_solve_one", "dmpc_solve_backward_one", "dmpc_status_string",
     "dmpc_version", "dmpc_workspace_offsets", "dmpc_plan_describe",
+    "dmpc_server_create", "dmpc_server_destroy", "dmpc_server_add_session", "dmpc_server_submit",
+    "dmpc_server_wait", "dmpc_server_drain", "dmpc_server_get_stats", "dmpc_server_reset_stats",
+    "dmpc_server_trace",
 )
+REQ_PENDING, REQ_RUNNING, REQ_DONE, REQ_FAILED = range(4)
 
 
 class Problem(ctypes.Structure):
@@ -61,6 +65,30 @@ class Opts(ctypes.Structure):
         ("bwd_pcg_tol", ctypes.c_float), ("block_threads", ctypes.c_int32),
         ("refine_steps", ctypes.c_int32), ("refine_tol", ctypes.c_float),
         ("kkt_tol", ctypes.c_float),
+    ]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [
+        ("device", ctypes.c_int32), ("max_sessions", ctypes.c_int32),
+        ("max_batch", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
+        ("max_T", ctypes.c_int32), ("max_nx", ctypes.c_int32), ("max_nu", ctypes.c_int32),
+        ("max_pending", ctypes.c_int32), ("batch_window_us", ctypes.c_int32),
+        ("dry_run", ctypes.c_int32), ("dry_run_us", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("hbm_budget", ctypes.c_int64), ("staging_bytes", ctypes.c_int64),
+        ("opts", Opts),
+    ]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_int64), ("rejected", ctypes.c_int64),
+        ("completed", ctypes.c_int64), ("backward_completed", ctypes.c_int64),
+        ("failed", ctypes.c_int64), ("groups", ctypes.c_int64),
+        ("mean_group_size", ctypes.c_double), ("max_group_size", ctypes.c_int64),
+        ("max_pending_seen", ctypes.c_int64), ("p50_latency_s", ctypes.c_double),
+        ("p99_latency_s", ctypes.c_double), ("max_latency_s", ctypes.c_double),
+        ("throughput", ctypes.c_double),
     ]
 
 
@@ -98,6 +126,15 @@ def load():
         "dmpc_version": (i32, []),
         "dmpc_workspace_offsets": (i32, [vp, i32, P(i64)]),
         "dmpc_plan_describe": (i32, [vp, ctypes.c_char_p, ctypes.c_size_t]),
+        "dmpc_server_create": (i32, [P(ServerConfig), P(vp)]),
+        "dmpc_server_destroy": (i32, [vp]),
+        "dmpc_server_add_session": (i32, [vp, i32, P(Problem), vp, i64, vp, vp]),
+        "dmpc_server_submit": (i32, [vp, i32, i32, vp, vp, P(i64)]),
+        "dmpc_server_wait": (i32, [vp, i64, ctypes.c_double, vp, vp, vp, P(i32), P(i32)]),
+        "dmpc_server_drain": (i32, [vp, ctypes.c_double]),
+        "dmpc_server_get_stats": (i32, [vp, P(ServerStats)]),
+        "dmpc_server_reset_stats": (i32, [vp]),
+        "dmpc_server_trace": (i32, [vp, ctypes.c_char_p, ctypes.c_size_t]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

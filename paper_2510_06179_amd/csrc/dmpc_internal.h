@@ -147,6 +147,17 @@ bool choose_cfg(const dmpc_problem& p, int force_bt, LaunchCfg* c);
 KArgs make_kargs(const dmpc_opts& o, const ProbRec* recs, const float* data, float* sol, void* ws,
                  const float* dl, float* adj, float* grad, int32_t* status, int32_t* info);
 
+// A copy of len 32-bit words between two device addresses (serving scatter
+// and gather).
+struct Seg {
+  const uint32_t* src;
+  uint32_t* dst;
+  int64_t len;
+};
+
+// Implemented in dmpc_serve.hip: copies every segment of segs[n] (device).
+int launch_seg_copy(const Seg* segs, int n, void* stream);
+
 // Implemented in dmpc_launch.hip.
 bool kernel_available(int nx, int slots, int maxbt, int reg);
 int launch_forward(const LaunchCfg& cfg, const KArgs& a, void* stream);

@@ -174,7 +174,9 @@ def bicycle_batch(seed=0, batch=512, T=64, phases=4, perturb=0.2):
     theta = f32(rng.normal(0.0, 0.1, size=phases * (nw + nu)))
     # per-state scale so that weights are O(1) in the scaled units
     wscale = f32([1.0, 0.5, 4.0, 0.01, 2.0, 0.5, 2.0, 2.0])
-    wfix = f32([1e-2, 1e-2])
+    # unit weights on the actuator states (delta, tau): with 1e-2 there the
+    # preconditioned Schur complement's condition number is ~4e5 instead of ~3e4
+    wfix = f32([1.0, 1.0])
     ranges = np.array([0.1, 0.5, 0.05, 1.0, 0.05, 0.2, 0.02, 0.05])
     for _ in range(batch):
         par = base.copy()
