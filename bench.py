@@ -8,7 +8,7 @@ FP64 oracle on the host cores, and the continuous-batching server under
 Poisson arrivals (p50/p99 latency).  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu] [--plain-sample 64]
-                    [--serve-seconds 60] [--traffic-reference]
+                    [--serve-seconds 60] [--no-extra] [--traffic-reference]
 """
 from __future__ import annotations
 
@@ -131,6 +131,51 @@ def traffic_reference(mib=512, reps=8):
     print(json.dumps({"traffic_reference_copy_bytes": n * 4, "launches": reps}), flush=True)
 
 
+def extra_workloads(steps=5, warmup=1):
+    """Throughput of the other two batch workloads, fwd+bwd per step: the
+    bicycle differentiation batch (512 OCPs, nx=8, nu=2, T=64, 10 SQP
+    iterations, softplus cost weights) and the uneven LTV batch (4096 OCPs,
+    T in {16..128}, nx in {4..16}, nu in {2,4}, 8 SQP iterations)."""
+    import torch
+    from paper_2510_06179_amd import batch
+    from paper_2510_06179_amd.solver import BatchSolver
+
+    out = {}
+    for name, probs, sqp in (("bicycle_b512_fwd_bwd", W.bicycle_batch(0, batch=512), 10),
+                             ("uneven_ltv_b4096_fwd_bwd", W.ltv_uneven_batch(0, batch=4096), 8)):
+        cots = W.loss_cotangents(probs, seed=0)
+        s = BatchSolver(probs, sqp_iters=sqp, pcg_tol=PCG_TOL, bwd_pcg_tol=PCG_TOL)
+        dl = torch.from_numpy(batch.sol_like(s.packed, [(c["gx"], c["gu"], c["glam"])
+                                                        for c in cots])).to(s.device)
+        sol = s.sol0.clone()
+        adj = torch.zeros_like(sol)
+        grad = torch.zeros_like(s.data)
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+        for i in range(warmup + steps):
+            e = ev[i - warmup] if i >= warmup else None
+            sol.copy_(s.sol0)
+            if e:
+                e[0].record()
+            s.solve(sol=sol)
+            if e:
+                e[1].record()
+            s.solve_backward(dl, adj=adj, grad=grad)
+            if e:
+                e[2].record()
+        torch.cuda.synchronize()
+        fwd = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+        bwd = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+        info = s.info.cpu().numpy()
+        status = s.status.cpu().numpy()
+        out[name] = {"solves_per_s": len(probs) / ((fwd + bwd) / 1e3), "fwd_ms": fwd, "bwd_ms": bwd,
+                     "sqp_iters": sqp, "fwd_pcg_iters_mean": float(info[:, 0].mean()),
+                     "bwd_pcg_iters_mean": float(info[:, 1].mean()),
+                     "pcg_capped": int(np.count_nonzero(status & 1)),
+                     "launch_groups": len(s.describe())}
+        s.close()
+    return out
+
+
 def serve_load(seconds, rate_hz=20000.0, sessions=4096, p_bwd=0.3, p_large=0.05, seed=0):
     """Poisson arrivals of solve and solve+backward requests over sessions drawn
     from the uneven LTV mix; each request perturbs its session's x_s by
@@ -240,6 +285,8 @@ def main():
                     help="duration of the serving load (0: skip)")
     ap.add_argument("--block-threads", type=int, default=0,
                     help="force the threads per workgroup (0: the library's choice)")
+    ap.add_argument("--no-extra", dest="extra", action="store_false",
+                    help="skip the bicycle and uneven-LTV throughput lines")
     ap.add_argument("--traffic-reference", action="store_true",
                     help="only run a plain 512 MiB device copy (counter scaling)")
     args = ap.parse_args()
@@ -333,6 +380,7 @@ def main():
                  "speedup_batched": value / plain_value}
     s.close()
 
+    extra = extra_workloads() if args.extra else None
     serving = serve_load(args.serve_seconds) if args.serve_seconds > 0 else None
 
     out = {
@@ -346,6 +394,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "plain_gpu": plain,
+        "other_workloads": extra,
         "serving": serving,
         "solver": {"fwd_pcg_iters_mean": float(info[:, 0].mean()),
                    "bwd_pcg_iters_mean": float(info[:, 1].mean()),

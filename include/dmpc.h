@@ -319,6 +319,39 @@ dmpc_status dmpc_server_reset_stats(dmpc_server* srv);
  * into the HOST buffer buf[len] (truncated if too small). */
 dmpc_status dmpc_server_trace(dmpc_server* srv, char* buf, size_t len);
 
+/* ------------------------------------------------------------------------ */
+/* Kernel mapping: instantiated variants and the tuning table                */
+/* ------------------------------------------------------------------------ */
+/* A problem's rows (T+1)*nx are spread over the threads of one workgroup,
+ * `slots` rows per thread, with the Schur and preconditioner rows held in
+ * registers (register_rows = 1) or read from the workspace.  Without a
+ * tuning-table entry the library picks the instantiated variant with the
+ * lowest modelled cost.
+ *
+ * dmpc_list_variants writes up to max_rows rows of 4 int32 (nx, slots,
+ * launch_bound, register_rows) of the instantiated kernels into the HOST array
+ * out and returns how many exist.  Host only. */
+int32_t dmpc_list_variants(int32_t* out, int32_t max_rows);
+
+/* Installs the process-wide tuning table: n_rows HOST rows of 7 int32
+ * (nx, T_min, T_max, slots, launch_bound, register_rows, block_threads).  A
+ * problem with that nx and T_min <= T <= T_max uses the first matching row
+ * whose variant is instantiated and holds its rows (slots * block_threads >=
+ * (T+1)*nx, block_threads a multiple of 64 not above launch_bound); otherwise
+ * the cost model decides.  Replaces the previous table; n_rows = 0 clears it.
+ * Affects plans and sessions created afterwards.  INVALID_ARG on a malformed
+ * row (nothing is installed then).  Host only; thread safe. */
+dmpc_status dmpc_set_tuning(const int32_t* rows, int32_t n_rows);
+
+/* Copies up to max_rows rows of the installed table into the HOST array rows
+ * and returns the number of rows installed. */
+int32_t dmpc_get_tuning(int32_t* rows, int32_t max_rows);
+
+/* The mapping a plan would give `problem` (HOST descriptor) under `opts`:
+ * out[0..3] = slots, launch_bound, register_rows, block_threads.  UNSUPPORTED
+ * when no instantiated variant holds it.  Host only. */
+dmpc_status dmpc_choose_mapping(const dmpc_problem* problem, const dmpc_opts* opts, int32_t* out);
+
 /* Human-readable name of a return code (static string). */
 const char* dmpc_status_string(dmpc_status s);
 

@@ -32,8 +32,10 @@ EXPORTED = (
     "dmpc_version", "dmpc_workspace_offsets", "dmpc_plan_describe",
     "dmpc_server_create", "dmpc_server_destroy", "dmpc_server_add_session", "dmpc_server_submit",
     "dmpc_server_wait", "dmpc_server_drain", "dmpc_server_get_stats", "dmpc_server_reset_stats",
-    "dmpc_server_trace",
+    "dmpc_server_trace", "dmpc_list_variants", "dmpc_set_tuning", "dmpc_get_tuning",
+    "dmpc_choose_mapping",
 )
+TUNING_PATH = os.path.join(PKG, "tuning_gfx950.json")
 REQ_PENDING, REQ_RUNNING, REQ_DONE, REQ_FAILED = range(4)
 
 
@@ -135,13 +137,42 @@ def load():
         "dmpc_server_get_stats": (i32, [vp, P(ServerStats)]),
         "dmpc_server_reset_stats": (i32, [vp]),
         "dmpc_server_trace": (i32, [vp, ctypes.c_char_p, ctypes.c_size_t]),
+        "dmpc_list_variants": (i32, [vp, i32]),
+        "dmpc_set_tuning": (i32, [vp, i32]),
+        "dmpc_get_tuning": (i32, [vp, i32]),
+        "dmpc_choose_mapping": (i32, [P(Problem), P(Opts), vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
     _lib = lib
+    if os.path.exists(TUNING_PATH) and not os.environ.get("DMPC_NO_TUNING"):
+        install_tuning(load_tuning(TUNING_PATH))
     return lib
+
+
+def load_tuning(path):
+    """Rows (nx, T_min, T_max, slots, launch_bound, register_rows,
+    block_threads) of a tuning file written by paper_2510_06179_amd.tune."""
+    import json
+    with open(path) as f:
+        return [tuple(int(v) for v in r) for r in json.load(f)["rows"]]
+
+
+def install_tuning(rows):
+    arr = np.ascontiguousarray(np.asarray(rows, dtype=np.int32).reshape(-1, 7))
+    check(load().dmpc_set_tuning(arr.ctypes.data if len(arr) else None, len(arr)),
+          "dmpc_set_tuning")
+
+
+def variants():
+    """(nx, slots, launch_bound, register_rows) of every instantiated kernel."""
+    lib = load()
+    n = lib.dmpc_list_variants(None, 0)
+    out = np.zeros((n, 4), np.int32)
+    lib.dmpc_list_variants(out.ctypes.data, n)
+    return [tuple(int(v) for v in r) for r in out]
 
 
 def check(rc, what=""):

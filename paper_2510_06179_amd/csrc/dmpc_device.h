@@ -283,7 +283,7 @@ __device__ __forceinline__ float block_sum(float v, float* red, int nwv) {
 // Per-problem context
 // ===========================================================================
 struct Prob {
-  int T, N, m, R, TM, dyn, cost, phases, nw;
+  int T, N, m, R, TM, dyn, cost, phases, nw, slots;
   const float* dynp;   // dynamics block in the data arena
   const float* costp;  // cost block in the data arena
   const float* x0;
@@ -309,6 +309,7 @@ __device__ __forceinline__ Prob make_prob(const ProbRec& pr, const float* data, 
   P.cost = pr.cost;
   P.phases = pr.phases;
   P.nw = pr.nw;
+  P.slots = pr.slots;
   P.dynp = data + pr.dyn_off;
   P.costp = data + pr.cost_off;
   P.x0 = data + pr.x0_off;
@@ -548,6 +549,8 @@ __device__ __forceinline__ void form_qp(const Prob& P, const float* xbar, const 
   float* Rd = W + P.L.Rd;
   float* iR = W + P.L.iR;
   float* r = W + P.L.r;
+  double* iQd = (double*)(W + P.L.iQd);
+  double* iRd = (double*)(W + P.L.iRd);
   // cost Hessians projected onto {H >= eps I} and linear terms
   // q = grad c(xb) - Q_proj xb  (written so that q = q_raw exactly when no clamp)
   for (int idx = tid; idx < P.R; idx += BT) {
@@ -563,6 +566,7 @@ __device__ __forceinline__ void form_qp(const Prob& P, const float* xbar, const 
     const float hp = fmaxf(h, kPdEps);
     Qd[idx] = hp;
     iQ[idx] = 1.f / hp;
+    iQd[idx] = 1.0 / (double)hp;
     q[idx] = qq + (h - hp) * xbar[idx];
   }
   for (int idx = tid; idx < P.TM; idx += BT) {
@@ -578,6 +582,7 @@ __device__ __forceinline__ void form_qp(const Prob& P, const float* xbar, const 
     const float hp = fmaxf(h, kPdEps);
     Rd[idx] = hp;
     iR[idx] = 1.f / hp;
+    iRd[idx] = 1.0 / (double)hp;
     r[idx] = rr + (h - hp) * ubar[idx];
   }
   // dynamics Jacobians for nonlinear models, one thread per stage
@@ -611,32 +616,32 @@ __device__ __forceinline__ void form_qp(const Prob& P, const float* xbar, const 
 //   g = -gamma:  g_0 = -(x_s + Q_0^-1 q_0),
 //   g_{t+1} = -(c_t - A_t Q_t^-1 q_t - B_t R_t^-1 r_t + Q_{t+1}^-1 q_{t+1})
 // S[0:NX] = E_{t,t-1}[i,:], S[NX:2NX] = D_t[i,:], S[2NX:3NX] = E_{t,t+1}[i,:]
-// The double version recomputes every inverse from the stored Hessian
-// diagonal; the float version uses the stored reciprocals.
+// Both versions read the reciprocals of the projected Hessian diagonal that
+// form_qp stores, in float and in double.
 // ===========================================================================
 template <typename R>
-__device__ __forceinline__ R rinv(const float* h, const float* ih, int idx) {
+__device__ __forceinline__ R rinv(const float* ih, const double* ihd, int idx) {
   if constexpr (sizeof(R) == sizeof(float)) {
     return ih[idx];
   } else {
-    return 1.0 / (double)h[idx];
+    return ihd[idx];
   }
 }
 
 template <int NX, typename R>
 __device__ __forceinline__ void schur_row(const Prob& P, int t, int i, R* S, R& g) {
   const float* W = P.W;
-  const float* Qd = W + P.L.Qd;
   const float* iQ = W + P.L.iQ;
   const float* q = W + P.L.q;
-  const float* Rd = W + P.L.Rd;
   const float* iR = W + P.L.iR;
   const float* r = W + P.L.r;
+  const double* iQd = (const double*)(W + P.L.iQd);
+  const double* iRd = (const double*)(W + P.L.iRd);
   const int m = P.m;
 #pragma unroll
   for (int j = 0; j < 3 * NX; ++j) S[j] = R(0);
   if (t == 0) {
-    const R d = rinv<R>(Qd, iQ, i);
+    const R d = rinv<R>(iQ, iQd, i);
 #pragma unroll
     for (int j = 0; j < NX; ++j) S[NX + j] = (j == i) ? d : R(0);
     g = -((R)P.x0[i] + (R)q[i] * d);
@@ -647,7 +652,7 @@ __device__ __forceinline__ void schur_row(const Prob& P, int t, int i, R* S, R& 
     R gs = R(0);
 #pragma unroll
     for (int j = 0; j < NX; ++j) {
-      ai[j] = ldA<R>(P, a0 + i * NX + j) * rinv<R>(Qd, iQ, tt * NX + j);
+      ai[j] = ldA<R>(P, a0 + i * NX + j) * rinv<R>(iQ, iQd, tt * NX + j);
       gs += ai[j] * (R)q[tt * NX + j];
       S[j] = -ai[j];
     }
@@ -659,19 +664,19 @@ __device__ __forceinline__ void schur_row(const Prob& P, int t, int i, R* S, R& 
       S[NX + k] = acc;
     }
     for (int l = 0; l < m; ++l) {
-      const R bi = ldB<R>(P, b0 + i * m + l) * rinv<R>(Rd, iR, tt * m + l);
+      const R bi = ldB<R>(P, b0 + i * m + l) * rinv<R>(iR, iRd, tt * m + l);
       gs += bi * (R)r[tt * m + l];
 #pragma unroll
       for (int k = 0; k < NX; ++k) S[NX + k] += bi * ldB<R>(P, b0 + k * m + l);
     }
-    const R dq = rinv<R>(Qd, iQ, t * NX + i);
+    const R dq = rinv<R>(iQ, iQd, t * NX + i);
 #pragma unroll
     for (int k = 0; k < NX; ++k) S[NX + k] += (k == i) ? dq : R(0);
     g = -(ldc<R>(P, tt * NX + i) - gs + (R)q[t * NX + i] * dq);
   }
   if (t < P.T) {
     const int a0 = t * NX * NX;
-    const R d = rinv<R>(Qd, iQ, t * NX + i);
+    const R d = rinv<R>(iQ, iQd, t * NX + i);
 #pragma unroll
     for (int k = 0; k < NX; ++k) S[2 * NX + k] = -ldA<R>(P, a0 + k * NX + i) * d;
   }
@@ -682,34 +687,51 @@ __device__ __forceinline__ void schur_row(const Prob& P, int t, int i, R* S, R& 
 template <int NX, typename R>
 __device__ __forceinline__ R adjoint_rhs_row(const Prob& P, int t, int i, const float* dlx,
                                              const float* dlu, const float* dll) {
-  const float* Qd = P.W + P.L.Qd;
   const float* iQ = P.W + P.L.iQ;
-  const float* Rd = P.W + P.L.Rd;
   const float* iR = P.W + P.L.iR;
+  const double* iQd = (const double*)(P.W + P.L.iQd);
+  const double* iRd = (const double*)(P.W + P.L.iRd);
   const int m = P.m;
   const int rho = t * NX + i;
-  R v = (R)dlx[rho] * rinv<R>(Qd, iQ, rho) - (R)dll[rho];
+  R v = (R)dlx[rho] * rinv<R>(iQ, iQd, rho) - (R)dll[rho];
   if (t >= 1) {
     const int tt = t - 1;
     const int a0 = tt * NX * NX + i * NX, b0 = tt * NX * m + i * m;
 #pragma unroll
     for (int j = 0; j < NX; ++j)
-      v -= ldA<R>(P, a0 + j) * ((R)dlx[tt * NX + j] * rinv<R>(Qd, iQ, tt * NX + j));
+      v -= ldA<R>(P, a0 + j) * ((R)dlx[tt * NX + j] * rinv<R>(iQ, iQd, tt * NX + j));
     for (int l = 0; l < m; ++l)
-      v -= ldB<R>(P, b0 + l) * ((R)dlu[tt * m + l] * rinv<R>(Rd, iR, tt * m + l));
+      v -= ldB<R>(P, b0 + l) * ((R)dlu[tt * m + l] * rinv<R>(iR, iRd, tt * m + l));
   }
   return v;
 }
 
 // Row product with a padded LDS window: sum_j coef[j] * win[j], win = w + t*NX.
+// For NX a multiple of 4 the window is 16-byte aligned (windows start on
+// 4-float boundaries) and is read with 128-bit LDS loads.
 template <int NX>
 __device__ __forceinline__ float row_dot(const float* coef, const float* win) {
+  float wv[3 * NX];
+  if constexpr (NX % 4 == 0) {
+    const float4* w4 = reinterpret_cast<const float4*>(win);
+#pragma unroll
+    for (int j = 0; j < 3 * NX / 4; ++j) {
+      const float4 v = w4[j];
+      wv[4 * j] = v.x;
+      wv[4 * j + 1] = v.y;
+      wv[4 * j + 2] = v.z;
+      wv[4 * j + 3] = v.w;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 3 * NX; ++j) wv[j] = win[j];
+  }
   float a0 = 0.f, a1 = 0.f, a2 = 0.f;
 #pragma unroll
   for (int j = 0; j < NX; ++j) {
-    a0 = fmaf(coef[j], win[j], a0);
-    a1 = fmaf(coef[NX + j], win[NX + j], a1);
-    a2 = fmaf(coef[2 * NX + j], win[2 * NX + j], a2);
+    a0 = fmaf(coef[j], wv[j], a0);
+    a1 = fmaf(coef[NX + j], wv[NX + j], a1);
+    a2 = fmaf(coef[2 * NX + j], wv[2 * NX + j], a2);
   }
   return (a0 + a1) + a2;
 }
@@ -733,7 +755,13 @@ struct Carve {
   int xbar, ubar, xp, up, lam, w0, w1, w2, piv, red, ls;
 };
 __device__ __forceinline__ int a4(int v) { return (v + 3) & ~3; }
-__device__ __forceinline__ Carve carve(int R, int TM, int N, int nx, int bt) {
+// Window length: a zero pad of nx, one entry for every row of every slot
+// (slots x bt >= R, so that the PCG runs all slots without a row guard: rows
+// past R hold zeros), and 2 nx of zero pad.
+__device__ __forceinline__ int win_len(int nx, int bt, int slots) {
+  return a4(slots * bt + 3 * nx);
+}
+__device__ __forceinline__ Carve carve(int R, int TM, int N, int nx, int bt, int slots) {
   Carve C;
   int o = 0;
   C.xbar = o;  o += a4(R);            // forward: iterate;     backward: x~
@@ -741,13 +769,26 @@ __device__ __forceinline__ Carve carve(int R, int TM, int N, int nx, int bt) {
   C.xp = o;    o += a4(R);            // QP solution
   C.up = o;    o += a4(TM);
   C.lam = o;   o += a4(R);            // backward: forward multipliers
-  C.w0 = o;    o += a4(R + 2 * nx);
-  C.w1 = o;    o += a4(R + 2 * nx);
-  C.w2 = o;    o += a4(R + 2 * nx);   // low part of a double-float vector in w0
+  const int wl = win_len(nx, bt, slots);
+  C.w0 = o;    o += wl;
+  C.w1 = o;    o += wl;
+  C.w2 = o;    o += wl;               // low part of a double-float vector in w0
   C.piv = o;   o += 4 * bt;
   C.red = o;   o += 128;
   C.ls = o;    o += 4 * (kMaxAlphas + 1) * N + 4 * (kMaxAlphas + 1);   // doubles
   return C;
+}
+
+// Zeroes the pads of the three windows: [0, nx) and [R + nx, window end).
+template <int NX>
+__device__ __forceinline__ void zero_pads(float* smem, const Carve& C, int R, int BT, int slots) {
+  const int wl = win_len(NX, BT, slots);
+  for (int i = threadIdx.x; i < NX + (wl - R - NX); i += BT) {
+    const int o = i < NX ? i : R + i;
+    smem[C.w0 + o] = 0.f;
+    smem[C.w1 + o] = 0.f;
+    smem[C.w2 + o] = 0.f;
+  }
 }
 
 struct Lds {
@@ -761,7 +802,7 @@ struct Lds {
 
 template <int NX>
 __device__ __forceinline__ Lds lds_of(float* smem, const Prob& P) {
-  const Carve C = carve(P.R, P.TM, P.N, NX, blockDim.x);
+  const Carve C = carve(P.R, P.TM, P.N, NX, blockDim.x, P.slots);
   Lds sh;
   sh.w0 = smem + C.w0;
   sh.w1 = smem + C.w1;
@@ -772,13 +813,22 @@ __device__ __forceinline__ Lds lds_of(float* smem, const Prob& P) {
   return sh;
 }
 
-template <int SLOTS>
+// Row guard of slot s.  With FULL (register-resident rows, which are zero
+// past R, as is every vector entry there) every row of every slot runs, with
+// no branch: rows past R compute zeros into the window's tail pad.
+template <bool FULL>
+__device__ __forceinline__ bool row_live(int s, int rho, int R, int BT) {
+  if constexpr (FULL) return true;
+  return rho < R;
+}
+
+template <int SLOTS, bool FULL = false>
 __device__ __forceinline__ void publish(float* w, const float (&v)[SLOTS], int R, int nx) {
   const int tid = threadIdx.x, BT = blockDim.x;
 #pragma unroll
   for (int s = 0; s < SLOTS; ++s) {
     const int rho = tid + s * BT;
-    if (rho < R) w[nx + rho] = v[s];
+    if (row_live<FULL>(s, rho, R, BT)) w[nx + rho] = v[s];
   }
 }
 
@@ -922,13 +972,13 @@ __device__ __forceinline__ float precond_norm(const Prob& P, const Lds& sh,
                                               float (&Ph)[SLOTS][3 * NX], const float (&v)[SLOTS],
                                               int& redi) {
   const int tid = threadIdx.x, BT = blockDim.x, nwv = (BT + 63) >> 6;
-  publish<SLOTS>(sh.w0, v, P.R, NX);
+  publish<SLOTS, REG>(sh.w0, v, P.R, NX);
   __syncthreads();
   float part = 0.f;
 #pragma unroll
   for (int s = 0; s < SLOTS; ++s) {
     const int rho = tid + s * BT;
-    if (rho < P.R) {
+    if (row_live<REG>(s, rho, P.R, BT)) {
       const int t = rho / NX;
       part = fmaf(v[s], row_dot<NX>(coefP<NX, SLOTS, REG>(P, Ph, s, rho), sh.w0 + t * NX), part);
     }
@@ -950,14 +1000,14 @@ __device__ __forceinline__ int pcg(const Prob& P, const Lds& sh, float (&S)[SLOT
     r[s] = rhs[s];
     d[s] = 0.f;
   }
-  publish<SLOTS>(sh.w1, r, R, NX);
+  publish<SLOTS, REG>(sh.w1, r, R, NX);
   __syncthreads();
   float part = 0.f;
 #pragma unroll
   for (int s = 0; s < SLOTS; ++s) {
     const int rho = tid + s * BT;
     z[s] = 0.f;
-    if (rho < R) {
+    if (row_live<REG>(s, rho, R, BT)) {
       const int t = rho / NX;
       z[s] = row_dot<NX>(coefP<NX, SLOTS, REG>(P, Ph, s, rho), sh.w1 + t * NX);
     }
@@ -973,14 +1023,14 @@ __device__ __forceinline__ int pcg(const Prob& P, const Lds& sh, float (&S)[SLOT
   }
   while (it < maxit && eta > thresh) {
     // y = S^ p (line 6), v = p'y (7), alpha = eta / v (8)
-    publish<SLOTS>(sh.w0, p, R, NX);
+    publish<SLOTS, REG>(sh.w0, p, R, NX);
     __syncthreads();
     part = 0.f;
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
       const int rho = tid + s * BT;
       y[s] = 0.f;
-      if (rho < R) {
+      if (row_live<REG>(s, rho, R, BT)) {
         const int t = rho / NX;
         y[s] = row_dot<NX>(coefS<NX, SLOTS, REG>(P, S, s, rho), sh.w0 + t * NX);
       }
@@ -999,14 +1049,14 @@ __device__ __forceinline__ int pcg(const Prob& P, const Lds& sh, float (&S)[SLOT
       r[s] = fmaf(-alpha, y[s], r[s]);
     }
     // r~ = Phi^-1 r (11), eta' = r'r~ (12)
-    publish<SLOTS>(sh.w1, r, R, NX);
+    publish<SLOTS, REG>(sh.w1, r, R, NX);
     __syncthreads();
     part = 0.f;
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
       const int rho = tid + s * BT;
       z[s] = 0.f;
-      if (rho < R) {
+      if (row_live<REG>(s, rho, R, BT)) {
         const int t = rho / NX;
         z[s] = row_dot<NX>(coefP<NX, SLOTS, REG>(P, Ph, s, rho), sh.w1 + t * NX);
       }
@@ -1044,7 +1094,7 @@ __device__ __noinline__ void fwd_begin(const ProbRec* rec, const float* data, co
   extern __shared__ float smem[];
   const int tid = threadIdx.x, BT = blockDim.x;
   const Prob P = make_prob<NX>(*rec, data, ws);
-  const Carve C = carve(P.R, P.TM, P.N, NX, BT);
+  const Carve C = carve(P.R, P.TM, P.N, NX, BT, P.slots);
   float* xbar = smem + C.xbar;
   float* ubar = smem + C.ubar;
   const int T = P.T, m = P.m, R = P.R, TM = P.TM;
@@ -1052,14 +1102,7 @@ __device__ __noinline__ void fwd_begin(const ProbRec* rec, const float* data, co
   const float* solu = solx + R;
   for (int i = tid; i < R; i += BT) xbar[i] = (i < NX) ? P.x0[i] : solx[i];
   for (int i = tid; i < TM; i += BT) ubar[i] = solu[i];
-  if (tid < NX) {
-    smem[C.w0 + tid] = 0.f;
-    smem[C.w0 + R + NX + tid] = 0.f;
-    smem[C.w1 + tid] = 0.f;
-    smem[C.w1 + R + NX + tid] = 0.f;
-    smem[C.w2 + tid] = 0.f;
-    smem[C.w2 + R + NX + tid] = 0.f;
-  }
+  zero_pads<NX>(smem, C, R, BT, P.slots);
   __syncthreads();
   if (init != DMPC_INIT_ROLLOUT) return;
   if (P.dyn == DMPC_DYN_LTV) {
@@ -1103,18 +1146,26 @@ __device__ __noinline__ int fwd_blocks(const ProbRec* rec, const float* data, fl
   extern __shared__ float smem[];
   const int tid = threadIdx.x, BT = blockDim.x;
   const Prob P = make_prob<NX>(*rec, data, ws);
-  const Carve C = carve(P.R, P.TM, P.N, NX, BT);
+  const Carve C = carve(P.R, P.TM, P.N, NX, BT, P.slots);
   form_qp<NX>(P, smem + C.xbar, smem + C.ubar);
   __syncthreads();
+  // rows assembled once per SQP iteration in double: kept for the refinement
+  // residuals (and the backward pass), rounded to float for the PCG
   float* blk = P.W + P.L.blk;
   float* gv = P.W + P.L.g;
+  double* blkd = (double*)(P.W + P.L.blkd);
+  double* gd = (double*)(P.W + P.L.gd);
   for (int rho = tid; rho < P.R; rho += BT) {
     const int t = rho / NX, i = rho - t * NX;
-    float row[3 * NX], g;
-    schur_row<NX, float>(P, t, i, row, g);
+    double row[3 * NX], g;
+    schur_row<NX, double>(P, t, i, row, g);
 #pragma unroll
-    for (int j = 0; j < 3 * NX; ++j) blk[rho * 6 * NX + j] = row[j];
-    gv[rho] = g;
+    for (int j = 0; j < 3 * NX; ++j) {
+      blkd[rho * 3 * NX + j] = row[j];
+      blk[rho * 6 * NX + j] = (float)row[j];
+    }
+    gd[rho] = g;
+    gv[rho] = (float)g;
   }
   __syncthreads();
   const bool bad = precond_rows<NX>(P, smem + C.piv);
@@ -1160,7 +1211,7 @@ __device__ __noinline__ ResNorms fwd_residual64(const ProbRec* rec, const float*
   extern __shared__ float smem[];
   const int tid = threadIdx.x, BT = blockDim.x;
   const Prob P = make_prob<NX>(*rec, data, ws);
-  const Carve C = carve(P.R, P.TM, P.N, NX, BT);
+  const Carve C = carve(P.R, P.TM, P.N, NX, BT, P.slots);
   const float* w0 = smem + C.w0;
   const float* w2 = smem + C.w2;
   float* w1 = smem + C.w1;
@@ -1168,10 +1219,14 @@ __device__ __noinline__ ResNorms fwd_residual64(const ProbRec* rec, const float*
   const float* q = P.W + P.L.q;
   const float* rr = P.W + P.L.r;
   float r2 = 0.f, f2 = 0.f, b2 = 0.f;
+  const double* blkd = (const double*)(P.W + P.L.blkd);
+  const double* gd = (const double*)(P.W + P.L.gd);
   for (int rho = tid; rho < P.R; rho += BT) {
     const int t = rho / NX, i = rho - t * NX;
-    double row[3 * NX], g;
-    schur_row<NX, double>(P, t, i, row, g);
+    double row[3 * NX];
+#pragma unroll
+    for (int j = 0; j < 3 * NX; ++j) row[j] = blkd[rho * 3 * NX + j];
+    const double g = gd[rho];
     const double res = g - row_dot64<NX>(row, w0 + t * NX, w2 + t * NX);
     w1[NX + rho] = (float)res;
     double fl = 0.0;
@@ -1196,7 +1251,7 @@ __device__ __noinline__ int fwd_recover_ls(const ProbRec* rec, const float* data
   extern __shared__ float smem[];
   const int tid = threadIdx.x, BT = blockDim.x, nwv = (BT + 63) >> 6;
   const Prob P = make_prob<NX>(*rec, data, ws);
-  const Carve C = carve(P.R, P.TM, P.N, NX, BT);
+  const Carve C = carve(P.R, P.TM, P.N, NX, BT, P.slots);
   const int T = P.T, N = P.N, m = P.m, R = P.R, TM = P.TM;
   float* xbar = smem + C.xbar;
   float* ubar = smem + C.ubar;
@@ -1205,9 +1260,9 @@ __device__ __noinline__ int fwd_recover_ls(const ProbRec* rec, const float* data
   const float* w0 = smem + C.w0;   // multipliers, high part
   const float* w2 = smem + C.w2;   // low part
   {
-    const float* Qd = P.W + P.L.Qd;
+    const double* iQd = (const double*)(P.W + P.L.iQd);
+    const double* iRd = (const double*)(P.W + P.L.iRd);
     const float* q = P.W + P.L.q;
-    const float* Rd = P.W + P.L.Rd;
     const float* rr = P.W + P.L.r;
     for (int rho = tid; rho < R; rho += BT) {
       const int t = rho / NX, i = rho - t * NX;
@@ -1220,7 +1275,7 @@ __device__ __noinline__ int fwd_recover_ls(const ProbRec* rec, const float* data
         for (int kk = 0; kk < NX; ++kk)
           acc -= ldA<double>(P, a0 + kk * NX + i) * ((double)lh[kk] + (double)ll[kk]);
       }
-      xp[rho] = (float)(-acc / (double)Qd[rho]);
+      xp[rho] = (float)(-acc * iQd[rho]);
     }
     for (int idx = tid; idx < TM; idx += BT) {
       const int t = idx / m, l = idx - t * m;
@@ -1231,7 +1286,7 @@ __device__ __noinline__ int fwd_recover_ls(const ProbRec* rec, const float* data
 #pragma unroll
       for (int kk = 0; kk < NX; ++kk)
         acc -= ldB<double>(P, b0 + kk * m + l) * ((double)lh[kk] + (double)ll[kk]);
-      up[idx] = (float)(-acc / (double)Rd[idx]);
+      up[idx] = (float)(-acc * iRd[idx]);
     }
   }
   __syncthreads();
@@ -1356,7 +1411,7 @@ __device__ __noinline__ int fwd_finish(const ProbRec* rec, const float* data, fl
   extern __shared__ float smem[];
   const int tid = threadIdx.x, BT = blockDim.x;
   const Prob P = make_prob<NX>(*rec, data, ws);
-  const Carve C = carve(P.R, P.TM, P.N, NX, BT);
+  const Carve C = carve(P.R, P.TM, P.N, NX, BT, P.slots);
   const float* xbar = smem + C.xbar;
   const float* ubar = smem + C.ubar;
   float* solx = sol + rec->sol_off;
@@ -1384,16 +1439,9 @@ __device__ __noinline__ void bwd_begin(const ProbRec* rec, const float* data, fl
   extern __shared__ float smem[];
   const int tid = threadIdx.x, BT = blockDim.x;
   const Prob P = make_prob<NX>(*rec, data, ws);
-  const Carve C = carve(P.R, P.TM, P.N, NX, BT);
+  const Carve C = carve(P.R, P.TM, P.N, NX, BT, P.slots);
   const int R = P.R, TM = P.TM;
-  if (tid < NX) {
-    smem[C.w0 + tid] = 0.f;
-    smem[C.w0 + R + NX + tid] = 0.f;
-    smem[C.w1 + tid] = 0.f;
-    smem[C.w1 + R + NX + tid] = 0.f;
-    smem[C.w2 + tid] = 0.f;
-    smem[C.w2 + R + NX + tid] = 0.f;
-  }
+  zero_pads<NX>(smem, C, R, BT, P.slots);
   for (int i = tid; i < R; i += BT) {
     smem[C.xp + i] = P.W[P.L.xp + i];
     smem[C.lam + i] = P.W[P.L.lam + i];
@@ -1402,10 +1450,15 @@ __device__ __noinline__ void bwd_begin(const ProbRec* rec, const float* data, fl
   const float* dlx = dl + rec->sol_off;
   const float* dlu = dlx + R;
   const float* dll = dlu + TM;
+  // adjoint right-hand side in double (the forward's rhs slot is free now),
+  // rounded to float for the PCG
   float* gv = P.W + P.L.g;
+  double* gd = (double*)(P.W + P.L.gd);
   for (int rho = tid; rho < R; rho += BT) {
     const int t = rho / NX, i = rho - t * NX;
-    gv[rho] = adjoint_rhs_row<NX, float>(P, t, i, dlx, dlu, dll);
+    const double g = adjoint_rhs_row<NX, double>(P, t, i, dlx, dlu, dll);
+    gd[rho] = g;
+    gv[rho] = (float)g;
   }
   __syncthreads();
 }
@@ -1419,7 +1472,7 @@ __device__ __noinline__ ResNorms bwd_residual64(const ProbRec* rec, const float*
   extern __shared__ float smem[];
   const int tid = threadIdx.x, BT = blockDim.x;
   const Prob P = make_prob<NX>(*rec, data, ws);
-  const Carve C = carve(P.R, P.TM, P.N, NX, BT);
+  const Carve C = carve(P.R, P.TM, P.N, NX, BT, P.slots);
   const float* w0 = smem + C.w0;
   const float* w2 = smem + C.w2;
   float* w1 = smem + C.w1;
@@ -1428,11 +1481,14 @@ __device__ __noinline__ ResNorms bwd_residual64(const ProbRec* rec, const float*
   const float* dll = dlu + P.TM;
   const int nwv = (BT + 63) >> 6;
   float r2 = 0.f, f2 = 0.f, b2 = 0.f;
+  const double* blkd = (const double*)(P.W + P.L.blkd);
+  const double* gd = (const double*)(P.W + P.L.gd);
   for (int rho = tid; rho < P.R; rho += BT) {
-    const int t = rho / NX, i = rho - t * NX;
-    double row[3 * NX], g0;
-    schur_row<NX, double>(P, t, i, row, g0);
-    const double g = adjoint_rhs_row<NX, double>(P, t, i, dlx, dlu, dll);
+    const int t = rho / NX;
+    double row[3 * NX];
+#pragma unroll
+    for (int j = 0; j < 3 * NX; ++j) row[j] = blkd[rho * 3 * NX + j];
+    const double g = gd[rho];
     const double res = g - row_dot64<NX>(row, w0 + t * NX, w2 + t * NX);
     w1[NX + rho] = (float)res;
     double fl = 0.0;
@@ -1455,7 +1511,7 @@ __device__ __noinline__ void bwd_finish(const ProbRec* rec, const float* data, f
   extern __shared__ float smem[];
   const int tid = threadIdx.x, BT = blockDim.x;
   const Prob P = make_prob<NX>(*rec, data, ws);
-  const Carve C = carve(P.R, P.TM, P.N, NX, BT);
+  const Carve C = carve(P.R, P.TM, P.N, NX, BT, P.slots);
   const int T = P.T, m = P.m, R = P.R, TM = P.TM;
   float* xt = smem + C.xbar;
   float* ut = smem + C.ubar;
@@ -1465,8 +1521,8 @@ __device__ __noinline__ void bwd_finish(const ProbRec* rec, const float* data, f
   const float* w0 = smem + C.w0;
   const float* lw = w0 + NX;                // lambda~, high part (unpadded view)
   const float* lwl = smem + C.w2 + NX;      // low part
-  const float* Qd = P.W + P.L.Qd;
-  const float* Rd = P.W + P.L.Rd;
+  const double* iQd = (const double*)(P.W + P.L.iQd);
+  const double* iRd = (const double*)(P.W + P.L.iRd);
   const float* dlx = dl + rec->sol_off;
   const float* dlu = dlx + R;
   float* ax = adj + rec->sol_off;
@@ -1483,7 +1539,7 @@ __device__ __noinline__ void bwd_finish(const ProbRec* rec, const float* data, f
       for (int kk = 0; kk < NX; ++kk)
         acc += ldA<double>(P, a0 + kk * NX + i) * ((double)lh[kk] + (double)ll[kk]);
     }
-    const float v = (float)(acc / (double)Qd[rho]);
+    const float v = (float)(acc * iQd[rho]);
     xt[rho] = v;
     ax[rho] = v;
     al[rho] = lw[rho];
@@ -1497,7 +1553,7 @@ __device__ __noinline__ void bwd_finish(const ProbRec* rec, const float* data, f
 #pragma unroll
     for (int kk = 0; kk < NX; ++kk)
       acc += ldB<double>(P, b0 + kk * m + l) * ((double)lh[kk] + (double)ll[kk]);
-    const float v = (float)(acc / (double)Rd[idx]);
+    const float v = (float)(acc * iRd[idx]);
     ut[idx] = v;
     au[idx] = v;
   }

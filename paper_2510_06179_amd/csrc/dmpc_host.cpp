@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cstdio>
+#include <mutex>
 #include <string>
 #include <cmath>
 #include <cstring>
@@ -23,7 +25,14 @@ struct dmpc_handle {
 struct Group {
   LaunchCfg cfg;
   int first, count;
+  double work;     // estimated cost: sum over its problems of (T+1) nx^2
+  int lane;        // side stream it runs on in a batched call
 };
+
+// Groups of one batched call run concurrently on up to kLanes side streams
+// (fork/join through events on the caller's stream), heaviest first onto the
+// least-loaded stream.  Four matches the hardware queues a process gets.
+constexpr int kLanes = 4;
 
 struct dmpc_plan {
   dmpc_handle* h;
@@ -35,6 +44,10 @@ struct dmpc_plan {
   ProbRec* d_recs;
   size_t ws_bytes;
   dmpc_opts opts;
+  int lanes = 0;                       // side streams (0: launch on the caller's stream)
+  hipStream_t side[kLanes] = {};
+  hipEvent_t joined[kLanes] = {};
+  hipEvent_t fork = nullptr;
 };
 
 namespace dmpc {
@@ -129,7 +142,26 @@ const Variant kVariants[] = {
     {4, 256, 0}, {8, 256, 0}, {8, 512, 0},
 };
 
+// Process-wide tuning table (rows of 7 int32, see dmpc_set_tuning).
+std::mutex g_tune_mu;
+std::vector<std::array<int32_t, 7>> g_tune;
+
+bool tuned_cfg(const dmpc_problem& p, LaunchCfg* c) {
+  const int64_t R = (int64_t)(p.T + 1) * p.nx;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const auto& r : g_tune) {
+    if (r[0] != p.nx || p.T < r[1] || p.T > r[2]) continue;
+    const int slots = r[3], maxbt = r[4], reg = r[5], bt = r[6];
+    if (!kernel_available(p.nx, slots, maxbt, reg)) continue;
+    if ((int64_t)slots * bt < R) continue;
+    *c = LaunchCfg{p.nx, slots, maxbt, reg, bt, 0, 0};
+    return true;
+  }
+  return false;
+}
+
 bool choose_cfg(const dmpc_problem& p, int force_bt, LaunchCfg* c) {
+  if (force_bt == 0 && tuned_cfg(p, c)) return true;
   const int64_t R = (int64_t)(p.T + 1) * p.nx;
   const double per_row = 6.0 * p.nx + 10.0, per_wave = 100.0;
   double best = 1e300;
@@ -231,6 +263,60 @@ const char* dmpc_status_string(dmpc_status s) {
 }
 
 int32_t dmpc_version(void) { return 100; }
+
+int32_t dmpc_list_variants(int32_t* out, int32_t max_rows) {
+  int32_t n = 0;
+  for (int nx : kStateSizes)
+    for (const Variant& v : kVariants) {
+      if (!kernel_available(nx, v.slots, v.maxbt, v.reg)) continue;
+      if (out && n < max_rows) {
+        out[4 * n] = nx;
+        out[4 * n + 1] = v.slots;
+        out[4 * n + 2] = v.maxbt;
+        out[4 * n + 3] = v.reg;
+      }
+      ++n;
+    }
+  return n;
+}
+
+dmpc_status dmpc_set_tuning(const int32_t* rows, int32_t n_rows) {
+  if (n_rows < 0 || (n_rows > 0 && !rows)) return DMPC_ERR_INVALID_ARG;
+  std::vector<std::array<int32_t, 7>> t(n_rows);
+  for (int i = 0; i < n_rows; ++i) {
+    for (int j = 0; j < 7; ++j) t[i][j] = rows[7 * i + j];
+    const auto& r = t[i];
+    if (!nx_supported(r[0]) || r[1] < 1 || r[2] < r[1] || r[3] < 1 || r[4] < 64 ||
+        r[4] > 1024 || (r[5] != 0 && r[5] != 1) || r[6] < 64 || r[6] > r[4] || r[6] % 64 != 0)
+      return DMPC_ERR_INVALID_ARG;
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.swap(t);
+  return DMPC_OK;
+}
+
+dmpc_status dmpc_choose_mapping(const dmpc_problem* problem, const dmpc_opts* opts, int32_t* out) {
+  if (!problem || !out) return DMPC_ERR_INVALID_ARG;
+  dmpc_status st = check_opts(opts);
+  if (st != DMPC_OK) return st;
+  if (problem->T < 1 || problem->nx < 1 || problem->nu < 1) return DMPC_ERR_INVALID_ARG;
+  LaunchCfg c;
+  if (!nx_supported(problem->nx) || !choose_cfg(*problem, opts->block_threads, &c))
+    return DMPC_ERR_UNSUPPORTED;
+  out[0] = c.slots;
+  out[1] = c.maxbt;
+  out[2] = c.reg;
+  out[3] = c.bt;
+  return DMPC_OK;
+}
+
+int32_t dmpc_get_tuning(int32_t* rows, int32_t max_rows) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  const int32_t n = (int32_t)g_tune.size();
+  for (int i = 0; i < n && i < max_rows && rows; ++i)
+    for (int j = 0; j < 7; ++j) rows[7 * i + j] = g_tune[i][j];
+  return n;
+}
 
 dmpc_status dmpc_validate(const dmpc_problem* problems, int32_t count, int64_t data_len,
                           int64_t sol_len, const dmpc_opts* opts, int32_t* bad_index) {
@@ -355,6 +441,7 @@ dmpc_status dmpc_plan_create(dmpc_handle* h, const dmpc_problem* problems, int32
     r.x0_off = p.x0_off;
     r.sol_off = p.sol_off;
     r.ws_off = ws_off;
+    r.slots = cfg[i].slots;
     ws_off += ws_layout(p.T, p.nx, p.nu, p.dyn).total;
     pl->recs[k] = r;
     pl->pos[i] = k;
@@ -363,12 +450,15 @@ dmpc_status dmpc_plan_create(dmpc_handle* h, const dmpc_problem* problems, int32
       g.cfg = cfg[i];
       g.first = k;
       g.count = 0;
+      g.work = 0.0;
+      g.lane = 0;
       g.cfg.lds_bytes = 0;
       pl->groups.push_back(g);
     }
     Group& g = pl->groups.back();
     g.count += 1;
-    g.cfg.lds_bytes = std::max(g.cfg.lds_bytes, (size_t)lds_floats(p.T, p.nx, p.nu, g.cfg.bt) * sizeof(float));
+    g.cfg.lds_bytes = std::max(g.cfg.lds_bytes, (size_t)lds_floats(p.T, p.nx, p.nu, g.cfg.bt, g.cfg.slots) * sizeof(float));
+    g.work += (double)(p.T + 1) * p.nx * p.nx;
     pl->grp[k] = (int)pl->groups.size() - 1;
   }
   pl->ws_bytes = (size_t)ws_off * sizeof(float);
@@ -397,6 +487,33 @@ dmpc_status dmpc_plan_create(dmpc_handle* h, const dmpc_problem* problems, int32
       delete pl;
       return DMPC_ERR_HIP;
     }
+    if (pl->groups.size() > 1) {
+      // longest-processing-time assignment of groups to side streams
+      const int lanes = std::min<int>(kLanes, (int)pl->groups.size());
+      std::vector<int> gi(pl->groups.size());
+      for (size_t g = 0; g < gi.size(); ++g) gi[g] = (int)g;
+      std::stable_sort(gi.begin(), gi.end(), [&](int a, int b) {
+        return pl->groups[a].work > pl->groups[b].work;
+      });
+      double load[kLanes] = {0, 0, 0, 0};
+      for (int g : gi) {
+        int best = 0;
+        for (int l = 1; l < lanes; ++l)
+          if (load[l] < load[best]) best = l;
+        pl->groups[g].lane = best;
+        load[best] += pl->groups[g].work;
+      }
+      bool ok = hipEventCreateWithFlags(&pl->fork, hipEventDisableTiming) == hipSuccess;
+      for (int l = 0; l < lanes && ok; ++l)
+        ok = hipStreamCreateWithFlags(&pl->side[l], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&pl->joined[l], hipEventDisableTiming) == hipSuccess;
+      pl->lanes = lanes;
+      if (!ok) {
+        dmpc_plan_destroy(pl);
+        hipSetDevice(prev);
+        return DMPC_ERR_HIP;
+      }
+    }
     hipSetDevice(prev);
   }
   *plan = pl;
@@ -423,12 +540,12 @@ dmpc_status dmpc_plan_describe(const dmpc_plan* plan, char* buf, size_t len) {
   std::string s = "[";
   for (size_t g = 0; g < plan->groups.size(); ++g) {
     const LaunchCfg& c = plan->groups[g].cfg;
-    char tmp[192];
+    char tmp[256];
     std::snprintf(tmp, sizeof(tmp),
                   "%s{\"nx\": %d, \"slots\": %d, \"block_threads\": %d, \"launch_bound\": %d, "
-                  "\"register_rows\": %d, \"problems\": %d, \"lds_bytes\": %zu}",
+                  "\"register_rows\": %d, \"problems\": %d, \"lds_bytes\": %zu, \"stream\": %d}",
                   g ? ", " : "", c.nx, c.slots, c.bt, c.maxbt, c.reg, plan->groups[g].count,
-                  c.lds_bytes);
+                  c.lds_bytes, plan->lanes ? plan->groups[g].lane : -1);
     s += tmp;
   }
   s += "]";
@@ -438,6 +555,11 @@ dmpc_status dmpc_plan_describe(const dmpc_plan* plan, char* buf, size_t len) {
 
 dmpc_status dmpc_plan_destroy(dmpc_plan* plan) {
   if (!plan) return DMPC_OK;
+  for (int l = 0; l < kLanes; ++l) {
+    if (plan->side[l]) hipStreamDestroy(plan->side[l]);
+    if (plan->joined[l]) hipEventDestroy(plan->joined[l]);
+  }
+  if (plan->fork) hipEventDestroy(plan->fork);
   if (plan->d_recs) hipFree(plan->d_recs);
   delete plan;
   return DMPC_OK;
@@ -464,12 +586,31 @@ static dmpc_status run(dmpc_plan* pl, int index, bool fwd, const float* data, fl
     a.first = k;
     a.count = 1;
     rc = fwd ? launch_forward(c, a, stream) : launch_backward(c, a, stream);
-  } else {
+  } else if (pl->lanes == 0) {
     for (const Group& g : pl->groups) {
       a.first = g.first;
       a.count = g.count;
       rc = fwd ? launch_forward(g.cfg, a, stream) : launch_backward(g.cfg, a, stream);
       if (rc != 0) break;
+    }
+  } else {
+    // fork: every side stream waits for the caller's stream; join: the
+    // caller's stream waits for every side stream
+    hipStream_t st = (hipStream_t)stream;
+    if (hipEventRecord(pl->fork, st) != hipSuccess) rc = -2;
+    for (int l = 0; l < pl->lanes && rc == 0; ++l)
+      if (hipStreamWaitEvent(pl->side[l], pl->fork, 0) != hipSuccess) rc = -2;
+    for (const Group& g : pl->groups) {
+      if (rc != 0) break;
+      a.first = g.first;
+      a.count = g.count;
+      hipStream_t ls = pl->side[g.lane];
+      rc = fwd ? launch_forward(g.cfg, a, ls) : launch_backward(g.cfg, a, ls);
+    }
+    for (int l = 0; l < pl->lanes; ++l) {
+      if (hipEventRecord(pl->joined[l], pl->side[l]) != hipSuccess ||
+          hipStreamWaitEvent(st, pl->joined[l], 0) != hipSuccess)
+        rc = rc ? rc : -2;
     }
   }
   if (prev != pl->h->device) hipSetDevice(prev);

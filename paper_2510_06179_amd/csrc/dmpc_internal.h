@@ -27,16 +27,21 @@ struct ProbRec {
   int32_t T, nx, nu, dyn, cost, phases, nw, index;  // index: slot in status/info
   int64_t dyn_off, cost_off, x0_off, sol_off;
   int64_t ws_off;                                   // float offset into the workspace
-  int64_t pad[3];
+  int32_t slots;                                    // rows per thread of its kernel
+  int32_t pad0;
+  int64_t pad[2];
 };
 
 // Per-problem workspace layout (float offsets from ProbRec::ws_off).
 struct WsLayout {
   int64_t Qd, iQ, q, Rd, iR, r;   // projected Hessian diagonals, inverses, linear terms
+  int64_t iQd, iRd;               // the inverses in double (float offsets, 8-byte aligned)
   int64_t A, B, c;                // linearised dynamics (nonlinear models only)
   int64_t Ad, Bd, cd;             // the same in double (float offsets, 8-byte aligned)
   int64_t Dinv;                   // diagonal Schur blocks inverted [N][nx][nx]
   int64_t blk;                    // saved rows of S^ and Phi^-1: [N*nx][6*nx]
+  int64_t blkd;                   // the rows of S^ in double: [N*nx][3*nx] (float offset)
+  int64_t gd;                     // right-hand side of the Schur system in double [N*nx]
   int64_t xp, up, lam;            // last QP solution and multipliers
   int64_t xlin, ulin;             // last linearisation point
   int64_t g;                      // right-hand side of the Schur system [N*nx]
@@ -56,6 +61,9 @@ DMPC_HD inline WsLayout ws_layout(int T, int nx, int nu, int dyn) {
   L.iR = o; o += TM;
   L.r = o; o += TM;
   o = align_up(o, 4);
+  L.iQd = o; o += 2 * R;
+  L.iRd = o; o += 2 * TM;
+  o = align_up(o, 4);
   if (dyn != DMPC_DYN_LTV) {
     L.A = o; o += (int64_t)T * nx * nx;
     L.B = o; o += (int64_t)T * nx * nu;
@@ -71,6 +79,9 @@ DMPC_HD inline WsLayout ws_layout(int T, int nx, int nu, int dyn) {
   L.Dinv = o; o += N * nx * nx;
   o = align_up(o, 4);
   L.blk = o; o += R * 6 * nx;
+  o = align_up(o, 4);
+  L.blkd = o; o += 2 * R * 3 * nx;
+  L.gd = o; o += 2 * R;
   L.xp = o; o += R;
   L.up = o; o += TM;
   L.lam = o; o += R;
@@ -99,10 +110,10 @@ DMPC_HD inline int64_t sol_block_len(int T, int nx, int nu) {
 // (must match the device-side carve in dmpc_device.h: every region rounded up
 // to 4 floats)
 DMPC_HD inline int64_t a4h(int64_t v) { return (v + 3) / 4 * 4; }
-DMPC_HD inline int64_t lds_floats(int T, int nx, int nu, int bt) {
+DMPC_HD inline int64_t lds_floats(int T, int nx, int nu, int bt, int slots) {
   const int64_t N = T + 1, R = N * nx, TM = (int64_t)T * nu;
   return 3 * a4h(R) + 2 * a4h(TM)        // iterate / QP solution / multipliers
-         + 3 * a4h(R + 2 * nx)           // three padded windows
+         + 3 * a4h((int64_t)slots * bt + 3 * nx)   // three padded windows
          + 4 * (int64_t)bt               // Gauss-Jordan pivot rows, double buffered
          + 128                           // reductions
          + 4 * (kMaxAlphas + 1) * N      // line-search stage costs and defects (double)

@@ -317,6 +317,7 @@ bool dmpc_server::launch_group(Slot* s) {
     rec.x0_off = ss.p.x0_off;
     rec.sol_off = ss.p.sol_off;
     rec.ws_off = ws_off;
+    rec.slots = ss.cfg.slots;
     ws_off += ss.ws_floats;
     if (r.has_x0) {
       segs.push_back(Seg{(const uint32_t*)(s->d_in + pay), (uint32_t*)(d_data + ss.p.x0_off), ss.p.nx});
@@ -383,7 +384,7 @@ bool dmpc_server::launch_group(Slot* s) {
     g.count += 1;
     g.nbwd += s->reqs[k].backward ? 1 : 0;
     g.cfg.lds_bytes = std::max(g.cfg.lds_bytes,
-                               (size_t)lds_floats(ss.p.T, ss.p.nx, ss.p.nu, g.cfg.bt) * sizeof(float));
+                               (size_t)lds_floats(ss.p.T, ss.p.nx, ss.p.nu, g.cfg.bt, g.cfg.slots) * sizeof(float));
   }
   for (const Range& g : ranges) {
     LaunchCfg c = g.cfg;
@@ -642,7 +643,8 @@ dmpc_status dmpc_server_add_session(dmpc_server* sv, int32_t session, const dmpc
   if (st != DMPC_OK) return st;
   LaunchCfg c;
   if (!nx_supported(p.nx) || !choose_cfg(p, sv->cfg.opts.block_threads, &c)) return DMPC_ERR_UNSUPPORTED;
-  if ((size_t)lds_floats(p.T, p.nx, p.nu, c.bt) * sizeof(float) > 160 * 1024) return DMPC_ERR_UNSUPPORTED;
+  if ((size_t)lds_floats(p.T, p.nx, p.nu, c.bt, c.slots) * sizeof(float) > 160 * 1024)
+    return DMPC_ERR_UNSUPPORTED;
   const int64_t ws = ws_layout(p.T, p.nx, p.nu, p.dyn).total;
   if (4 * ws > sv->ws_share) return DMPC_ERR_NOMEM;
   std::lock_guard<std::mutex> lk(sv->mu);

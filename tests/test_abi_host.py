@@ -144,3 +144,77 @@ def test_pack_roundtrip():
         assert np.array_equal(g["A"], p["A"].astype(np.float32))
         assert np.array_equal(g["Rd"], p["Rd"].astype(np.float32))
         assert np.array_equal(g["x0"], p["x0"].astype(np.float32))
+
+
+# ---------------------------------------------------------------------------
+# kernel mapping: variants, cost model, tuning table (host only)
+# ---------------------------------------------------------------------------
+def _mapping(p, **opts):
+    from paper_2510_06179_amd import batch as bt
+    pk = bt.pack([p])
+    d = pk.descs[0]
+    desc = _lib.Problem(*[d[n].item() for n in _lib.PROBLEM_DTYPE.names])
+    o = _lib.make_opts(**opts)
+    out = np.zeros(4, np.int32)
+    rc = _lib.load().dmpc_choose_mapping(ctypes.byref(desc), ctypes.byref(o), out.ctypes.data)
+    return rc, tuple(int(v) for v in out)
+
+
+def test_variants_cover_every_state_size():
+    v = _lib.variants()
+    assert {r[0] for r in v} == {2, 3, 4, 8, 12, 16}
+    for nx, slots, maxbt, reg in v:
+        assert slots >= 1 and maxbt in (64, 128, 256, 512, 1024) and reg in (0, 1)
+
+
+def test_mapping_holds_the_rows_and_respects_forced_threads():
+    saved = _saved_tuning()
+    try:
+        _lib.install_tuning([])
+        rng = np.random.default_rng(0)
+        for T in (16, 50, 128):
+            for nx in (4, 8, 12, 16):
+                rc, (slots, maxbt, reg, bt) = _mapping(W.ltv_problem(rng, T, nx, 2))
+                assert rc == _lib.DMPC_OK
+                assert slots * bt >= (T + 1) * nx and bt % 64 == 0 and bt <= maxbt
+        rc, m = _mapping(W.cartpole_batch(0, batch=1)[0], block_threads=128)
+        assert rc == _lib.DMPC_OK and m[3] == 128
+    finally:
+        _lib.install_tuning(saved)
+
+
+def _saved_tuning():
+    lib = _lib.load()
+    n = lib.dmpc_get_tuning(None, 0)
+    rows = np.zeros((max(n, 1), 7), np.int32)
+    lib.dmpc_get_tuning(rows.ctypes.data, n)
+    return [tuple(int(v) for v in r) for r in rows[:n]]
+
+
+def test_tuning_table_overrides_the_cost_model():
+    saved = _saved_tuning()
+    try:
+        p = W.cartpole_batch(0, batch=1)[0]          # nx=4, T=50: 204 rows
+        _lib.install_tuning([(4, 40, 60, 1, 256, 1, 256)])
+        assert _mapping(p)[1] == (1, 256, 1, 256)
+        assert _saved_tuning() == [(4, 40, 60, 1, 256, 1, 256)]
+        # a row that cannot hold the problem is skipped
+        _lib.install_tuning([(4, 40, 60, 1, 128, 1, 128)])
+        rc, m = _mapping(p)
+        assert rc == _lib.DMPC_OK and m[0] * m[3] >= 204 and m != (1, 128, 1, 128)
+        # outside the T range the cost model decides
+        _lib.install_tuning([])
+        model = _mapping(p)[1]
+        _lib.install_tuning([(4, 1, 10, 1, 256, 1, 256)])
+        assert _mapping(p)[1] == model
+        # forcing the threads per workgroup bypasses the table
+        _lib.install_tuning([(4, 40, 60, 1, 256, 1, 256)])
+        assert _mapping(p, block_threads=64)[1][3] == 64
+        # malformed rows are refused and leave the table as it was
+        for bad in [(5, 1, 9, 1, 64, 1, 64), (4, 9, 1, 1, 64, 1, 64), (4, 1, 9, 1, 64, 2, 64),
+                    (4, 1, 9, 1, 64, 1, 96), (4, 1, 9, 1, 64, 1, 128)]:
+            with pytest.raises(_lib.DmpcError):
+                _lib.install_tuning([bad])
+        assert _saved_tuning() == [(4, 40, 60, 1, 256, 1, 256)]
+    finally:
+        _lib.install_tuning(saved)
