@@ -120,7 +120,7 @@ typedef struct dmpc_opts {
   float refine_tol;         /* relative tolerance of each refinement correction, relative
                                to the residual it corrects (0 = the pass's tol; default 1e-2) */
   float kkt_tol;            /* refinement stops once ||residual||_2 <= kkt_tol * ||KKT
-                               right-hand side||_2 or the float32 floor (default 1e-6) */
+                               right-hand side||_2 (default 1e-6) */
 } dmpc_opts;
 
 /* Fills *o with the defaults: 1 SQP iteration, PCG tol 1e-6, up to three

@@ -108,6 +108,12 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise DmpcError(f"{LIB_PATH} is missing: run `python -m paper_2510_06179_amd.build`")
+    # PyTorch ships its own HIP runtime; loading it first makes the library
+    # bind to that one instead of bringing a second runtime into the process.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     P = ctypes.POINTER

@@ -775,7 +775,7 @@ __device__ __forceinline__ Carve carve(int R, int TM, int N, int nx, int bt, int
   C.w2 = o;    o += wl;               // low part of a double-float vector in w0
   C.piv = o;   o += 4 * bt;
   C.red = o;   o += 128;
-  C.ls = o;    o += 4 * (kMaxAlphas + 1) * N + 4 * (kMaxAlphas + 1);   // doubles
+  C.ls = o;    o += (int)ls_floats(N, R, TM);   // doubles
   return C;
 }
 
@@ -1149,96 +1149,122 @@ __device__ __noinline__ int fwd_blocks(const ProbRec* rec, const float* data, fl
   const Carve C = carve(P.R, P.TM, P.N, NX, BT, P.slots);
   form_qp<NX>(P, smem + C.xbar, smem + C.ubar);
   __syncthreads();
-  // rows assembled once per SQP iteration in double: kept for the refinement
-  // residuals (and the backward pass), rounded to float for the PCG
   float* blk = P.W + P.L.blk;
   float* gv = P.W + P.L.g;
-  double* blkd = (double*)(P.W + P.L.blkd);
-  double* gd = (double*)(P.W + P.L.gd);
   for (int rho = tid; rho < P.R; rho += BT) {
     const int t = rho / NX, i = rho - t * NX;
-    double row[3 * NX], g;
-    schur_row<NX, double>(P, t, i, row, g);
+    float row[3 * NX], g;
+    schur_row<NX, float>(P, t, i, row, g);
 #pragma unroll
-    for (int j = 0; j < 3 * NX; ++j) {
-      blkd[rho * 3 * NX + j] = row[j];
-      blk[rho * 6 * NX + j] = (float)row[j];
-    }
-    gd[rho] = g;
-    gv[rho] = (float)g;
+    for (int j = 0; j < 3 * NX; ++j) blk[rho * 6 * NX + j] = row[j];
+    gv[rho] = g;
   }
   __syncthreads();
   const bool bad = precond_rows<NX>(P, smem + C.piv);
   return __syncthreads_or(bad ? 1 : 0);
 }
 
-// Squared norms that steer the refinement: of the residual, of its float32
-// floor (unit roundoff times |S^| |lambda| row by row) and of the KKT
+// Squared norms that steer the refinement: of the residual and of the KKT
 // right-hand side the residual is measured against.
 struct ResNorms {
-  float r2, floor2, rhs2;
+  float r2, rhs2;
 };
 
-__device__ __forceinline__ ResNorms block_sum3(float a, float b, float c, float* red, int nwv) {
+__device__ __forceinline__ ResNorms block_sum2(float a, float b, float* red, int nwv) {
   a = wave_sum(a);
   b = wave_sum(b);
-  c = wave_sum(c);
-  ResNorms n{a, b, c};
+  ResNorms n{a, b};
   if (nwv == 1) return n;
   if ((threadIdx.x & 63) == 0) {
     const int w = threadIdx.x >> 6;
-    red[3 * w] = a;
-    red[3 * w + 1] = b;
-    red[3 * w + 2] = c;
+    red[2 * w] = a;
+    red[2 * w + 1] = b;
   }
   __syncthreads();
-  n = ResNorms{0.f, 0.f, 0.f};
+  n = ResNorms{0.f, 0.f};
   for (int w = 0; w < nwv; ++w) {
-    n.r2 += red[3 * w];
-    n.floor2 += red[3 * w + 1];
-    n.rhs2 += red[3 * w + 2];
+    n.r2 += red[2 * w];
+    n.rhs2 += red[2 * w + 1];
   }
   return n;
 }
 
-// Residual of the Schur system with every row and the right-hand side
-// re-assembled and accumulated in double: r = g - S^ lambda, lambda = w0 + w2
-// (double-float), result (rounded to float) written to w1[NX + rho].  Returns
-// the norms of r, of its float32 floor and of the KKT right-hand side
-// [-b; d] = [-(q, r); (x_s, c)] (Eq. ocp:KKT), identical in every thread.
+// Residual of the Schur system in double, r = g - S^ lambda with lambda = w0
+// + w2 (double-float), in factored form: with the primal point of the
+// multipliers (Eq. schur:xu)
+//   x_t = -Q_t^-1 (q_t + lambda_t - A_t' lambda_{t+1}),  u_t = -R_t^-1 (r_t - B_t' lambda_{t+1}),
+// the rows of g - S^ lambda are the dynamics defects of that point:
+//   r_0 = x_0 - x_s,   r_{t+1} = x_{t+1} - A_t x_t - B_t u_t - c_t
+// (expand S^ = H G^-1 H' and g = -gamma: the q, r terms cancel).  This needs
+// O(nx + nu) work per row instead of re-assembling the rows of S^.  Result
+// (rounded to float) to w1[NX + rho]; returns the norms of r and of the KKT
+// right-hand side [-b; d] = [-(q, r); (x_s, c)] (Eq. ocp:KKT), identical in
+// every thread.
 template <int NX>
 __device__ __noinline__ ResNorms fwd_residual64(const ProbRec* rec, const float* data, float* ws) {
   extern __shared__ float smem[];
   const int tid = threadIdx.x, BT = blockDim.x;
   const Prob P = make_prob<NX>(*rec, data, ws);
   const Carve C = carve(P.R, P.TM, P.N, NX, BT, P.slots);
-  const float* w0 = smem + C.w0;
-  const float* w2 = smem + C.w2;
+  const int T = P.T, m = P.m, R = P.R, TM = P.TM;
+  const float* w0 = smem + C.w0 + NX;   // lambda, high part (unpadded view)
+  const float* w2 = smem + C.w2 + NX;   // low part
   float* w1 = smem + C.w1;
+  double* xz = (double*)(smem + C.ls);  // primal point of lambda: x [R], u [TM]
+  double* uz = xz + R;
   const int nwv = (BT + 63) >> 6;
   const float* q = P.W + P.L.q;
   const float* rr = P.W + P.L.r;
-  float r2 = 0.f, f2 = 0.f, b2 = 0.f;
-  const double* blkd = (const double*)(P.W + P.L.blkd);
-  const double* gd = (const double*)(P.W + P.L.gd);
-  for (int rho = tid; rho < P.R; rho += BT) {
+  const double* iQd = (const double*)(P.W + P.L.iQd);
+  const double* iRd = (const double*)(P.W + P.L.iRd);
+  for (int rho = tid; rho < R; rho += BT) {
     const int t = rho / NX, i = rho - t * NX;
-    double row[3 * NX];
+    double acc = (double)q[rho] + ((double)w0[rho] + (double)w2[rho]);
+    if (t < T) {
+      const int a0 = t * NX * NX;
 #pragma unroll
-    for (int j = 0; j < 3 * NX; ++j) row[j] = blkd[rho * 3 * NX + j];
-    const double g = gd[rho];
-    const double res = g - row_dot64<NX>(row, w0 + t * NX, w2 + t * NX);
+      for (int k = 0; k < NX; ++k)
+        acc -= ldA<double>(P, a0 + k * NX + i) *
+               ((double)w0[(t + 1) * NX + k] + (double)w2[(t + 1) * NX + k]);
+    }
+    xz[rho] = -acc * iQd[rho];
+  }
+  for (int idx = tid; idx < TM; idx += BT) {
+    const int t = idx / m, l = idx - t * m;
+    const int b0 = t * NX * m;
+    double acc = (double)rr[idx];
+#pragma unroll
+    for (int k = 0; k < NX; ++k)
+      acc -= ldB<double>(P, b0 + k * m + l) *
+             ((double)w0[(t + 1) * NX + k] + (double)w2[(t + 1) * NX + k]);
+    uz[idx] = -acc * iRd[idx];
+  }
+  __syncthreads();
+  float r2 = 0.f, b2 = 0.f;
+  for (int rho = tid; rho < R; rho += BT) {
+    const int t = rho / NX, i = rho - t * NX;
+    double res;
+    float dv;
+    if (t == 0) {
+      dv = P.x0[i];
+      res = xz[i] - (double)dv;
+    } else {
+      const int tt = t - 1;
+      dv = P.c[tt * NX + i];
+      double acc = ldc<double>(P, tt * NX + i);
+#pragma unroll
+      for (int j = 0; j < NX; ++j) acc += ldA<double>(P, tt * NX * NX + i * NX + j) * xz[tt * NX + j];
+      for (int l = 0; l < m; ++l) acc += ldB<double>(P, tt * NX * m + i * m + l) * uz[tt * m + l];
+      res = xz[rho] - acc;
+    }
     w1[NX + rho] = (float)res;
-    double fl = 0.0;
-#pragma unroll
-    for (int j = 0; j < 3 * NX; ++j) fl += fabs(row[j] * (double)w0[t * NX + j]);
-    const float dv = (t == 0) ? P.x0[i] : P.c[(t - 1) * NX + i];
     r2 += (float)(res * res);
-    f2 += (float)(fl * fl);
     b2 += q[rho] * q[rho] + dv * dv;
   }
-  for (int idx = tid; idx < P.TM; idx += BT) b2 += rr[idx] * rr[idx];
-  return block_sum3(r2, f2, b2, smem + C.red, nwv);
+  for (int idx = tid; idx < TM; idx += BT) b2 += rr[idx] * rr[idx];
+  const ResNorms n = block_sum2(r2, b2, smem + C.red, nwv);
+  __syncthreads();   // xz is the line search's region
+  return n;
 }
 
 // QP primal solution (Eq. schur:xu, user signs; accumulated in double):
@@ -1450,22 +1476,21 @@ __device__ __noinline__ void bwd_begin(const ProbRec* rec, const float* data, fl
   const float* dlx = dl + rec->sol_off;
   const float* dlu = dlx + R;
   const float* dll = dlu + TM;
-  // adjoint right-hand side in double (the forward's rhs slot is free now),
-  // rounded to float for the PCG
   float* gv = P.W + P.L.g;
-  double* gd = (double*)(P.W + P.L.gd);
   for (int rho = tid; rho < R; rho += BT) {
     const int t = rho / NX, i = rho - t * NX;
-    const double g = adjoint_rhs_row<NX, double>(P, t, i, dlx, dlu, dll);
-    gd[rho] = g;
-    gv[rho] = (float)g;
+    gv[rho] = (float)adjoint_rhs_row<NX, double>(P, t, i, dlx, dlu, dll);
   }
   __syncthreads();
 }
 
-// Residual of the adjoint Schur system in double: g~ - S^ lambda~ with
-// lambda~ = w0 + w2, result to w1; norms as for the forward residual, the
-// right-hand side being the adjoint's (dl/dz, dl/dlambda) (Eq. ocp:backward).
+// Residual of the adjoint Schur system in double, g~ - S^ lambda~ with
+// lambda~ = w0 + w2, in factored form as for the forward residual: with the
+// adjoint primal point of Alg. backward
+//   x~_t = Q_t^-1 (dl/dx_t - lambda~_t + A_t' lambda~_{t+1}),  u~_t = R_t^-1 (dl/du_t + B_t' lambda~_{t+1})
+// the rows are  r_0 = x~_0 - dl/dlambda_0,
+//   r_{t+1} = x~_{t+1} - A_t x~_t - B_t u~_t - dl/dlambda_{t+1}.
+// Result to w1; norms of r and of the adjoint right-hand side (dl/dz, dl/dlambda).
 template <int NX>
 __device__ __noinline__ ResNorms bwd_residual64(const ProbRec* rec, const float* data, float* ws,
                                                 const float* dl) {
@@ -1473,33 +1498,60 @@ __device__ __noinline__ ResNorms bwd_residual64(const ProbRec* rec, const float*
   const int tid = threadIdx.x, BT = blockDim.x;
   const Prob P = make_prob<NX>(*rec, data, ws);
   const Carve C = carve(P.R, P.TM, P.N, NX, BT, P.slots);
-  const float* w0 = smem + C.w0;
-  const float* w2 = smem + C.w2;
+  const int T = P.T, m = P.m, R = P.R, TM = P.TM;
+  const float* w0 = smem + C.w0 + NX;
+  const float* w2 = smem + C.w2 + NX;
   float* w1 = smem + C.w1;
+  double* xz = (double*)(smem + C.ls);
+  double* uz = xz + R;
   const float* dlx = dl + rec->sol_off;
-  const float* dlu = dlx + P.R;
-  const float* dll = dlu + P.TM;
+  const float* dlu = dlx + R;
+  const float* dll = dlu + TM;
+  const double* iQd = (const double*)(P.W + P.L.iQd);
+  const double* iRd = (const double*)(P.W + P.L.iRd);
   const int nwv = (BT + 63) >> 6;
-  float r2 = 0.f, f2 = 0.f, b2 = 0.f;
-  const double* blkd = (const double*)(P.W + P.L.blkd);
-  const double* gd = (const double*)(P.W + P.L.gd);
-  for (int rho = tid; rho < P.R; rho += BT) {
-    const int t = rho / NX;
-    double row[3 * NX];
+  for (int rho = tid; rho < R; rho += BT) {
+    const int t = rho / NX, i = rho - t * NX;
+    double acc = (double)dlx[rho] - ((double)w0[rho] + (double)w2[rho]);
+    if (t < T) {
+      const int a0 = t * NX * NX;
 #pragma unroll
-    for (int j = 0; j < 3 * NX; ++j) row[j] = blkd[rho * 3 * NX + j];
-    const double g = gd[rho];
-    const double res = g - row_dot64<NX>(row, w0 + t * NX, w2 + t * NX);
+      for (int k = 0; k < NX; ++k)
+        acc += ldA<double>(P, a0 + k * NX + i) *
+               ((double)w0[(t + 1) * NX + k] + (double)w2[(t + 1) * NX + k]);
+    }
+    xz[rho] = acc * iQd[rho];
+  }
+  for (int idx = tid; idx < TM; idx += BT) {
+    const int t = idx / m, l = idx - t * m;
+    const int b0 = t * NX * m;
+    double acc = (double)dlu[idx];
+#pragma unroll
+    for (int k = 0; k < NX; ++k)
+      acc += ldB<double>(P, b0 + k * m + l) *
+             ((double)w0[(t + 1) * NX + k] + (double)w2[(t + 1) * NX + k]);
+    uz[idx] = acc * iRd[idx];
+  }
+  __syncthreads();
+  float r2 = 0.f, b2 = 0.f;
+  for (int rho = tid; rho < R; rho += BT) {
+    const int t = rho / NX, i = rho - t * NX;
+    double acc = (double)dll[rho];
+    if (t > 0) {
+      const int tt = t - 1;
+#pragma unroll
+      for (int j = 0; j < NX; ++j) acc += ldA<double>(P, tt * NX * NX + i * NX + j) * xz[tt * NX + j];
+      for (int l = 0; l < m; ++l) acc += ldB<double>(P, tt * NX * m + i * m + l) * uz[tt * m + l];
+    }
+    const double res = xz[rho] - acc;
     w1[NX + rho] = (float)res;
-    double fl = 0.0;
-#pragma unroll
-    for (int j = 0; j < 3 * NX; ++j) fl += fabs(row[j] * (double)w0[t * NX + j]);
     r2 += (float)(res * res);
-    f2 += (float)(fl * fl);
     b2 += dlx[rho] * dlx[rho] + dll[rho] * dll[rho];
   }
-  for (int idx = tid; idx < P.TM; idx += BT) b2 += dlu[idx] * dlu[idx];
-  return block_sum3(r2, f2, b2, smem + C.red, nwv);
+  for (int idx = tid; idx < TM; idx += BT) b2 += dlu[idx] * dlu[idx];
+  const ResNorms n = block_sum2(r2, b2, smem + C.red, nwv);
+  __syncthreads();
+  return n;
 }
 
 // z~ = G^-1 (dl/dz - H' lambda~) (Alg. backward line 3, in double), then the

@@ -40,8 +40,6 @@ struct WsLayout {
   int64_t Ad, Bd, cd;             // the same in double (float offsets, 8-byte aligned)
   int64_t Dinv;                   // diagonal Schur blocks inverted [N][nx][nx]
   int64_t blk;                    // saved rows of S^ and Phi^-1: [N*nx][6*nx]
-  int64_t blkd;                   // the rows of S^ in double: [N*nx][3*nx] (float offset)
-  int64_t gd;                     // right-hand side of the Schur system in double [N*nx]
   int64_t xp, up, lam;            // last QP solution and multipliers
   int64_t xlin, ulin;             // last linearisation point
   int64_t g;                      // right-hand side of the Schur system [N*nx]
@@ -79,9 +77,6 @@ DMPC_HD inline WsLayout ws_layout(int T, int nx, int nu, int dyn) {
   L.Dinv = o; o += N * nx * nx;
   o = align_up(o, 4);
   L.blk = o; o += R * 6 * nx;
-  o = align_up(o, 4);
-  L.blkd = o; o += 2 * R * 3 * nx;
-  L.gd = o; o += 2 * R;
   L.xp = o; o += R;
   L.up = o; o += TM;
   L.lam = o; o += R;
@@ -110,14 +105,21 @@ DMPC_HD inline int64_t sol_block_len(int T, int nx, int nu) {
 // (must match the device-side carve in dmpc_device.h: every region rounded up
 // to 4 floats)
 DMPC_HD inline int64_t a4h(int64_t v) { return (v + 3) / 4 * 4; }
+// Shared region used by the line search (stage costs and defects of every
+// candidate, per-candidate sums) and, during a QP solve, by the refinement
+// residual (the primal point of the current multipliers): doubles.
+DMPC_HD inline int64_t ls_floats(int64_t N, int64_t R, int64_t TM) {
+  const int64_t a = 4 * (kMaxAlphas + 1) * N + 4 * (kMaxAlphas + 1);
+  const int64_t b = 2 * (R + TM);
+  return a > b ? a : b;
+}
 DMPC_HD inline int64_t lds_floats(int T, int nx, int nu, int bt, int slots) {
   const int64_t N = T + 1, R = N * nx, TM = (int64_t)T * nu;
   return 3 * a4h(R) + 2 * a4h(TM)        // iterate / QP solution / multipliers
          + 3 * a4h((int64_t)slots * bt + 3 * nx)   // three padded windows
          + 4 * (int64_t)bt               // Gauss-Jordan pivot rows, double buffered
          + 128                           // reductions
-         + 4 * (kMaxAlphas + 1) * N      // line-search stage costs and defects (double)
-         + 4 * (kMaxAlphas + 1);         // per-candidate sums (double)
+         + ls_floats(N, R, TM);          // line search / refinement primal (double)
 }
 
 // Launch-time arguments of the kernels.
