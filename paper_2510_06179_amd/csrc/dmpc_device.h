@@ -710,7 +710,7 @@ __device__ __forceinline__ R adjoint_rhs_row(const Prob& P, int t, int i, const 
 // For NX a multiple of 4 the window is 16-byte aligned (windows start on
 // 4-float boundaries) and is read with 128-bit LDS loads.
 template <int NX>
-__device__ __forceinline__ float row_dot(const float* coef, const float* win) {
+__device__ __forceinline__ float row_dot(const float* coef, const float* win, int cs = 1) {
   float wv[3 * NX];
   if constexpr (NX % 4 == 0) {
     const float4* w4 = reinterpret_cast<const float4*>(win);
@@ -729,9 +729,9 @@ __device__ __forceinline__ float row_dot(const float* coef, const float* win) {
   float a0 = 0.f, a1 = 0.f, a2 = 0.f;
 #pragma unroll
   for (int j = 0; j < NX; ++j) {
-    a0 = fmaf(coef[j], wv[j], a0);
-    a1 = fmaf(coef[NX + j], wv[NX + j], a1);
-    a2 = fmaf(coef[2 * NX + j], wv[2 * NX + j], a2);
+    a0 = fmaf(coef[j * cs], wv[j], a0);
+    a1 = fmaf(coef[(NX + j) * cs], wv[NX + j], a1);
+    a2 = fmaf(coef[(2 * NX + j) * cs], wv[2 * NX + j], a2);
   }
   return (a0 + a1) + a2;
 }
@@ -837,8 +837,9 @@ __device__ __forceinline__ void publish(float* w, const float (&v)[SLOTS], int R
 // every D_t (rows of a block are handled by consecutive threads; the rows are
 // processed in chunks of whole blocks), then the off-diagonal blocks
 // -D_t^-1 E_{t,t-1} D_{t-1}^-1 and -D_t^-1 E_{t,t+1} D_{t+1}^-1.  Reads the
-// diagonal-block rows from blk[rho][NX:2NX] and writes the preconditioner
-// rows to blk[rho][3NX:6NX].  Returns true (in this thread) on a
+// diagonal-block rows from coefficients NX..2NX-1 of blk and writes the
+// preconditioner rows to coefficients 3NX..6NX-1 (blk is stored coefficient-
+// major: coefficient j of row rho at blk[j * R + rho]).  Returns true (in this thread) on a
 // non-positive pivot.
 // ===========================================================================
 template <int NX>
@@ -857,7 +858,7 @@ __device__ __forceinline__ bool precond_rows(const Prob& P, float* piv) {
     float ga[NX], gb[NX];
 #pragma unroll
     for (int j = 0; j < NX; ++j) {
-      ga[j] = act ? blk[rho * 6 * NX + NX + j] : 0.f;
+      ga[j] = act ? blk[(int64_t)(NX + j) * P.R + rho] : 0.f;
       gb[j] = (j == i) ? 1.f : 0.f;
     }
 #pragma unroll
@@ -935,12 +936,12 @@ __device__ __forceinline__ bool precond_rows(const Prob& P, float* piv) {
         for (int j = 0; j < NX; ++j) up[j] = fmaf(w, Dn[k * NX + j], up[j]);
       }
     }
-    float* b = blk + rho * 6 * NX + 3 * NX;
+    float* b = blk + (int64_t)3 * NX * P.R + rho;
 #pragma unroll
     for (int j = 0; j < NX; ++j) {
-      b[j] = lo[j];
-      b[NX + j] = dr[j];
-      b[2 * NX + j] = up[j];
+      b[(int64_t)j * P.R] = lo[j];
+      b[(int64_t)(NX + j) * P.R] = dr[j];
+      b[(int64_t)(2 * NX + j) * P.R] = up[j];
     }
   }
   return nonpd;
@@ -957,13 +958,13 @@ template <int NX, int SLOTS, bool REG>
 __device__ __forceinline__ const float* coefS(const Prob& P, float (&S)[SLOTS][3 * NX], int s,
                                               int rho) {
   if constexpr (REG) return S[s];
-  return P.W + P.L.blk + rho * 6 * NX;
+  return P.W + P.L.blk + rho;   // coefficient-major: stride P.R
 }
 template <int NX, int SLOTS, bool REG>
 __device__ __forceinline__ const float* coefP(const Prob& P, float (&Ph)[SLOTS][3 * NX], int s,
                                               int rho) {
   if constexpr (REG) return Ph[s];
-  return P.W + P.L.blk + rho * 6 * NX + 3 * NX;
+  return P.W + P.L.blk + (int64_t)3 * NX * P.R + rho;
 }
 
 // v' Phi^-1 v for a vector held in this thread's rows.
@@ -972,6 +973,7 @@ __device__ __forceinline__ float precond_norm(const Prob& P, const Lds& sh,
                                               float (&Ph)[SLOTS][3 * NX], const float (&v)[SLOTS],
                                               int& redi) {
   const int tid = threadIdx.x, BT = blockDim.x, nwv = (BT + 63) >> 6;
+  const int cs = REG ? 1 : P.R;   // coefficient stride
   publish<SLOTS, REG>(sh.w0, v, P.R, NX);
   __syncthreads();
   float part = 0.f;
@@ -980,7 +982,8 @@ __device__ __forceinline__ float precond_norm(const Prob& P, const Lds& sh,
     const int rho = tid + s * BT;
     if (row_live<REG>(s, rho, P.R, BT)) {
       const int t = rho / NX;
-      part = fmaf(v[s], row_dot<NX>(coefP<NX, SLOTS, REG>(P, Ph, s, rho), sh.w0 + t * NX), part);
+      part = fmaf(v[s], row_dot<NX>(coefP<NX, SLOTS, REG>(P, Ph, s, rho), sh.w0 + t * NX, cs),
+                  part);
     }
   }
   return block_sum(part, sh.red + 64 * (redi++ & 1), nwv);
@@ -993,6 +996,7 @@ __device__ __forceinline__ int pcg(const Prob& P, const Lds& sh, float (&S)[SLOT
                                    int& flags, int& redi, int maxit_flag) {
   const int tid = threadIdx.x, BT = blockDim.x, nwv = (BT + 63) >> 6;
   const int R = P.R;
+  const int cs = REG ? 1 : R;   // coefficient stride
   float r[SLOTS], p[SLOTS], z[SLOTS], y[SLOTS];
   // r = rhs (line 1 with d = 0), r~ = Phi^-1 r (2), p = r~ (3), eta = r'r~ (4)
 #pragma unroll
@@ -1009,7 +1013,7 @@ __device__ __forceinline__ int pcg(const Prob& P, const Lds& sh, float (&S)[SLOT
     z[s] = 0.f;
     if (row_live<REG>(s, rho, R, BT)) {
       const int t = rho / NX;
-      z[s] = row_dot<NX>(coefP<NX, SLOTS, REG>(P, Ph, s, rho), sh.w1 + t * NX);
+      z[s] = row_dot<NX>(coefP<NX, SLOTS, REG>(P, Ph, s, rho), sh.w1 + t * NX, cs);
     }
     p[s] = z[s];
     part = fmaf(r[s], z[s], part);
@@ -1032,7 +1036,7 @@ __device__ __forceinline__ int pcg(const Prob& P, const Lds& sh, float (&S)[SLOT
       y[s] = 0.f;
       if (row_live<REG>(s, rho, R, BT)) {
         const int t = rho / NX;
-        y[s] = row_dot<NX>(coefS<NX, SLOTS, REG>(P, S, s, rho), sh.w0 + t * NX);
+        y[s] = row_dot<NX>(coefS<NX, SLOTS, REG>(P, S, s, rho), sh.w0 + t * NX, cs);
       }
       part = fmaf(p[s], y[s], part);
     }
@@ -1058,7 +1062,7 @@ __device__ __forceinline__ int pcg(const Prob& P, const Lds& sh, float (&S)[SLOT
       z[s] = 0.f;
       if (row_live<REG>(s, rho, R, BT)) {
         const int t = rho / NX;
-        z[s] = row_dot<NX>(coefP<NX, SLOTS, REG>(P, Ph, s, rho), sh.w1 + t * NX);
+        z[s] = row_dot<NX>(coefP<NX, SLOTS, REG>(P, Ph, s, rho), sh.w1 + t * NX, cs);
       }
       part = fmaf(r[s], z[s], part);
     }
@@ -1156,7 +1160,7 @@ __device__ __noinline__ int fwd_blocks(const ProbRec* rec, const float* data, fl
     float row[3 * NX], g;
     schur_row<NX, float>(P, t, i, row, g);
 #pragma unroll
-    for (int j = 0; j < 3 * NX; ++j) blk[rho * 6 * NX + j] = row[j];
+    for (int j = 0; j < 3 * NX; ++j) blk[(int64_t)j * P.R + rho] = row[j];
     gv[rho] = g;
   }
   __syncthreads();
@@ -1200,7 +1204,7 @@ __device__ __forceinline__ ResNorms block_sum2(float a, float b, float* red, int
 // (rounded to float) to w1[NX + rho]; returns the norms of r and of the KKT
 // right-hand side [-b; d] = [-(q, r); (x_s, c)] (Eq. ocp:KKT), identical in
 // every thread.
-template <int NX>
+template <int NX, int SLOTS>
 __device__ __noinline__ ResNorms fwd_residual64(const ProbRec* rec, const float* data, float* ws) {
   extern __shared__ float smem[];
   const int tid = threadIdx.x, BT = blockDim.x;
@@ -1217,17 +1221,23 @@ __device__ __noinline__ ResNorms fwd_residual64(const ProbRec* rec, const float*
   const float* rr = P.W + P.L.r;
   const double* iQd = (const double*)(P.W + P.L.iQd);
   const double* iRd = (const double*)(P.W + P.L.iRd);
-  for (int rho = tid; rho < R; rho += BT) {
-    const int t = rho / NX, i = rho - t * NX;
-    double acc = (double)q[rho] + ((double)w0[rho] + (double)w2[rho]);
-    if (t < T) {
-      const int a0 = t * NX * NX;
+  // the thread's rows are rho = tid + s * BT, s < SLOTS (slots * BT >= R):
+  // unrolled so that the loads of all of them are in flight together
 #pragma unroll
-      for (int k = 0; k < NX; ++k)
-        acc -= ldA<double>(P, a0 + k * NX + i) *
-               ((double)w0[(t + 1) * NX + k] + (double)w2[(t + 1) * NX + k]);
+  for (int s = 0; s < SLOTS; ++s) {
+    const int rho = tid + s * BT;
+    if (rho < R) {
+      const int t = rho / NX, i = rho - t * NX;
+      double acc = (double)q[rho] + ((double)w0[rho] + (double)w2[rho]);
+      if (t < T) {
+        const int a0 = t * NX * NX;
+#pragma unroll
+        for (int k = 0; k < NX; ++k)
+          acc -= ldA<double>(P, a0 + k * NX + i) *
+                 ((double)w0[(t + 1) * NX + k] + (double)w2[(t + 1) * NX + k]);
+      }
+      xz[rho] = -acc * iQd[rho];
     }
-    xz[rho] = -acc * iQd[rho];
   }
   for (int idx = tid; idx < TM; idx += BT) {
     const int t = idx / m, l = idx - t * m;
@@ -1241,25 +1251,30 @@ __device__ __noinline__ ResNorms fwd_residual64(const ProbRec* rec, const float*
   }
   __syncthreads();
   float r2 = 0.f, b2 = 0.f;
-  for (int rho = tid; rho < R; rho += BT) {
-    const int t = rho / NX, i = rho - t * NX;
-    double res;
-    float dv;
-    if (t == 0) {
-      dv = P.x0[i];
-      res = xz[i] - (double)dv;
-    } else {
-      const int tt = t - 1;
-      dv = P.c[tt * NX + i];
-      double acc = ldc<double>(P, tt * NX + i);
 #pragma unroll
-      for (int j = 0; j < NX; ++j) acc += ldA<double>(P, tt * NX * NX + i * NX + j) * xz[tt * NX + j];
-      for (int l = 0; l < m; ++l) acc += ldB<double>(P, tt * NX * m + i * m + l) * uz[tt * m + l];
-      res = xz[rho] - acc;
+  for (int s = 0; s < SLOTS; ++s) {
+    const int rho = tid + s * BT;
+    if (rho < R) {
+      const int t = rho / NX, i = rho - t * NX;
+      double res;
+      float dv;
+      if (t == 0) {
+        dv = P.x0[i];
+        res = xz[i] - (double)dv;
+      } else {
+        const int tt = t - 1;
+        dv = P.c[tt * NX + i];
+        double acc = ldc<double>(P, tt * NX + i);
+#pragma unroll
+        for (int j = 0; j < NX; ++j)
+          acc += ldA<double>(P, tt * NX * NX + i * NX + j) * xz[tt * NX + j];
+        for (int l = 0; l < m; ++l) acc += ldB<double>(P, tt * NX * m + i * m + l) * uz[tt * m + l];
+        res = xz[rho] - acc;
+      }
+      w1[NX + rho] = (float)res;
+      r2 += (float)(res * res);
+      b2 += q[rho] * q[rho] + dv * dv;
     }
-    w1[NX + rho] = (float)res;
-    r2 += (float)(res * res);
-    b2 += q[rho] * q[rho] + dv * dv;
   }
   for (int idx = tid; idx < TM; idx += BT) b2 += rr[idx] * rr[idx];
   const ResNorms n = block_sum2(r2, b2, smem + C.red, nwv);
@@ -1491,7 +1506,7 @@ __device__ __noinline__ void bwd_begin(const ProbRec* rec, const float* data, fl
 // the rows are  r_0 = x~_0 - dl/dlambda_0,
 //   r_{t+1} = x~_{t+1} - A_t x~_t - B_t u~_t - dl/dlambda_{t+1}.
 // Result to w1; norms of r and of the adjoint right-hand side (dl/dz, dl/dlambda).
-template <int NX>
+template <int NX, int SLOTS>
 __device__ __noinline__ ResNorms bwd_residual64(const ProbRec* rec, const float* data, float* ws,
                                                 const float* dl) {
   extern __shared__ float smem[];
@@ -1510,17 +1525,21 @@ __device__ __noinline__ ResNorms bwd_residual64(const ProbRec* rec, const float*
   const double* iQd = (const double*)(P.W + P.L.iQd);
   const double* iRd = (const double*)(P.W + P.L.iRd);
   const int nwv = (BT + 63) >> 6;
-  for (int rho = tid; rho < R; rho += BT) {
-    const int t = rho / NX, i = rho - t * NX;
-    double acc = (double)dlx[rho] - ((double)w0[rho] + (double)w2[rho]);
-    if (t < T) {
-      const int a0 = t * NX * NX;
 #pragma unroll
-      for (int k = 0; k < NX; ++k)
-        acc += ldA<double>(P, a0 + k * NX + i) *
-               ((double)w0[(t + 1) * NX + k] + (double)w2[(t + 1) * NX + k]);
+  for (int s = 0; s < SLOTS; ++s) {
+    const int rho = tid + s * BT;
+    if (rho < R) {
+      const int t = rho / NX, i = rho - t * NX;
+      double acc = (double)dlx[rho] - ((double)w0[rho] + (double)w2[rho]);
+      if (t < T) {
+        const int a0 = t * NX * NX;
+#pragma unroll
+        for (int k = 0; k < NX; ++k)
+          acc += ldA<double>(P, a0 + k * NX + i) *
+                 ((double)w0[(t + 1) * NX + k] + (double)w2[(t + 1) * NX + k]);
+      }
+      xz[rho] = acc * iQd[rho];
     }
-    xz[rho] = acc * iQd[rho];
   }
   for (int idx = tid; idx < TM; idx += BT) {
     const int t = idx / m, l = idx - t * m;
@@ -1534,19 +1553,24 @@ __device__ __noinline__ ResNorms bwd_residual64(const ProbRec* rec, const float*
   }
   __syncthreads();
   float r2 = 0.f, b2 = 0.f;
-  for (int rho = tid; rho < R; rho += BT) {
-    const int t = rho / NX, i = rho - t * NX;
-    double acc = (double)dll[rho];
-    if (t > 0) {
-      const int tt = t - 1;
 #pragma unroll
-      for (int j = 0; j < NX; ++j) acc += ldA<double>(P, tt * NX * NX + i * NX + j) * xz[tt * NX + j];
-      for (int l = 0; l < m; ++l) acc += ldB<double>(P, tt * NX * m + i * m + l) * uz[tt * m + l];
+  for (int s = 0; s < SLOTS; ++s) {
+    const int rho = tid + s * BT;
+    if (rho < R) {
+      const int t = rho / NX, i = rho - t * NX;
+      double acc = (double)dll[rho];
+      if (t > 0) {
+        const int tt = t - 1;
+#pragma unroll
+        for (int j = 0; j < NX; ++j)
+          acc += ldA<double>(P, tt * NX * NX + i * NX + j) * xz[tt * NX + j];
+        for (int l = 0; l < m; ++l) acc += ldB<double>(P, tt * NX * m + i * m + l) * uz[tt * m + l];
+      }
+      const double res = xz[rho] - acc;
+      w1[NX + rho] = (float)res;
+      r2 += (float)(res * res);
+      b2 += dlx[rho] * dlx[rho] + dll[rho] * dll[rho];
     }
-    const double res = xz[rho] - acc;
-    w1[NX + rho] = (float)res;
-    r2 += (float)(res * res);
-    b2 += dlx[rho] * dlx[rho] + dll[rho] * dll[rho];
   }
   for (int idx = tid; idx < TM; idx += BT) b2 += dlu[idx] * dlu[idx];
   const ResNorms n = block_sum2(r2, b2, smem + C.red, nwv);
@@ -1716,8 +1740,8 @@ __device__ __forceinline__ void load_rows(const Prob& P, float (&S)[SLOTS][3 * N
     if constexpr (REG) {
 #pragma unroll
       for (int j = 0; j < 3 * NX; ++j) {
-        S[s][j] = ok ? blk[rho * 6 * NX + j] : 0.f;
-        Ph[s][j] = ok ? blk[rho * 6 * NX + 3 * NX + j] : 0.f;
+        S[s][j] = ok ? blk[(int64_t)j * P.R + rho] : 0.f;
+        Ph[s][j] = ok ? blk[(int64_t)(3 * NX + j) * P.R + rho] : 0.f;
       }
     }
   }
@@ -1802,7 +1826,7 @@ __global__ __launch_bounds__(MAXBT) void forward_kernel(KArgs a) {
       pcg_total += qp_solve<NX, SLOTS, REG>(
           P, sh, S, Ph, g, lam, lo, a.refine_steps, maxit, a.pcg_tol, a.pcg_abs_tol, rtol,
           a.kkt_tol, flags, redi, DMPC_PROB_PCG_MAXITER,
-          [&]() { return fwd_residual64<NX>(rec, a.data, a.ws); });
+          [&]() { return fwd_residual64<NX, SLOTS>(rec, a.data, a.ws); });
       publish<SLOTS>(sh.w0, lam, P.R, NX);
       publish<SLOTS>(sh.w2, lo, P.R, NX);
       __syncthreads();
@@ -1856,7 +1880,7 @@ __global__ __launch_bounds__(MAXBT) void backward_kernel(KArgs a) {
     const int its = qp_solve<NX, SLOTS, REG>(
         P, sh, S, Ph, g, lt, lo, a.refine_steps, maxit, a.bwd_tol, 0.f, rtol, a.kkt_tol, flags,
         redi, DMPC_PROB_BWD_PCG_MAXITER,
-        [&]() { return bwd_residual64<NX>(rec, a.data, a.ws, a.dl); });
+        [&]() { return bwd_residual64<NX, SLOTS>(rec, a.data, a.ws, a.dl); });
     publish<SLOTS>(sh.w0, lt, P.R, NX);
     publish<SLOTS>(sh.w2, lo, P.R, NX);
     __syncthreads();
