@@ -84,7 +84,9 @@ typedef enum dmpc_init_kind {
   DMPC_INIT_ROLLOUT = 1  /* u from the solution arena, x rolled out from x_s, lambda = 0 */
 } dmpc_init_kind;
 
-/* One problem of a batch (host struct, 64 bytes).  Offsets are in floats. */
+/* One problem of a batch (host struct, 64 bytes).  Offsets are in floats.
+ * Kernels are built for nx in {2, 3, 4, 8, 12, 16, 32} and nu <= 16; other
+ * state sizes are UNSUPPORTED. */
 typedef struct dmpc_problem {
   int32_t T;            /* horizon, >= 1 */
   int32_t nx, nu;       /* state and input sizes */

@@ -15,6 +15,9 @@ Follows Sec. 3.1 of the paper:
                    rhs = [-b; d], b = (q_0, r_0, ..., q_T), d = (x_s, C_0, ...,
                    C_{T-1}), with z = (x_0, u_0, ..., x_{T-1}, u_{T-1}, x_T).
 * ``solve_qp``  -- LU with partial pivoting of the dense K (LAPACK getrf/getrs).
+* ``kkt_residual`` / ``kkt_residual_blocks`` -- ||K w - rhs||_2 / ||rhs||_2,
+                   from the dense K or stage by stage from its blocks (long
+                   horizons); pinned equal to each other.
 
 Pinned (tests): Riccati closed form on LQ problems, a hand-solved scalar
 problem, KKT residual at machine precision, complex-step Jacobians against
@@ -158,3 +161,34 @@ def kkt_residual(qpd, xs, x, u, lam):
     K, rhs, _ = kkt(qpd, xs)
     w = join_w(np.asarray(x, np.float64), np.asarray(u, np.float64), np.asarray(lam, np.float64))
     return float(np.linalg.norm(K @ w - rhs) / max(np.linalg.norm(rhs), 1e-300))
+
+
+def kkt_residual_blocks(qpd, xs, x, u, lam):
+    """The same relative KKT residual as ``kkt_residual``, accumulated stage by
+    stage from the blocks of G, H, b, d (Eq. KKTmatrix) instead of the dense
+    K, so that long horizons do not need the dense matrix."""
+    T = qpd["T"]
+    x = np.asarray(x, np.float64)
+    u = np.asarray(u, np.float64)
+    lam = np.asarray(lam, np.float64)
+    r2 = 0.0
+    rhs2 = float(np.dot(xs, xs))
+    for t in range(T + 1):
+        # stationarity in x_t: Q_t x_t + (H' lam)_{x_t} + q_t
+        g = qpd["Q"][t] @ x[t] + qpd["q"][t]
+        g = g + (lam[0] if t == 0 else qpd["Aplus"][t - 1].T @ lam[t])
+        if t < T:
+            g = g + qpd["A"][t].T @ lam[t + 1]
+        r2 += float(np.dot(g, g))
+        rhs2 += float(np.dot(qpd["q"][t], qpd["q"][t]))
+    for t in range(T):
+        g = qpd["R"][t] @ u[t] + qpd["r"][t] + qpd["B"][t].T @ lam[t + 1]
+        r2 += float(np.dot(g, g))
+        rhs2 += float(np.dot(qpd["r"][t], qpd["r"][t]))
+        # dynamics row t+1: A+_t x_{t+1} + A_t x_t + B_t u_t - C_t
+        h = qpd["Aplus"][t] @ x[t + 1] + qpd["A"][t] @ x[t] + qpd["B"][t] @ u[t] - qpd["C"][t]
+        r2 += float(np.dot(h, h))
+        rhs2 += float(np.dot(qpd["C"][t], qpd["C"][t]))
+    h = x[0] - xs
+    r2 += float(np.dot(h, h))
+    return float(np.sqrt(r2) / max(np.sqrt(rhs2), 1e-300))

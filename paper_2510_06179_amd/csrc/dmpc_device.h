@@ -283,7 +283,7 @@ __device__ __forceinline__ float block_sum(float v, float* red, int nwv) {
 // Per-problem context
 // ===========================================================================
 struct Prob {
-  int T, N, m, R, TM, dyn, cost, phases, nw, slots;
+  int T, N, m, R, TM, dyn, cost, phases, nw, slots, flags;
   const float* dynp;   // dynamics block in the data arena
   const float* costp;  // cost block in the data arena
   const float* x0;
@@ -310,11 +310,12 @@ __device__ __forceinline__ Prob make_prob(const ProbRec& pr, const float* data, 
   P.phases = pr.phases;
   P.nw = pr.nw;
   P.slots = pr.slots;
+  P.flags = pr.flags;
   P.dynp = data + pr.dyn_off;
   P.costp = data + pr.cost_off;
   P.x0 = data + pr.x0_off;
   P.W = ws + pr.ws_off;
-  P.L = ws_layout(pr.T, NX, pr.nu, pr.dyn);
+  P.L = ws_layout(pr.T, NX, pr.nu, pr.dyn, pr.flags);
   if (pr.dyn == DMPC_DYN_LTV) {
     P.A = P.dynp;
     P.B = P.A + pr.T * NX * NX;
@@ -706,11 +707,21 @@ __device__ __forceinline__ R adjoint_rhs_row(const Prob& P, int t, int i, const 
   return v;
 }
 
+// Storage of the Schur and preconditioner rows in the workspace: tiles of 64
+// rows, coefficient-major inside a tile -- coefficient j of row rho at
+// (rho / 64) * 6 NX * 64 + 64 j + rho % 64.  A wave reads one coefficient of
+// 64 consecutive rows as one contiguous 256-byte access, and a thread walks
+// its row with constant offsets of 64 floats.
+template <int NX>
+__device__ __forceinline__ int64_t blk_at(int rho, int j) {
+  return (int64_t)(rho >> 6) * (6 * NX * 64) + 64 * j + (rho & 63);
+}
+
 // Row product with a padded LDS window: sum_j coef[j] * win[j], win = w + t*NX.
 // For NX a multiple of 4 the window is 16-byte aligned (windows start on
 // 4-float boundaries) and is read with 128-bit LDS loads.
 template <int NX>
-__device__ __forceinline__ float row_dot(const float* coef, const float* win, int cs = 1) {
+__device__ __forceinline__ float row_dot(const float* coef, const float* win) {
   float wv[3 * NX];
   if constexpr (NX % 4 == 0) {
     const float4* w4 = reinterpret_cast<const float4*>(win);
@@ -729,12 +740,31 @@ __device__ __forceinline__ float row_dot(const float* coef, const float* win, in
   float a0 = 0.f, a1 = 0.f, a2 = 0.f;
 #pragma unroll
   for (int j = 0; j < NX; ++j) {
-    a0 = fmaf(coef[j * cs], wv[j], a0);
-    a1 = fmaf(coef[(NX + j) * cs], wv[NX + j], a1);
-    a2 = fmaf(coef[(2 * NX + j) * cs], wv[2 * NX + j], a2);
+    a0 = fmaf(coef[j], wv[j], a0);
+    a1 = fmaf(coef[NX + j], wv[NX + j], a1);
+    a2 = fmaf(coef[2 * NX + j], wv[2 * NX + j], a2);
   }
   return (a0 + a1) + a2;
 }
+// Row product with the coefficients read from the workspace (tiled storage:
+// coefficient j at coef[64 j]).  The row address passes through an empty asm:
+// the coefficients do not change during the PCG, and without it the compiler
+// hoists their loads out of the loop -- 6 nx values per row kept live, which
+// spill.
+template <int NX>
+__device__ __forceinline__ float row_dot_ws(const float* coef, const float* win) {
+  uint64_t a = (uint64_t)(uintptr_t)coef;
+  asm volatile("" : "+v"(a));
+  coef = (const float*)(uintptr_t)a;
+  float acc[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+#pragma unroll
+    for (int j = 0; j < NX; ++j) acc[b] = fmaf(coef[64 * (b * NX + j)], win[b * NX + j], acc[b]);
+  }
+  return (acc[0] + acc[1]) + acc[2];
+}
+
 // Same with the window value taken as the double-float hi + lo.
 template <int NX>
 __device__ __forceinline__ double row_dot64(const double* coef, const float* hi, const float* lo) {
@@ -755,13 +785,12 @@ struct Carve {
   int xbar, ubar, xp, up, lam, w0, w1, w2, piv, red, ls;
 };
 __device__ __forceinline__ int a4(int v) { return (v + 3) & ~3; }
-// Window length: a zero pad of nx, one entry for every row of every slot
-// (slots x bt >= R, so that the PCG runs all slots without a row guard: rows
-// past R hold zeros), and 2 nx of zero pad.
-__device__ __forceinline__ int win_len(int nx, int bt, int slots) {
-  return a4(slots * bt + 3 * nx);
-}
-__device__ __forceinline__ Carve carve(int R, int TM, int N, int nx, int bt, int slots) {
+// Offsets: the bulk regions (iterate, QP solution, multipliers, line-search
+// region) from the bulk base -- the start of LDS, or the workspace's bulk
+// region for problems too large for LDS -- and the windows, pivot rows and
+// reduction slots in LDS after them (or from the start of LDS).
+__device__ __forceinline__ Carve carve(int R, int TM, int N, int nx, int bt, int slots,
+                                       int flags) {
   Carve C;
   int o = 0;
   C.xbar = o;  o += a4(R);            // forward: iterate;     backward: x~
@@ -769,21 +798,31 @@ __device__ __forceinline__ Carve carve(int R, int TM, int N, int nx, int bt, int
   C.xp = o;    o += a4(R);            // QP solution
   C.up = o;    o += a4(TM);
   C.lam = o;   o += a4(R);            // backward: forward multipliers
-  const int wl = win_len(nx, bt, slots);
+  C.ls = o;    o += a4((int)ls_floats(N, R, TM));   // doubles
+  if (flags & kRecBulkWs) o = 0;
+  const int wl = (int)win_floats(R, nx, bt, slots, flags);
   C.w0 = o;    o += wl;
   C.w1 = o;    o += wl;
   C.w2 = o;    o += wl;               // low part of a double-float vector in w0
   C.piv = o;   o += 4 * bt;
   C.red = o;   o += 128;
-  C.ls = o;    o += (int)ls_floats(N, R, TM);   // doubles
   return C;
+}
+template <int NX>
+__device__ __forceinline__ Carve carve_of(const Prob& P) {
+  return carve(P.R, P.TM, P.N, NX, blockDim.x, P.slots, P.flags);
+}
+// Base of the bulk regions.
+__device__ __forceinline__ float* bulk_base(float* smem, const Prob& P) {
+  return (P.flags & kRecBulkWs) ? P.W + P.L.bulk : smem;
 }
 
 // Zeroes the pads of the three windows: [0, nx) and [R + nx, window end).
 template <int NX>
-__device__ __forceinline__ void zero_pads(float* smem, const Carve& C, int R, int BT, int slots) {
-  const int wl = win_len(NX, BT, slots);
-  for (int i = threadIdx.x; i < NX + (wl - R - NX); i += BT) {
+__device__ __forceinline__ void zero_pads(float* smem, const Carve& C, const Prob& P) {
+  const int wl = (int)win_floats(P.R, NX, blockDim.x, P.slots, P.flags);
+  const int R = P.R;
+  for (int i = threadIdx.x; i < NX + (wl - R - NX); i += blockDim.x) {
     const int o = i < NX ? i : R + i;
     smem[C.w0 + o] = 0.f;
     smem[C.w1 + o] = 0.f;
@@ -797,19 +836,17 @@ struct Lds {
   float* w2;   // low part of the vector in w0 (double-float multipliers)
   float* piv;  // Gauss-Jordan pivot rows, double buffered
   float* red;  // 2 x 64 floats for block reductions
-  float* ls;   // line-search stage results and per-candidate sums
 };
 
 template <int NX>
 __device__ __forceinline__ Lds lds_of(float* smem, const Prob& P) {
-  const Carve C = carve(P.R, P.TM, P.N, NX, blockDim.x, P.slots);
+  const Carve C = carve_of<NX>(P);
   Lds sh;
   sh.w0 = smem + C.w0;
   sh.w1 = smem + C.w1;
   sh.w2 = smem + C.w2;
   sh.piv = smem + C.piv;
   sh.red = smem + C.red;
-  sh.ls = smem + C.ls;
   return sh;
 }
 
@@ -838,8 +875,8 @@ __device__ __forceinline__ void publish(float* w, const float (&v)[SLOTS], int R
 // processed in chunks of whole blocks), then the off-diagonal blocks
 // -D_t^-1 E_{t,t-1} D_{t-1}^-1 and -D_t^-1 E_{t,t+1} D_{t+1}^-1.  Reads the
 // diagonal-block rows from coefficients NX..2NX-1 of blk and writes the
-// preconditioner rows to coefficients 3NX..6NX-1 (blk is stored coefficient-
-// major: coefficient j of row rho at blk[j * R + rho]).  Returns true (in this thread) on a
+// preconditioner rows to coefficients 3NX..6NX-1.  Returns true (in this
+// thread) on a
 // non-positive pivot.
 // ===========================================================================
 template <int NX>
@@ -858,7 +895,7 @@ __device__ __forceinline__ bool precond_rows(const Prob& P, float* piv) {
     float ga[NX], gb[NX];
 #pragma unroll
     for (int j = 0; j < NX; ++j) {
-      ga[j] = act ? blk[(int64_t)(NX + j) * P.R + rho] : 0.f;
+      ga[j] = act ? blk[blk_at<NX>(rho, NX + j)] : 0.f;
       gb[j] = (j == i) ? 1.f : 0.f;
     }
 #pragma unroll
@@ -936,12 +973,12 @@ __device__ __forceinline__ bool precond_rows(const Prob& P, float* piv) {
         for (int j = 0; j < NX; ++j) up[j] = fmaf(w, Dn[k * NX + j], up[j]);
       }
     }
-    float* b = blk + (int64_t)3 * NX * P.R + rho;
+    float* b = blk + blk_at<NX>(rho, 3 * NX);
 #pragma unroll
     for (int j = 0; j < NX; ++j) {
-      b[(int64_t)j * P.R] = lo[j];
-      b[(int64_t)(NX + j) * P.R] = dr[j];
-      b[(int64_t)(2 * NX + j) * P.R] = up[j];
+      b[64 * j] = lo[j];
+      b[64 * (NX + j)] = dr[j];
+      b[64 * (2 * NX + j)] = up[j];
     }
   }
   return nonpd;
@@ -954,26 +991,36 @@ __device__ __forceinline__ bool precond_rows(const Prob& P, float* piv) {
 // (The warm start of Alg. pcg enters through rhs = g - S^ lambda, which the
 // caller computes in double.)  Returns the iteration count; ORs status bits.
 // ===========================================================================
+// Register copy of a thread's Schur / preconditioner rows; a placeholder of
+// one float when the rows are read from the workspace.
 template <int NX, int SLOTS, bool REG>
-__device__ __forceinline__ const float* coefS(const Prob& P, float (&S)[SLOTS][3 * NX], int s,
+using RowRegs = float[REG ? SLOTS : 1][REG ? 3 * NX : 1];
+
+template <int NX, int SLOTS, bool REG>
+__device__ __forceinline__ const float* coefS(const Prob& P, RowRegs<NX, SLOTS, REG>& S, int s,
                                               int rho) {
   if constexpr (REG) return S[s];
-  return P.W + P.L.blk + rho;   // coefficient-major: stride P.R
+  return P.W + P.L.blk + blk_at<NX>(rho, 0);          // stride 64
 }
 template <int NX, int SLOTS, bool REG>
-__device__ __forceinline__ const float* coefP(const Prob& P, float (&Ph)[SLOTS][3 * NX], int s,
+__device__ __forceinline__ const float* coefP(const Prob& P, RowRegs<NX, SLOTS, REG>& Ph, int s,
                                               int rho) {
   if constexpr (REG) return Ph[s];
-  return P.W + P.L.blk + (int64_t)3 * NX * P.R + rho;
+  return P.W + P.L.blk + blk_at<NX>(rho, 3 * NX);     // stride 64
+}
+
+template <int NX, int SLOTS, bool REG>
+__device__ __forceinline__ float rdot(const float* coef, const float* win) {
+  if constexpr (REG) return row_dot<NX>(coef, win);
+  return row_dot_ws<NX>(coef, win);
 }
 
 // v' Phi^-1 v for a vector held in this thread's rows.
 template <int NX, int SLOTS, bool REG>
 __device__ __forceinline__ float precond_norm(const Prob& P, const Lds& sh,
-                                              float (&Ph)[SLOTS][3 * NX], const float (&v)[SLOTS],
+                                              RowRegs<NX, SLOTS, REG>& Ph, const float (&v)[SLOTS],
                                               int& redi) {
   const int tid = threadIdx.x, BT = blockDim.x, nwv = (BT + 63) >> 6;
-  const int cs = REG ? 1 : P.R;   // coefficient stride
   publish<SLOTS, REG>(sh.w0, v, P.R, NX);
   __syncthreads();
   float part = 0.f;
@@ -982,7 +1029,7 @@ __device__ __forceinline__ float precond_norm(const Prob& P, const Lds& sh,
     const int rho = tid + s * BT;
     if (row_live<REG>(s, rho, P.R, BT)) {
       const int t = rho / NX;
-      part = fmaf(v[s], row_dot<NX>(coefP<NX, SLOTS, REG>(P, Ph, s, rho), sh.w0 + t * NX, cs),
+      part = fmaf(v[s], rdot<NX, SLOTS, REG>(coefP<NX, SLOTS, REG>(P, Ph, s, rho), sh.w0 + t * NX),
                   part);
     }
   }
@@ -990,13 +1037,12 @@ __device__ __forceinline__ float precond_norm(const Prob& P, const Lds& sh,
 }
 
 template <int NX, int SLOTS, bool REG>
-__device__ __forceinline__ int pcg(const Prob& P, const Lds& sh, float (&S)[SLOTS][3 * NX],
-                                   float (&Ph)[SLOTS][3 * NX], const float (&rhs)[SLOTS],
+__device__ __forceinline__ int pcg(const Prob& P, const Lds& sh, RowRegs<NX, SLOTS, REG>& S,
+                                   RowRegs<NX, SLOTS, REG>& Ph, const float (&rhs)[SLOTS],
                                    float (&d)[SLOTS], int maxit, float rel_tol, float abs_thresh,
                                    int& flags, int& redi, int maxit_flag) {
   const int tid = threadIdx.x, BT = blockDim.x, nwv = (BT + 63) >> 6;
   const int R = P.R;
-  const int cs = REG ? 1 : R;   // coefficient stride
   float r[SLOTS], p[SLOTS], z[SLOTS], y[SLOTS];
   // r = rhs (line 1 with d = 0), r~ = Phi^-1 r (2), p = r~ (3), eta = r'r~ (4)
 #pragma unroll
@@ -1013,7 +1059,7 @@ __device__ __forceinline__ int pcg(const Prob& P, const Lds& sh, float (&S)[SLOT
     z[s] = 0.f;
     if (row_live<REG>(s, rho, R, BT)) {
       const int t = rho / NX;
-      z[s] = row_dot<NX>(coefP<NX, SLOTS, REG>(P, Ph, s, rho), sh.w1 + t * NX, cs);
+      z[s] = rdot<NX, SLOTS, REG>(coefP<NX, SLOTS, REG>(P, Ph, s, rho), sh.w1 + t * NX);
     }
     p[s] = z[s];
     part = fmaf(r[s], z[s], part);
@@ -1036,7 +1082,7 @@ __device__ __forceinline__ int pcg(const Prob& P, const Lds& sh, float (&S)[SLOT
       y[s] = 0.f;
       if (row_live<REG>(s, rho, R, BT)) {
         const int t = rho / NX;
-        y[s] = row_dot<NX>(coefS<NX, SLOTS, REG>(P, S, s, rho), sh.w0 + t * NX, cs);
+        y[s] = rdot<NX, SLOTS, REG>(coefS<NX, SLOTS, REG>(P, S, s, rho), sh.w0 + t * NX);
       }
       part = fmaf(p[s], y[s], part);
     }
@@ -1062,7 +1108,7 @@ __device__ __forceinline__ int pcg(const Prob& P, const Lds& sh, float (&S)[SLOT
       z[s] = 0.f;
       if (row_live<REG>(s, rho, R, BT)) {
         const int t = rho / NX;
-        z[s] = row_dot<NX>(coefP<NX, SLOTS, REG>(P, Ph, s, rho), sh.w1 + t * NX, cs);
+        z[s] = rdot<NX, SLOTS, REG>(coefP<NX, SLOTS, REG>(P, Ph, s, rho), sh.w1 + t * NX);
       }
       part = fmaf(r[s], z[s], part);
     }
@@ -1098,15 +1144,15 @@ __device__ __noinline__ void fwd_begin(const ProbRec* rec, const float* data, co
   extern __shared__ float smem[];
   const int tid = threadIdx.x, BT = blockDim.x;
   const Prob P = make_prob<NX>(*rec, data, ws);
-  const Carve C = carve(P.R, P.TM, P.N, NX, BT, P.slots);
-  float* xbar = smem + C.xbar;
-  float* ubar = smem + C.ubar;
+  const Carve C = carve_of<NX>(P);
+  float* xbar = bulk_base(smem, P) + C.xbar;
+  float* ubar = bulk_base(smem, P) + C.ubar;
   const int T = P.T, m = P.m, R = P.R, TM = P.TM;
   const float* solx = sol + rec->sol_off;
   const float* solu = solx + R;
   for (int i = tid; i < R; i += BT) xbar[i] = (i < NX) ? P.x0[i] : solx[i];
   for (int i = tid; i < TM; i += BT) ubar[i] = solu[i];
-  zero_pads<NX>(smem, C, R, BT, P.slots);
+  zero_pads<NX>(smem, C, P);
   __syncthreads();
   if (init != DMPC_INIT_ROLLOUT) return;
   if (P.dyn == DMPC_DYN_LTV) {
@@ -1150,8 +1196,8 @@ __device__ __noinline__ int fwd_blocks(const ProbRec* rec, const float* data, fl
   extern __shared__ float smem[];
   const int tid = threadIdx.x, BT = blockDim.x;
   const Prob P = make_prob<NX>(*rec, data, ws);
-  const Carve C = carve(P.R, P.TM, P.N, NX, BT, P.slots);
-  form_qp<NX>(P, smem + C.xbar, smem + C.ubar);
+  const Carve C = carve_of<NX>(P);
+  form_qp<NX>(P, bulk_base(smem, P) + C.xbar, bulk_base(smem, P) + C.ubar);
   __syncthreads();
   float* blk = P.W + P.L.blk;
   float* gv = P.W + P.L.g;
@@ -1160,7 +1206,7 @@ __device__ __noinline__ int fwd_blocks(const ProbRec* rec, const float* data, fl
     float row[3 * NX], g;
     schur_row<NX, float>(P, t, i, row, g);
 #pragma unroll
-    for (int j = 0; j < 3 * NX; ++j) blk[(int64_t)j * P.R + rho] = row[j];
+    for (int j = 0; j < 3 * NX; ++j) blk[blk_at<NX>(rho, j)] = row[j];
     gv[rho] = g;
   }
   __syncthreads();
@@ -1209,12 +1255,12 @@ __device__ __noinline__ ResNorms fwd_residual64(const ProbRec* rec, const float*
   extern __shared__ float smem[];
   const int tid = threadIdx.x, BT = blockDim.x;
   const Prob P = make_prob<NX>(*rec, data, ws);
-  const Carve C = carve(P.R, P.TM, P.N, NX, BT, P.slots);
+  const Carve C = carve_of<NX>(P);
   const int T = P.T, m = P.m, R = P.R, TM = P.TM;
   const float* w0 = smem + C.w0 + NX;   // lambda, high part (unpadded view)
   const float* w2 = smem + C.w2 + NX;   // low part
   float* w1 = smem + C.w1;
-  double* xz = (double*)(smem + C.ls);  // primal point of lambda: x [R], u [TM]
+  double* xz = (double*)(bulk_base(smem, P) + C.ls);  // primal point of lambda: x [R], u [TM]
   double* uz = xz + R;
   const int nwv = (BT + 63) >> 6;
   const float* q = P.W + P.L.q;
@@ -1292,12 +1338,12 @@ __device__ __noinline__ int fwd_recover_ls(const ProbRec* rec, const float* data
   extern __shared__ float smem[];
   const int tid = threadIdx.x, BT = blockDim.x, nwv = (BT + 63) >> 6;
   const Prob P = make_prob<NX>(*rec, data, ws);
-  const Carve C = carve(P.R, P.TM, P.N, NX, BT, P.slots);
+  const Carve C = carve_of<NX>(P);
   const int T = P.T, N = P.N, m = P.m, R = P.R, TM = P.TM;
-  float* xbar = smem + C.xbar;
-  float* ubar = smem + C.ubar;
-  float* xp = smem + C.xp;
-  float* up = smem + C.up;
+  float* xbar = bulk_base(smem, P) + C.xbar;
+  float* ubar = bulk_base(smem, P) + C.ubar;
+  float* xp = bulk_base(smem, P) + C.xp;
+  float* up = bulk_base(smem, P) + C.up;
   const float* w0 = smem + C.w0;   // multipliers, high part
   const float* w2 = smem + C.w2;   // low part
   {
@@ -1336,7 +1382,7 @@ __device__ __noinline__ int fwd_recover_ls(const ProbRec* rec, const float* data
   // then reduces each candidate in a fixed order.
   const int na = lp.n;
   const int ntask = (na + 1) * N;
-  double* tc = (double*)(smem + C.ls);
+  double* tc = (double*)(bulk_base(smem, P) + C.ls);
   double* td = tc + (kMaxAlphas + 1) * N;
   double* res = td + (kMaxAlphas + 1) * N;
   double dn = 0.0;
@@ -1452,9 +1498,9 @@ __device__ __noinline__ int fwd_finish(const ProbRec* rec, const float* data, fl
   extern __shared__ float smem[];
   const int tid = threadIdx.x, BT = blockDim.x;
   const Prob P = make_prob<NX>(*rec, data, ws);
-  const Carve C = carve(P.R, P.TM, P.N, NX, BT, P.slots);
-  const float* xbar = smem + C.xbar;
-  const float* ubar = smem + C.ubar;
+  const Carve C = carve_of<NX>(P);
+  const float* xbar = bulk_base(smem, P) + C.xbar;
+  const float* ubar = bulk_base(smem, P) + C.ubar;
   float* solx = sol + rec->sol_off;
   float* solu = solx + P.R;
   int bad = 0;
@@ -1480,14 +1526,14 @@ __device__ __noinline__ void bwd_begin(const ProbRec* rec, const float* data, fl
   extern __shared__ float smem[];
   const int tid = threadIdx.x, BT = blockDim.x;
   const Prob P = make_prob<NX>(*rec, data, ws);
-  const Carve C = carve(P.R, P.TM, P.N, NX, BT, P.slots);
+  const Carve C = carve_of<NX>(P);
   const int R = P.R, TM = P.TM;
-  zero_pads<NX>(smem, C, R, BT, P.slots);
+  zero_pads<NX>(smem, C, P);
   for (int i = tid; i < R; i += BT) {
-    smem[C.xp + i] = P.W[P.L.xp + i];
-    smem[C.lam + i] = P.W[P.L.lam + i];
+    bulk_base(smem, P)[C.xp + i] = P.W[P.L.xp + i];
+    bulk_base(smem, P)[C.lam + i] = P.W[P.L.lam + i];
   }
-  for (int i = tid; i < TM; i += BT) smem[C.up + i] = P.W[P.L.up + i];
+  for (int i = tid; i < TM; i += BT) bulk_base(smem, P)[C.up + i] = P.W[P.L.up + i];
   const float* dlx = dl + rec->sol_off;
   const float* dlu = dlx + R;
   const float* dll = dlu + TM;
@@ -1512,12 +1558,12 @@ __device__ __noinline__ ResNorms bwd_residual64(const ProbRec* rec, const float*
   extern __shared__ float smem[];
   const int tid = threadIdx.x, BT = blockDim.x;
   const Prob P = make_prob<NX>(*rec, data, ws);
-  const Carve C = carve(P.R, P.TM, P.N, NX, BT, P.slots);
+  const Carve C = carve_of<NX>(P);
   const int T = P.T, m = P.m, R = P.R, TM = P.TM;
   const float* w0 = smem + C.w0 + NX;
   const float* w2 = smem + C.w2 + NX;
   float* w1 = smem + C.w1;
-  double* xz = (double*)(smem + C.ls);
+  double* xz = (double*)(bulk_base(smem, P) + C.ls);
   double* uz = xz + R;
   const float* dlx = dl + rec->sol_off;
   const float* dlu = dlx + R;
@@ -1587,13 +1633,13 @@ __device__ __noinline__ void bwd_finish(const ProbRec* rec, const float* data, f
   extern __shared__ float smem[];
   const int tid = threadIdx.x, BT = blockDim.x;
   const Prob P = make_prob<NX>(*rec, data, ws);
-  const Carve C = carve(P.R, P.TM, P.N, NX, BT, P.slots);
+  const Carve C = carve_of<NX>(P);
   const int T = P.T, m = P.m, R = P.R, TM = P.TM;
-  float* xt = smem + C.xbar;
-  float* ut = smem + C.ubar;
-  const float* xpl = smem + C.xp;
-  const float* upl = smem + C.up;
-  const float* laml = smem + C.lam;
+  float* xt = bulk_base(smem, P) + C.xbar;
+  float* ut = bulk_base(smem, P) + C.ubar;
+  const float* xpl = bulk_base(smem, P) + C.xp;
+  const float* upl = bulk_base(smem, P) + C.up;
+  const float* laml = bulk_base(smem, P) + C.lam;
   const float* w0 = smem + C.w0;
   const float* lw = w0 + NX;                // lambda~, high part (unpadded view)
   const float* lwl = smem + C.w2 + NX;      // low part
@@ -1727,8 +1773,8 @@ struct KEntry {
 
 // Loads this thread's rows (Schur, preconditioner, right-hand side).
 template <int NX, int SLOTS, bool REG>
-__device__ __forceinline__ void load_rows(const Prob& P, float (&S)[SLOTS][3 * NX],
-                                          float (&Ph)[SLOTS][3 * NX], float (&g)[SLOTS]) {
+__device__ __forceinline__ void load_rows(const Prob& P, RowRegs<NX, SLOTS, REG>& S,
+                                          RowRegs<NX, SLOTS, REG>& Ph, float (&g)[SLOTS]) {
   const int tid = threadIdx.x, BT = blockDim.x;
   const float* blk = P.W + P.L.blk;
   const float* gv = P.W + P.L.g;
@@ -1740,8 +1786,8 @@ __device__ __forceinline__ void load_rows(const Prob& P, float (&S)[SLOTS][3 * N
     if constexpr (REG) {
 #pragma unroll
       for (int j = 0; j < 3 * NX; ++j) {
-        S[s][j] = ok ? blk[(int64_t)j * P.R + rho] : 0.f;
-        Ph[s][j] = ok ? blk[(int64_t)(3 * NX + j) * P.R + rho] : 0.f;
+        S[s][j] = ok ? blk[blk_at<NX>(rho, j)] : 0.f;
+        Ph[s][j] = ok ? blk[blk_at<NX>(rho, 3 * NX + j)] : 0.f;
       }
     }
   }
@@ -1756,8 +1802,8 @@ __device__ __forceinline__ void load_rows(const Prob& P, float (&S)[SLOTS][3 * N
 // relative tolerance ref_tol, stop once the residual meets the KKT target
 // (||r||_2 <= kkt_tol ||rhs||_2).
 template <int NX, int SLOTS, bool REG, typename ResidualFn>
-__device__ __forceinline__ int qp_solve(const Prob& P, const Lds& sh, float (&S)[SLOTS][3 * NX],
-                                        float (&Ph)[SLOTS][3 * NX], const float (&g)[SLOTS],
+__device__ __forceinline__ int qp_solve(const Prob& P, const Lds& sh, RowRegs<NX, SLOTS, REG>& S,
+                                        RowRegs<NX, SLOTS, REG>& Ph, const float (&g)[SLOTS],
                                         float (&hi)[SLOTS], float (&lo)[SLOTS], int steps,
                                         int maxit, float tol, float abs_tol, float ref_tol,
                                         float kkt_tol, int& flags, int& redi, int maxit_flag,
@@ -1821,7 +1867,8 @@ __global__ __launch_bounds__(MAXBT) void forward_kernel(KArgs a) {
     const float rtol = a.refine_tol > 0.f ? a.refine_tol : a.pcg_tol;
     for (int k = 0; k < a.sqp_iters; ++k) {
       if (fwd_blocks<NX>(rec, a.data, a.ws)) flags |= DMPC_PROB_NONPD;
-      float S[SLOTS][3 * NX], Ph[SLOTS][3 * NX], g[SLOTS];
+      RowRegs<NX, SLOTS, REG> S, Ph;
+      float g[SLOTS];
       load_rows<NX, SLOTS, REG>(P, S, Ph, g);
       pcg_total += qp_solve<NX, SLOTS, REG>(
           P, sh, S, Ph, g, lam, lo, a.refine_steps, maxit, a.pcg_tol, a.pcg_abs_tol, rtol,
@@ -1864,7 +1911,8 @@ __global__ __launch_bounds__(MAXBT) void backward_kernel(KArgs a) {
     const Prob P = make_prob<NX>(*rec, a.data, a.ws);
     const Lds sh = lds_of<NX>(smem, P);
     bwd_begin<NX>(rec, a.data, a.ws, a.dl);
-    float S[SLOTS][3 * NX], Ph[SLOTS][3 * NX], g[SLOTS], lt[SLOTS], lo[SLOTS];
+    RowRegs<NX, SLOTS, REG> S, Ph;
+    float g[SLOTS], lt[SLOTS], lo[SLOTS];
     load_rows<NX, SLOTS, REG>(P, S, Ph, g);
     const float* alv = a.adj + rec->sol_off + P.R + P.TM;
 #pragma unroll

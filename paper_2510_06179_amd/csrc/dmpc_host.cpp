@@ -52,7 +52,7 @@ struct dmpc_plan {
 
 namespace dmpc {
 
-const int kStateSizes[] = {2, 3, 4, 8, 12, 16};
+const int kStateSizes[] = {2, 3, 4, 8, 12, 16, 32};
 
 bool nx_supported(int nx) {
   for (int v : kStateSizes)
@@ -92,7 +92,7 @@ bool in_arena(int64_t off, int64_t len, int64_t arena) {
 
 dmpc_status check_problem(const dmpc_problem& p, int64_t data_len, int64_t sol_len) {
   if (p.T < 1 || p.T > 1000000) return DMPC_ERR_INVALID_ARG;
-  if (p.nx < 1 || p.nx > 16 || p.nu < 1 || p.nu > kMaxNu) return DMPC_ERR_INVALID_ARG;
+  if (p.nx < 1 || p.nx > kMaxNx || p.nu < 1 || p.nu > kMaxNu) return DMPC_ERR_INVALID_ARG;
   if (p.reserved != 0) return DMPC_ERR_INVALID_ARG;
   switch (p.dyn) {
     case DMPC_DYN_LTV:
@@ -139,7 +139,7 @@ struct Variant {
 const Variant kVariants[] = {
     {1, 64, 1},  {2, 64, 1},  {4, 64, 1},  {8, 64, 1},  {1, 128, 1}, {2, 128, 1}, {4, 128, 1},
     {8, 128, 1}, {1, 256, 1}, {2, 256, 1}, {4, 256, 1}, {1, 512, 1}, {2, 512, 1}, {1, 1024, 1},
-    {4, 256, 0}, {8, 256, 0}, {8, 512, 0},
+    {4, 256, 0}, {8, 256, 0}, {8, 512, 0}, {2, 1024, 0}, {4, 1024, 0}, {8, 1024, 0}, {12, 1024, 0},
 };
 
 // Process-wide tuning table (rows of 7 int32, see dmpc_set_tuning).
@@ -186,6 +186,12 @@ bool choose_cfg(const dmpc_problem& p, int force_bt, LaunchCfg* c) {
     }
   }
   return found;
+}
+
+int problem_flags(const dmpc_problem& p, int force_bt) {
+  LaunchCfg c;
+  if (!nx_supported(p.nx) || !choose_cfg(p, force_bt, &c)) return 0;
+  return rec_flags(p.T, p.nx, p.nu, c.bt, c.slots, c.reg);
 }
 
 }  // namespace dmpc
@@ -358,12 +364,11 @@ dmpc_status dmpc_validate(const dmpc_problem* problems, int32_t count, int64_t d
 dmpc_status dmpc_workspace_size(const dmpc_problem* problems, int32_t count,
                                 const dmpc_opts* opts, size_t* bytes) {
   if (!bytes || count < 0 || (count > 0 && !problems)) return DMPC_ERR_INVALID_ARG;
-  (void)opts;
   int64_t total = 0;
   for (int i = 0; i < count; ++i) {
     const dmpc_problem& p = problems[i];
     if (p.T < 1 || p.nx < 1 || p.nu < 1) return DMPC_ERR_INVALID_ARG;
-    total += ws_layout(p.T, p.nx, p.nu, p.dyn).total;
+    total += ws_layout(p.T, p.nx, p.nu, p.dyn, problem_flags(p, opts ? opts->block_threads : 0)).total;
   }
   *bytes = (size_t)total * sizeof(float);
   return DMPC_OK;
@@ -442,7 +447,8 @@ dmpc_status dmpc_plan_create(dmpc_handle* h, const dmpc_problem* problems, int32
     r.sol_off = p.sol_off;
     r.ws_off = ws_off;
     r.slots = cfg[i].slots;
-    ws_off += ws_layout(p.T, p.nx, p.nu, p.dyn).total;
+    r.flags = rec_flags(p.T, p.nx, p.nu, cfg[i].bt, cfg[i].slots, cfg[i].reg);
+    ws_off += ws_layout(p.T, p.nx, p.nu, p.dyn, r.flags).total;
     pl->recs[k] = r;
     pl->pos[i] = k;
     if (k == 0 || key(order[k - 1]) != key(i)) {
@@ -457,14 +463,17 @@ dmpc_status dmpc_plan_create(dmpc_handle* h, const dmpc_problem* problems, int32
     }
     Group& g = pl->groups.back();
     g.count += 1;
-    g.cfg.lds_bytes = std::max(g.cfg.lds_bytes, (size_t)lds_floats(p.T, p.nx, p.nu, g.cfg.bt, g.cfg.slots) * sizeof(float));
+    g.cfg.lds_bytes = std::max(
+        g.cfg.lds_bytes,
+        (size_t)lds_floats(p.T, p.nx, p.nu, g.cfg.bt, g.cfg.slots, r.flags) * sizeof(float));
     g.work += (double)(p.T + 1) * p.nx * p.nx;
     pl->grp[k] = (int)pl->groups.size() - 1;
   }
   pl->ws_bytes = (size_t)ws_off * sizeof(float);
   for (Group& g : pl->groups) {
     g.cfg.grid = g.count;
-    if (g.cfg.lds_bytes > 160 * 1024 || !kernel_available(g.cfg.nx, g.cfg.slots, g.cfg.maxbt, g.cfg.reg)) {
+    if (g.cfg.lds_bytes > (size_t)kLdsBytes ||
+        !kernel_available(g.cfg.nx, g.cfg.slots, g.cfg.maxbt, g.cfg.reg)) {
       delete pl;
       return DMPC_ERR_UNSUPPORTED;
     }
@@ -529,7 +538,7 @@ dmpc_status dmpc_plan_workspace_size(const dmpc_plan* plan, size_t* bytes) {
 dmpc_status dmpc_workspace_offsets(const dmpc_plan* plan, int32_t index, int64_t* out) {
   if (!plan || !out || index < 0 || index >= plan->count) return DMPC_ERR_INVALID_ARG;
   const ProbRec& r = plan->recs[plan->pos[index]];
-  const WsLayout L = ws_layout(r.T, r.nx, r.nu, r.dyn);
+  const WsLayout L = ws_layout(r.T, r.nx, r.nu, r.dyn, r.flags);
   const int64_t v[7] = {L.xlin, L.ulin, L.xp, L.up, L.lam, L.Qd, L.Rd};
   for (int i = 0; i < 7; ++i) out[i] = r.ws_off + v[i];
   return DMPC_OK;

@@ -18,9 +18,16 @@ namespace dmpc {
 constexpr float kPdEps = 1e-6f;   // eigenvalue floor of the PD projection (Sec. 3.1)
 constexpr int kMaxAlphas = 8;
 constexpr int kMaxNu = 16;
+constexpr int kMaxNx = 32;
 constexpr int kCartpoleParams = 5;
 constexpr int kBicycleParams = 16;
 constexpr int kAlignFloats = 64;  // per-problem workspace alignment (256 B)
+constexpr int kLdsBytes = 160 * 1024;   // LDS of one workgroup on gfx950
+
+// ProbRec::flags
+constexpr int kRecRegRows = 1;   // the kernel keeps the Schur rows in registers
+constexpr int kRecBulkWs = 2;    // iterate, QP solution, multipliers and the line-search
+                                 // region live in the workspace (too large for LDS)
 
 // Device record of one problem (96 bytes).
 struct ProbRec {
@@ -28,7 +35,7 @@ struct ProbRec {
   int64_t dyn_off, cost_off, x0_off, sol_off;
   int64_t ws_off;                                   // float offset into the workspace
   int32_t slots;                                    // rows per thread of its kernel
-  int32_t pad0;
+  int32_t flags;                                    // kRec* bits
   int64_t pad[2];
 };
 
@@ -39,16 +46,20 @@ struct WsLayout {
   int64_t A, B, c;                // linearised dynamics (nonlinear models only)
   int64_t Ad, Bd, cd;             // the same in double (float offsets, 8-byte aligned)
   int64_t Dinv;                   // diagonal Schur blocks inverted [N][nx][nx]
-  int64_t blk;                    // saved rows of S^ and Phi^-1: [N*nx][6*nx]
+  int64_t blk;                    // saved rows of S^ and Phi^-1, 6*nx coefficients per row,
+                                  // in tiles of 64 rows (see blk_at in dmpc_device.h)
   int64_t xp, up, lam;            // last QP solution and multipliers
   int64_t xlin, ulin;             // last linearisation point
   int64_t g;                      // right-hand side of the Schur system [N*nx]
+  int64_t bulk;                   // kRecBulkWs: the regions that do not fit LDS (-1 if unused)
   int64_t total;
 };
 
 DMPC_HD inline int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
-DMPC_HD inline WsLayout ws_layout(int T, int nx, int nu, int dyn) {
+DMPC_HD inline int64_t bulk_floats(int64_t N, int64_t R, int64_t TM);
+
+DMPC_HD inline WsLayout ws_layout(int T, int nx, int nu, int dyn, int flags) {
   const int64_t N = T + 1, R = N * nx, TM = (int64_t)T * nu;
   WsLayout L;
   int64_t o = 0;
@@ -76,13 +87,19 @@ DMPC_HD inline WsLayout ws_layout(int T, int nx, int nu, int dyn) {
   o = align_up(o, 4);
   L.Dinv = o; o += N * nx * nx;
   o = align_up(o, 4);
-  L.blk = o; o += R * 6 * nx;
+  L.blk = o; o += align_up(R, 64) * 6 * nx;
   L.xp = o; o += R;
   L.up = o; o += TM;
   L.lam = o; o += R;
   L.xlin = o; o += R;
   L.ulin = o; o += TM;
   L.g = o; o += R;
+  if (flags & kRecBulkWs) {
+    o = align_up(o, 4);
+    L.bulk = o; o += bulk_floats(N, R, TM);
+  } else {
+    L.bulk = -1;
+  }
   L.total = align_up(o, kAlignFloats);
   return L;
 }
@@ -113,13 +130,29 @@ DMPC_HD inline int64_t ls_floats(int64_t N, int64_t R, int64_t TM) {
   const int64_t b = 2 * (R + TM);
   return a > b ? a : b;
 }
-DMPC_HD inline int64_t lds_floats(int T, int nx, int nu, int bt, int slots) {
+// Regions that may live in LDS or in the workspace: iterate, QP solution
+// (x, u each), multipliers, line-search / refinement region.
+DMPC_HD inline int64_t bulk_floats(int64_t N, int64_t R, int64_t TM) {
+  return 3 * a4h(R) + 2 * a4h(TM) + a4h(ls_floats(N, R, TM));
+}
+// Length of one vector window: a zero pad of nx, an entry per row (per row of
+// every slot when the rows are in registers: those PCG loops have no row
+// guard), and 2 nx of zero pad.
+DMPC_HD inline int64_t win_floats(int64_t R, int nx, int bt, int slots, int flags) {
+  return a4h(((flags & kRecRegRows) ? (int64_t)slots * bt : R) + 3 * nx);
+}
+DMPC_HD inline int64_t lds_floats(int T, int nx, int nu, int bt, int slots, int flags) {
   const int64_t N = T + 1, R = N * nx, TM = (int64_t)T * nu;
-  return 3 * a4h(R) + 2 * a4h(TM)        // iterate / QP solution / multipliers
-         + 3 * a4h((int64_t)slots * bt + 3 * nx)   // three padded windows
+  return ((flags & kRecBulkWs) ? 0 : bulk_floats(N, R, TM))
+         + 3 * win_floats(R, nx, bt, slots, flags)   // three padded windows
          + 4 * (int64_t)bt               // Gauss-Jordan pivot rows, double buffered
-         + 128                           // reductions
-         + ls_floats(N, R, TM);          // line search / refinement primal (double)
+         + 128;                          // reductions
+}
+// Record flags of a problem run by a kernel variant: register rows as the
+// variant has them; the bulk regions go to the workspace when LDS is too small.
+DMPC_HD inline int rec_flags(int T, int nx, int nu, int bt, int slots, int reg) {
+  const int f = reg ? kRecRegRows : 0;
+  return lds_floats(T, nx, nu, bt, slots, f) * 4 > kLdsBytes ? (f | kRecBulkWs) : f;
 }
 
 // Launch-time arguments of the kernels.
@@ -157,6 +190,7 @@ bool nx_supported(int nx);
 dmpc_status check_opts(const dmpc_opts* o);
 dmpc_status check_problem(const dmpc_problem& p, int64_t data_len, int64_t sol_len);
 bool choose_cfg(const dmpc_problem& p, int force_bt, LaunchCfg* c);
+int problem_flags(const dmpc_problem& p, int force_bt);   // ProbRec::flags under choose_cfg
 KArgs make_kargs(const dmpc_opts& o, const ProbRec* recs, const float* data, float* sol, void* ws,
                  const float* dl, float* adj, float* grad, int32_t* status, int32_t* info);
 

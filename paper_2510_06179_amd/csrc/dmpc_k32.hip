@@ -1,0 +1,23 @@
+// Kernel instantiations for nx = 32 (see dmpc_device.h).  Rows of S^ and
+// Phi^-1 are read from the workspace (3 x 32 coefficients per row do not fit
+// in registers next to the PCG vectors); the iterate, QP solution and
+// line-search region of long horizons live in the workspace too.
+#include "dmpc_device.h"
+
+namespace dmpc {
+
+#define DMPC_K(NX, SL, MB, RG) \
+  {NX, SL, MB, RG, forward_kernel<NX, SL, MB, (RG != 0)>, backward_kernel<NX, SL, MB, (RG != 0)>}
+
+// (rows per thread, launch bound, rows of S^ and Phi^-1 held in registers)
+static const KEntry kEntries[] = {
+    DMPC_K(32, 2, 1024, 0), DMPC_K(32, 4, 1024, 0), DMPC_K(32, 8, 1024, 0),
+    DMPC_K(32, 12, 1024, 0),
+};
+
+const KEntry* kernel_entries_nx32(int* n) {
+  *n = (int)(sizeof(kEntries) / sizeof(kEntries[0]));
+  return kEntries;
+}
+
+}  // namespace dmpc

@@ -18,11 +18,13 @@ DMPC_DECL(4)
 DMPC_DECL(8)
 DMPC_DECL(12)
 DMPC_DECL(16)
+DMPC_DECL(32)
 
 static const KEntry* find_entry(int nx, int slots, int maxbt, int reg) {
   typedef const KEntry* (*Getter)(int*);
   static const Getter getters[] = {kernel_entries_nx2, kernel_entries_nx3, kernel_entries_nx4,
-                                   kernel_entries_nx8, kernel_entries_nx12, kernel_entries_nx16};
+                                   kernel_entries_nx8, kernel_entries_nx12, kernel_entries_nx16,
+                                   kernel_entries_nx32};
   for (Getter g : getters) {
     int n = 0;
     const KEntry* e = g(&n);

@@ -52,6 +52,7 @@ struct Session {
   bool used = false;
   dmpc_problem p{};      // offsets rebased into the server stores
   LaunchCfg cfg{};
+  int flags = 0;         // ProbRec::flags
   int64_t data_len = 0, sol_len = 0, ws_floats = 0;
   int queued = 0;        // requests pending or in flight
   bool busy = false;     // a request in flight
@@ -61,7 +62,7 @@ struct Request {
   int64_t ticket = 0;
   int32_t session = 0, backward = 0;
   bool has_x0 = false, has_dl = false;
-  float x0[16];
+  float x0[kMaxNx];
   std::vector<float> dl;
   double t_submit = 0;
 };
@@ -174,7 +175,7 @@ dmpc_status check_config(const dmpc_server_config* c) {
   if (!c) return DMPC_ERR_INVALID_ARG;
   if (c->max_sessions < 1 || c->max_batch < 1 || c->max_batch > 65536) return DMPC_ERR_INVALID_ARG;
   if (c->max_inflight < 1 || c->max_inflight > 8) return DMPC_ERR_INVALID_ARG;
-  if (c->max_T < 1 || c->max_nx < 1 || c->max_nx > 16 || c->max_nu < 1 || c->max_nu > kMaxNu)
+  if (c->max_T < 1 || c->max_nx < 1 || c->max_nx > kMaxNx || c->max_nu < 1 || c->max_nu > kMaxNu)
     return DMPC_ERR_INVALID_ARG;
   if (c->max_pending < 0 || c->batch_window_us < 0 || c->batch_window_us > 1000000)
     return DMPC_ERR_INVALID_ARG;
@@ -318,6 +319,7 @@ bool dmpc_server::launch_group(Slot* s) {
     rec.sol_off = ss.p.sol_off;
     rec.ws_off = ws_off;
     rec.slots = ss.cfg.slots;
+    rec.flags = ss.flags;
     ws_off += ss.ws_floats;
     if (r.has_x0) {
       segs.push_back(Seg{(const uint32_t*)(s->d_in + pay), (uint32_t*)(d_data + ss.p.x0_off), ss.p.nx});
@@ -384,7 +386,9 @@ bool dmpc_server::launch_group(Slot* s) {
     g.count += 1;
     g.nbwd += s->reqs[k].backward ? 1 : 0;
     g.cfg.lds_bytes = std::max(g.cfg.lds_bytes,
-                               (size_t)lds_floats(ss.p.T, ss.p.nx, ss.p.nu, g.cfg.bt, g.cfg.slots) * sizeof(float));
+                               (size_t)lds_floats(ss.p.T, ss.p.nx, ss.p.nu, g.cfg.bt, g.cfg.slots,
+                                                  ss.flags) *
+                                   sizeof(float));
   }
   for (const Range& g : ranges) {
     LaunchCfg c = g.cfg;
@@ -531,8 +535,8 @@ dmpc_status dmpc_server_create(const dmpc_server_config* cfg, dmpc_server** out)
   sv->staging = cfg->staging_bytes > 0 ? cfg->staging_bytes : kDefaultStaging;
   // one request of the largest shape must fit a share and the staging
   const int64_t ws_max =
-      4 * std::max(ws_layout(cfg->max_T, cfg->max_nx, cfg->max_nu, DMPC_DYN_LTV).total,
-                   ws_layout(cfg->max_T, cfg->max_nx, cfg->max_nu, DMPC_DYN_CARTPOLE).total);
+      4 * std::max(ws_layout(cfg->max_T, cfg->max_nx, cfg->max_nu, DMPC_DYN_LTV, kRecBulkWs).total,
+                   ws_layout(cfg->max_T, cfg->max_nx, cfg->max_nu, DMPC_DYN_CARTPOLE, kRecBulkWs).total);
   const int64_t one_in = 1024 + (int64_t)sizeof(ProbRec) + 4 * sizeof(Seg) +
                          4 * (a4(cfg->max_nx) + sv->sol_stride);
   const int64_t one_out = 1024 + 20 + 4 * (sv->sol_stride + sv->data_stride);
@@ -643,9 +647,10 @@ dmpc_status dmpc_server_add_session(dmpc_server* sv, int32_t session, const dmpc
   if (st != DMPC_OK) return st;
   LaunchCfg c;
   if (!nx_supported(p.nx) || !choose_cfg(p, sv->cfg.opts.block_threads, &c)) return DMPC_ERR_UNSUPPORTED;
-  if ((size_t)lds_floats(p.T, p.nx, p.nu, c.bt, c.slots) * sizeof(float) > 160 * 1024)
+  const int flags = rec_flags(p.T, p.nx, p.nu, c.bt, c.slots, c.reg);
+  if ((size_t)lds_floats(p.T, p.nx, p.nu, c.bt, c.slots, flags) * sizeof(float) > (size_t)kLdsBytes)
     return DMPC_ERR_UNSUPPORTED;
-  const int64_t ws = ws_layout(p.T, p.nx, p.nu, p.dyn).total;
+  const int64_t ws = ws_layout(p.T, p.nx, p.nu, p.dyn, flags).total;
   if (4 * ws > sv->ws_share) return DMPC_ERR_NOMEM;
   std::lock_guard<std::mutex> lk(sv->mu);
   Session& ss = sv->sessions[session];
@@ -675,6 +680,7 @@ dmpc_status dmpc_server_add_session(dmpc_server* sv, int32_t session, const dmpc
   ss.p.x0_off += dbase;
   ss.p.sol_off = sbase;
   ss.cfg = c;
+  ss.flags = flags;
   ss.data_len = data_len;
   ss.sol_len = sol_len;
   ss.ws_floats = ws;

@@ -33,6 +33,10 @@ def _shapes():
                 rng = np.random.default_rng(1000 * nx + T)
                 return [W.ltv_problem(rng, T, nx, 4 if nx >= 12 else 2) for _ in range(1024)]
             out.append((f"ltv nx={nx} T={T}", nx, T, mk, 8))
+    def big():
+        rng = np.random.default_rng(32256)
+        return [W.ltv_problem(rng, 256, 32, 8) for _ in range(256)]
+    out.append(("ltv nx=32 T=256", 32, 256, big, 1))
     out.append(("cartpole nx=4 T=50", 4, 50, lambda: W.cartpole_batch(0, batch=1024), 10))
     out.append(("bicycle nx=8 T=64", 8, 64, lambda: W.bicycle_batch(0, batch=512), 10))
     return out

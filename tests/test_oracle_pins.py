@@ -342,3 +342,24 @@ def test_softplus_theta_vjp_matches_fd():
               - _loss(pm, xbar, ubar, g["gx"], g["gu"], 0.0)) / (2 * h)
         an = np.sum(grads[key] * dirn)
         assert an == pytest.approx(fd, rel=2e-6, abs=1e-8), key
+
+
+def test_blockwise_kkt_residual_equals_dense():
+    # the stage-by-stage residual is the dense ||K w - rhs|| / ||rhs|| written
+    # out by blocks: equal on random points and problems of every model
+    rng = np.random.default_rng(11)
+    cases = [W.ltv_problem(rng, 6, 3, 2), W.cartpole_batch(2, batch=1, T=7)[0],
+             W.bicycle_batch(3, batch=1, T=5)[0]]
+    for p in cases:
+        T, nx, nu = p["T"], p["nx"], p["nu"]
+        xb, ub, _ = oracle.sqp.initial_guess(p)
+        qpd = oracle.qp.qp_data(p, xb, ub)
+        for _ in range(3):
+            x = rng.standard_normal((T + 1, nx))
+            u = rng.standard_normal((T, nu))
+            lam = rng.standard_normal((T + 1, nx))
+            a = oracle.qp.kkt_residual(qpd, p["x0"], x, u, lam)
+            b = oracle.qp.kkt_residual_blocks(qpd, p["x0"], x, u, lam)
+            assert abs(a - b) <= 1e-12 * max(a, 1.0), (a, b)
+        s = oracle.qp.solve_qp(qpd, p["x0"])
+        assert oracle.qp.kkt_residual_blocks(qpd, p["x0"], s["x"], s["u"], s["lam"]) < 1e-12

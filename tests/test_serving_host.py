@@ -43,7 +43,7 @@ def test_config_validation():
     with pytest.raises(_lib.DmpcError):
         dry(max_batch=0)
     with pytest.raises(_lib.DmpcError):
-        dry(max_nx=17)
+        dry(max_nx=33)
     # one request of the largest shape must fit a share of the budget
     with pytest.raises(_lib.DmpcError):
         dry(hbm_budget=1 << 16)
