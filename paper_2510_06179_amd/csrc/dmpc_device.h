@@ -707,14 +707,13 @@ __device__ __forceinline__ R adjoint_rhs_row(const Prob& P, int t, int i, const 
   return v;
 }
 
-// Storage of the Schur and preconditioner rows in the workspace: tiles of 64
-// rows, coefficient-major inside a tile -- coefficient j of row rho at
-// (rho / 64) * 6 NX * 64 + 64 j + rho % 64.  A wave reads one coefficient of
-// 64 consecutive rows as one contiguous 256-byte access, and a thread walks
-// its row with constant offsets of 64 floats.
+// Storage of the Schur and preconditioner rows in the workspace: row-major,
+// 6 NX coefficients per row (S^ row, then Phi^-1 row).  (A layout in tiles of
+// 64 rows, coefficient-major, made the wave's loads contiguous but measured
+// two to four times slower on the workspace-row kernels.)
 template <int NX>
 __device__ __forceinline__ int64_t blk_at(int rho, int j) {
-  return (int64_t)(rho >> 6) * (6 * NX * 64) + 64 * j + (rho & 63);
+  return (int64_t)rho * (6 * NX) + j;
 }
 
 // Row product with a padded LDS window: sum_j coef[j] * win[j], win = w + t*NX.
@@ -746,13 +745,17 @@ __device__ __forceinline__ float row_dot(const float* coef, const float* win) {
   }
   return (a0 + a1) + a2;
 }
-// Row product with the coefficients read from the workspace (tiled storage:
-// coefficient j at coef[64 j]).  The row address passes through an empty asm:
-// the coefficients do not change during the PCG, and without it the compiler
-// hoists their loads out of the loop -- 6 nx values per row kept live, which
-// spill.
+// Row product with the coefficients read from the workspace (row-major).  The coefficients do not change during the
+// PCG, so the compiler hoists their loads out of the loop and keeps what it
+// can in registers (the rest in AGPRs and swizzled scratch): measured faster
+// than re-reading the rows for nx <= 16.  For nx = 32 that would keep
+// 6 x 32 values per row live, so there the row address passes through an
+// empty asm at each product and the rows are re-read every iteration.
 template <int NX>
 __device__ __forceinline__ float row_dot_ws(const float* coef, const float* win) {
+  if constexpr (NX <= 16) {
+    return row_dot<NX>(coef, win);
+  }
   uint64_t a = (uint64_t)(uintptr_t)coef;
   asm volatile("" : "+v"(a));
   coef = (const float*)(uintptr_t)a;
@@ -760,7 +763,7 @@ __device__ __forceinline__ float row_dot_ws(const float* coef, const float* win)
 #pragma unroll
   for (int b = 0; b < 3; ++b) {
 #pragma unroll
-    for (int j = 0; j < NX; ++j) acc[b] = fmaf(coef[64 * (b * NX + j)], win[b * NX + j], acc[b]);
+    for (int j = 0; j < NX; ++j) acc[b] = fmaf(coef[b * NX + j], win[b * NX + j], acc[b]);
   }
   return (acc[0] + acc[1]) + acc[2];
 }
@@ -888,7 +891,50 @@ __device__ __forceinline__ bool precond_rows(const Prob& P, float* piv) {
   float* Dinv = P.W + P.L.Dinv;
   const float* iQ = P.W + P.L.iQ;
   bool nonpd = false;
-  for (int c0 = 0; c0 < P.R; c0 += BTb) {
+  if constexpr (NX <= 8) {
+    // small blocks: one thread inverts a whole D_t in registers (the same
+    // operations in the same order as the row-parallel elimination below)
+    for (int t = tid; t < P.N; t += BT) {
+      float a[NX][NX], b[NX][NX];
+#pragma unroll
+      for (int i = 0; i < NX; ++i)
+#pragma unroll
+        for (int j = 0; j < NX; ++j) {
+          a[i][j] = blk[blk_at<NX>(t * NX + i, NX + j)];
+          b[i][j] = (i == j) ? 1.f : 0.f;
+        }
+#pragma unroll
+      for (int kk = 0; kk < NX; ++kk) {
+        float pv = a[kk][kk];
+        if (!(pv > 0.f)) {
+          nonpd = true;
+          pv = 1.f;
+        }
+        const float inv = 1.f / pv;
+#pragma unroll
+        for (int j = 0; j < NX; ++j) {
+          a[kk][j] *= inv;
+          b[kk][j] *= inv;
+        }
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+          if (i == kk) continue;
+          const float f = a[i][kk];
+#pragma unroll
+          for (int j = 0; j < NX; ++j) {
+            a[i][j] = fmaf(-f, a[kk][j], a[i][j]);
+            b[i][j] = fmaf(-f, b[kk][j], b[i][j]);
+          }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < NX; ++i)
+#pragma unroll
+        for (int j = 0; j < NX; ++j) Dinv[(t * NX + i) * NX + j] = b[i][j];
+    }
+    __syncthreads();
+  }
+  for (int c0 = 0; NX > 8 && c0 < P.R; c0 += BTb) {
     const int rho = c0 + tid;
     const bool act = tid < BTb && rho < P.R;
     const int tl = tid / NX, i = tid - tl * NX;
@@ -976,9 +1022,9 @@ __device__ __forceinline__ bool precond_rows(const Prob& P, float* piv) {
     float* b = blk + blk_at<NX>(rho, 3 * NX);
 #pragma unroll
     for (int j = 0; j < NX; ++j) {
-      b[64 * j] = lo[j];
-      b[64 * (NX + j)] = dr[j];
-      b[64 * (2 * NX + j)] = up[j];
+      b[j] = lo[j];
+      b[NX + j] = dr[j];
+      b[2 * NX + j] = up[j];
     }
   }
   return nonpd;
@@ -1000,13 +1046,13 @@ template <int NX, int SLOTS, bool REG>
 __device__ __forceinline__ const float* coefS(const Prob& P, RowRegs<NX, SLOTS, REG>& S, int s,
                                               int rho) {
   if constexpr (REG) return S[s];
-  return P.W + P.L.blk + blk_at<NX>(rho, 0);          // stride 64
+  return P.W + P.L.blk + blk_at<NX>(rho, 0);
 }
 template <int NX, int SLOTS, bool REG>
 __device__ __forceinline__ const float* coefP(const Prob& P, RowRegs<NX, SLOTS, REG>& Ph, int s,
                                               int rho) {
   if constexpr (REG) return Ph[s];
-  return P.W + P.L.blk + blk_at<NX>(rho, 3 * NX);     // stride 64
+  return P.W + P.L.blk + blk_at<NX>(rho, 3 * NX);
 }
 
 template <int NX, int SLOTS, bool REG>
@@ -1250,7 +1296,7 @@ __device__ __forceinline__ ResNorms block_sum2(float a, float b, float* red, int
 // (rounded to float) to w1[NX + rho]; returns the norms of r and of the KKT
 // right-hand side [-b; d] = [-(q, r); (x_s, c)] (Eq. ocp:KKT), identical in
 // every thread.
-template <int NX, int SLOTS>
+template <int NX>
 __device__ __noinline__ ResNorms fwd_residual64(const ProbRec* rec, const float* data, float* ws) {
   extern __shared__ float smem[];
   const int tid = threadIdx.x, BT = blockDim.x;
@@ -1267,23 +1313,17 @@ __device__ __noinline__ ResNorms fwd_residual64(const ProbRec* rec, const float*
   const float* rr = P.W + P.L.r;
   const double* iQd = (const double*)(P.W + P.L.iQd);
   const double* iRd = (const double*)(P.W + P.L.iRd);
-  // the thread's rows are rho = tid + s * BT, s < SLOTS (slots * BT >= R):
-  // unrolled so that the loads of all of them are in flight together
+  for (int rho = tid; rho < R; rho += BT) {
+    const int t = rho / NX, i = rho - t * NX;
+    double acc = (double)q[rho] + ((double)w0[rho] + (double)w2[rho]);
+    if (t < T) {
+      const int a0 = t * NX * NX;
 #pragma unroll
-  for (int s = 0; s < SLOTS; ++s) {
-    const int rho = tid + s * BT;
-    if (rho < R) {
-      const int t = rho / NX, i = rho - t * NX;
-      double acc = (double)q[rho] + ((double)w0[rho] + (double)w2[rho]);
-      if (t < T) {
-        const int a0 = t * NX * NX;
-#pragma unroll
-        for (int k = 0; k < NX; ++k)
-          acc -= ldA<double>(P, a0 + k * NX + i) *
-                 ((double)w0[(t + 1) * NX + k] + (double)w2[(t + 1) * NX + k]);
-      }
-      xz[rho] = -acc * iQd[rho];
+      for (int k = 0; k < NX; ++k)
+        acc -= ldA<double>(P, a0 + k * NX + i) *
+               ((double)w0[(t + 1) * NX + k] + (double)w2[(t + 1) * NX + k]);
     }
+    xz[rho] = -acc * iQd[rho];
   }
   for (int idx = tid; idx < TM; idx += BT) {
     const int t = idx / m, l = idx - t * m;
@@ -1297,30 +1337,26 @@ __device__ __noinline__ ResNorms fwd_residual64(const ProbRec* rec, const float*
   }
   __syncthreads();
   float r2 = 0.f, b2 = 0.f;
+  for (int rho = tid; rho < R; rho += BT) {
+    const int t = rho / NX, i = rho - t * NX;
+    double res;
+    float dv;
+    if (t == 0) {
+      dv = P.x0[i];
+      res = xz[i] - (double)dv;
+    } else {
+      const int tt = t - 1;
+      dv = P.c[tt * NX + i];
+      double acc = ldc<double>(P, tt * NX + i);
 #pragma unroll
-  for (int s = 0; s < SLOTS; ++s) {
-    const int rho = tid + s * BT;
-    if (rho < R) {
-      const int t = rho / NX, i = rho - t * NX;
-      double res;
-      float dv;
-      if (t == 0) {
-        dv = P.x0[i];
-        res = xz[i] - (double)dv;
-      } else {
-        const int tt = t - 1;
-        dv = P.c[tt * NX + i];
-        double acc = ldc<double>(P, tt * NX + i);
-#pragma unroll
-        for (int j = 0; j < NX; ++j)
-          acc += ldA<double>(P, tt * NX * NX + i * NX + j) * xz[tt * NX + j];
-        for (int l = 0; l < m; ++l) acc += ldB<double>(P, tt * NX * m + i * m + l) * uz[tt * m + l];
-        res = xz[rho] - acc;
-      }
-      w1[NX + rho] = (float)res;
-      r2 += (float)(res * res);
-      b2 += q[rho] * q[rho] + dv * dv;
+      for (int j = 0; j < NX; ++j)
+        acc += ldA<double>(P, tt * NX * NX + i * NX + j) * xz[tt * NX + j];
+      for (int l = 0; l < m; ++l) acc += ldB<double>(P, tt * NX * m + i * m + l) * uz[tt * m + l];
+      res = xz[rho] - acc;
     }
+    w1[NX + rho] = (float)res;
+    r2 += (float)(res * res);
+    b2 += q[rho] * q[rho] + dv * dv;
   }
   for (int idx = tid; idx < TM; idx += BT) b2 += rr[idx] * rr[idx];
   const ResNorms n = block_sum2(r2, b2, smem + C.red, nwv);
@@ -1552,7 +1588,7 @@ __device__ __noinline__ void bwd_begin(const ProbRec* rec, const float* data, fl
 // the rows are  r_0 = x~_0 - dl/dlambda_0,
 //   r_{t+1} = x~_{t+1} - A_t x~_t - B_t u~_t - dl/dlambda_{t+1}.
 // Result to w1; norms of r and of the adjoint right-hand side (dl/dz, dl/dlambda).
-template <int NX, int SLOTS>
+template <int NX>
 __device__ __noinline__ ResNorms bwd_residual64(const ProbRec* rec, const float* data, float* ws,
                                                 const float* dl) {
   extern __shared__ float smem[];
@@ -1571,21 +1607,17 @@ __device__ __noinline__ ResNorms bwd_residual64(const ProbRec* rec, const float*
   const double* iQd = (const double*)(P.W + P.L.iQd);
   const double* iRd = (const double*)(P.W + P.L.iRd);
   const int nwv = (BT + 63) >> 6;
+  for (int rho = tid; rho < R; rho += BT) {
+    const int t = rho / NX, i = rho - t * NX;
+    double acc = (double)dlx[rho] - ((double)w0[rho] + (double)w2[rho]);
+    if (t < T) {
+      const int a0 = t * NX * NX;
 #pragma unroll
-  for (int s = 0; s < SLOTS; ++s) {
-    const int rho = tid + s * BT;
-    if (rho < R) {
-      const int t = rho / NX, i = rho - t * NX;
-      double acc = (double)dlx[rho] - ((double)w0[rho] + (double)w2[rho]);
-      if (t < T) {
-        const int a0 = t * NX * NX;
-#pragma unroll
-        for (int k = 0; k < NX; ++k)
-          acc += ldA<double>(P, a0 + k * NX + i) *
-                 ((double)w0[(t + 1) * NX + k] + (double)w2[(t + 1) * NX + k]);
-      }
-      xz[rho] = acc * iQd[rho];
+      for (int k = 0; k < NX; ++k)
+        acc += ldA<double>(P, a0 + k * NX + i) *
+               ((double)w0[(t + 1) * NX + k] + (double)w2[(t + 1) * NX + k]);
     }
+    xz[rho] = acc * iQd[rho];
   }
   for (int idx = tid; idx < TM; idx += BT) {
     const int t = idx / m, l = idx - t * m;
@@ -1599,24 +1631,20 @@ __device__ __noinline__ ResNorms bwd_residual64(const ProbRec* rec, const float*
   }
   __syncthreads();
   float r2 = 0.f, b2 = 0.f;
+  for (int rho = tid; rho < R; rho += BT) {
+    const int t = rho / NX, i = rho - t * NX;
+    double acc = (double)dll[rho];
+    if (t > 0) {
+      const int tt = t - 1;
 #pragma unroll
-  for (int s = 0; s < SLOTS; ++s) {
-    const int rho = tid + s * BT;
-    if (rho < R) {
-      const int t = rho / NX, i = rho - t * NX;
-      double acc = (double)dll[rho];
-      if (t > 0) {
-        const int tt = t - 1;
-#pragma unroll
-        for (int j = 0; j < NX; ++j)
-          acc += ldA<double>(P, tt * NX * NX + i * NX + j) * xz[tt * NX + j];
-        for (int l = 0; l < m; ++l) acc += ldB<double>(P, tt * NX * m + i * m + l) * uz[tt * m + l];
-      }
-      const double res = xz[rho] - acc;
-      w1[NX + rho] = (float)res;
-      r2 += (float)(res * res);
-      b2 += dlx[rho] * dlx[rho] + dll[rho] * dll[rho];
+      for (int j = 0; j < NX; ++j)
+        acc += ldA<double>(P, tt * NX * NX + i * NX + j) * xz[tt * NX + j];
+      for (int l = 0; l < m; ++l) acc += ldB<double>(P, tt * NX * m + i * m + l) * uz[tt * m + l];
     }
+    const double res = xz[rho] - acc;
+    w1[NX + rho] = (float)res;
+    r2 += (float)(res * res);
+    b2 += dlx[rho] * dlx[rho] + dll[rho] * dll[rho];
   }
   for (int idx = tid; idx < TM; idx += BT) b2 += dlu[idx] * dlu[idx];
   const ResNorms n = block_sum2(r2, b2, smem + C.red, nwv);
@@ -1873,7 +1901,7 @@ __global__ __launch_bounds__(MAXBT) void forward_kernel(KArgs a) {
       pcg_total += qp_solve<NX, SLOTS, REG>(
           P, sh, S, Ph, g, lam, lo, a.refine_steps, maxit, a.pcg_tol, a.pcg_abs_tol, rtol,
           a.kkt_tol, flags, redi, DMPC_PROB_PCG_MAXITER,
-          [&]() { return fwd_residual64<NX, SLOTS>(rec, a.data, a.ws); });
+          [&]() { return fwd_residual64<NX>(rec, a.data, a.ws); });
       publish<SLOTS>(sh.w0, lam, P.R, NX);
       publish<SLOTS>(sh.w2, lo, P.R, NX);
       __syncthreads();
@@ -1928,7 +1956,7 @@ __global__ __launch_bounds__(MAXBT) void backward_kernel(KArgs a) {
     const int its = qp_solve<NX, SLOTS, REG>(
         P, sh, S, Ph, g, lt, lo, a.refine_steps, maxit, a.bwd_tol, 0.f, rtol, a.kkt_tol, flags,
         redi, DMPC_PROB_BWD_PCG_MAXITER,
-        [&]() { return bwd_residual64<NX, SLOTS>(rec, a.data, a.ws, a.dl); });
+        [&]() { return bwd_residual64<NX>(rec, a.data, a.ws, a.dl); });
     publish<SLOTS>(sh.w0, lt, P.R, NX);
     publish<SLOTS>(sh.w2, lo, P.R, NX);
     __syncthreads();

@@ -46,8 +46,7 @@ struct WsLayout {
   int64_t A, B, c;                // linearised dynamics (nonlinear models only)
   int64_t Ad, Bd, cd;             // the same in double (float offsets, 8-byte aligned)
   int64_t Dinv;                   // diagonal Schur blocks inverted [N][nx][nx]
-  int64_t blk;                    // saved rows of S^ and Phi^-1, 6*nx coefficients per row,
-                                  // in tiles of 64 rows (see blk_at in dmpc_device.h)
+  int64_t blk;                    // saved rows of S^ and Phi^-1: [N*nx][6*nx]
   int64_t xp, up, lam;            // last QP solution and multipliers
   int64_t xlin, ulin;             // last linearisation point
   int64_t g;                      // right-hand side of the Schur system [N*nx]
@@ -87,7 +86,7 @@ DMPC_HD inline WsLayout ws_layout(int T, int nx, int nu, int dyn, int flags) {
   o = align_up(o, 4);
   L.Dinv = o; o += N * nx * nx;
   o = align_up(o, 4);
-  L.blk = o; o += align_up(R, 64) * 6 * nx;
+  L.blk = o; o += R * 6 * nx;
   L.xp = o; o += R;
   L.up = o; o += TM;
   L.lam = o; o += R;
