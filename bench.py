@@ -264,6 +264,12 @@ def serve_load(seconds, rate_hz=20000.0, sessions=4096, p_bwd=0.3, p_large=0.05,
         "completed": st["completed"], "rejected": st["rejected"], "failed": st["failed"],
         "throughput_rps": st["throughput"], "p50_latency_ms": 1e3 * st["p50_latency_s"],
         "p99_latency_ms": 1e3 * st["p99_latency_s"], "max_latency_ms": 1e3 * st["max_latency_s"],
+        "light": {"completed": st["completed"] - st["heavy_completed"],
+                  "p50_latency_ms": 1e3 * st["light_p50_latency_s"],
+                  "p99_latency_ms": 1e3 * st["light_p99_latency_s"]},
+        "large": {"completed": st["heavy_completed"],
+                  "p50_latency_ms": 1e3 * st["heavy_p50_latency_s"],
+                  "p99_latency_ms": 1e3 * st["heavy_p99_latency_s"]},
         "mean_group_size": st["mean_group_size"], "max_group_size": st["max_group_size"],
         "max_queue_depth": st["max_pending_seen"], "groups": st["groups"],
         "submit_lag_p99_ms": 1e3 * float(np.quantile(lag, 0.99)) if lag else 0.0,

@@ -229,7 +229,10 @@ dmpc_status dmpc_plan_describe(const dmpc_plan* plan, char* buf, size_t len);
  * on the GPU are taken by the next group as soon as a share frees up, and
  * their kernels overlap on the device.  A session has at most one request in
  * flight; its later requests wait and run in submission order.  A result does
- * not depend on which other requests share its group.
+ * not depend on which other requests share its group.  Sessions too large for
+ * a workgroup's LDS are "heavy": their requests form groups of their own, and
+ * at most max(1, max_inflight / 4) heavy groups run at once, so that they
+ * never hold up the other requests.
  *
  * Device memory is allocated in dmpc_server_create only: per-session stores
  * (max_sessions blocks sized for the largest shape max_T, max_nx, max_nu),
@@ -272,6 +275,9 @@ typedef struct dmpc_server_stats {
   int64_t max_pending_seen; /* deepest admission queue seen */
   double p50_latency_s, p99_latency_s, max_latency_s;  /* submit -> results on the host */
   double throughput;        /* completed / (last completion - first submission), per second */
+  int64_t heavy_completed;  /* of completed: requests of heavy sessions (see below) */
+  double light_p50_latency_s, light_p99_latency_s;   /* the same percentiles per class */
+  double heavy_p50_latency_s, heavy_p99_latency_s;
 } dmpc_server_stats;
 
 /* Request states reported by dmpc_server_wait */

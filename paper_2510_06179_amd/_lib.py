@@ -90,7 +90,9 @@ class ServerStats(ctypes.Structure):
         ("mean_group_size", ctypes.c_double), ("max_group_size", ctypes.c_int64),
         ("max_pending_seen", ctypes.c_int64), ("p50_latency_s", ctypes.c_double),
         ("p99_latency_s", ctypes.c_double), ("max_latency_s", ctypes.c_double),
-        ("throughput", ctypes.c_double),
+        ("throughput", ctypes.c_double), ("heavy_completed", ctypes.c_int64),
+        ("light_p50_latency_s", ctypes.c_double), ("light_p99_latency_s", ctypes.c_double),
+        ("heavy_p50_latency_s", ctypes.c_double), ("heavy_p99_latency_s", ctypes.c_double),
     ]
 
 

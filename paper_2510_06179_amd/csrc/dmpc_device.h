@@ -758,12 +758,21 @@ __device__ __forceinline__ float row_dot_ws(const float* coef, const float* win)
   }
   uint64_t a = (uint64_t)(uintptr_t)coef;
   asm volatile("" : "+v"(a));
-  coef = (const float*)(uintptr_t)a;
+  // rows are 6 NX floats and the workspace is 256-byte aligned: 16-byte loads
+  const float4* c4 = (const float4*)(uintptr_t)a;
+  const float4* w4 = reinterpret_cast<const float4*>(win);
   float acc[3] = {0.f, 0.f, 0.f};
 #pragma unroll
   for (int b = 0; b < 3; ++b) {
 #pragma unroll
-    for (int j = 0; j < NX; ++j) acc[b] = fmaf(coef[b * NX + j], win[b * NX + j], acc[b]);
+    for (int j = 0; j < NX / 4; ++j) {
+      const float4 c = c4[b * (NX / 4) + j];
+      const float4 v = w4[b * (NX / 4) + j];
+      acc[b] = fmaf(c.x, v.x, acc[b]);
+      acc[b] = fmaf(c.y, v.y, acc[b]);
+      acc[b] = fmaf(c.z, v.z, acc[b]);
+      acc[b] = fmaf(c.w, v.w, acc[b]);
+    }
   }
   return (acc[0] + acc[1]) + acc[2];
 }
@@ -1238,7 +1247,7 @@ __device__ __noinline__ void fwd_begin(const ProbRec* rec, const float* data, co
 // (Eq. shurcomplement) and preconditioner rows (Eq. S_Phiinv) into the
 // workspace.  Returns non-zero (in every thread) on a non-positive pivot.
 template <int NX>
-__device__ __noinline__ int fwd_blocks(const ProbRec* rec, const float* data, float* ws) {
+__device__ __forceinline__ int fwd_blocks_body(const ProbRec* rec, const float* data, float* ws) {
   extern __shared__ float smem[];
   const int tid = threadIdx.x, BT = blockDim.x;
   const Prob P = make_prob<NX>(*rec, data, ws);
@@ -1369,8 +1378,8 @@ __device__ __noinline__ ResNorms fwd_residual64(const ProbRec* rec, const float*
 // lambda from the LDS window w0; then the line search (App. A.3, Alg.
 // linesearch) and the SQP update of (x, u).  Returns sel | flags << 8.
 template <int NX>
-__device__ __noinline__ int fwd_recover_ls(const ProbRec* rec, const float* data, float* ws,
-                                           LsParams lp, int last) {
+__device__ __forceinline__ int fwd_recover_ls_body(const ProbRec* rec, const float* data,
+                                                   float* ws, LsParams lp, int last) {
   extern __shared__ float smem[];
   const int tid = threadIdx.x, BT = blockDim.x, nwv = (BT + 63) >> 6;
   const Prob P = make_prob<NX>(*rec, data, ws);
@@ -1866,6 +1875,31 @@ __device__ __forceinline__ int qp_solve(const Prob& P, const Lds& sh, RowRegs<NX
     }
   }
   return its;
+}
+
+// The two per-SQP-iteration phases as calls (their registers are not live
+// across the PCG) or, for the smallest state sizes, inlined: the call frames
+// save and restore some sixty callee-saved registers per call through scratch,
+// and at nx <= 4 the inlined kernel still fits its registers without spills.
+template <int NX>
+__device__ __noinline__ int fwd_blocks_call(const ProbRec* rec, const float* data, float* ws) {
+  return fwd_blocks_body<NX>(rec, data, ws);
+}
+template <int NX>
+__device__ __noinline__ int fwd_recover_ls_call(const ProbRec* rec, const float* data, float* ws,
+                                                LsParams lp, int last) {
+  return fwd_recover_ls_body<NX>(rec, data, ws, lp, last);
+}
+template <int NX>
+__device__ __forceinline__ int fwd_blocks(const ProbRec* rec, const float* data, float* ws) {
+  if constexpr (NX <= 4) return fwd_blocks_body<NX>(rec, data, ws);
+  return fwd_blocks_call<NX>(rec, data, ws);
+}
+template <int NX>
+__device__ __forceinline__ int fwd_recover_ls(const ProbRec* rec, const float* data, float* ws,
+                                              LsParams lp, int last) {
+  if constexpr (NX <= 4) return fwd_recover_ls_body<NX>(rec, data, ws, lp, last);
+  return fwd_recover_ls_call<NX>(rec, data, ws, lp, last);
 }
 
 template <int NX, int SLOTS, int MAXBT, bool REG>

@@ -53,6 +53,7 @@ struct Session {
   dmpc_problem p{};      // offsets rebased into the server stores
   LaunchCfg cfg{};
   int flags = 0;         // ProbRec::flags
+  bool heavy = false;    // too large for LDS: runs in groups of its own (see form_group)
   int64_t data_len = 0, sol_len = 0, ws_floats = 0;
   int queued = 0;        // requests pending or in flight
   bool busy = false;     // a request in flight
@@ -109,6 +110,7 @@ struct Slot {
   int64_t ws_bytes = 0;
   int64_t group_id = -1;
   bool busy = false, launched = false, failed = false;
+  bool heavy = false;   // the group holds heavy requests
   double t_launch = 0;
   std::thread th;
   std::condition_variable cv;
@@ -144,7 +146,9 @@ struct dmpc_server {
   int64_t st_submitted = 0, st_rejected = 0, st_completed = 0, st_bwd = 0, st_failed = 0;
   int64_t st_groups = 0, st_group_reqs = 0, st_max_group = 0, st_max_pending = 0;
   double st_first_submit = -1, st_last_done = 0;
-  std::vector<double> latencies;
+  std::vector<double> latencies, lat_light, lat_heavy;
+  int heavy_inflight = 0;
+  int max_heavy = 1;    // heavy groups in flight at once
   std::deque<GroupTrace> trace;
 
   double now() const {
@@ -193,8 +197,10 @@ dmpc_status check_config(const dmpc_server_config* c) {
 // dispatcher
 // ---------------------------------------------------------------------------
 bool dmpc_server::ready_request() const {
-  for (const Request& r : pending)
-    if (!sessions[r.session].busy) return true;
+  for (const Request& r : pending) {
+    const Session& ss = sessions[r.session];
+    if (!ss.busy && (!ss.heavy || heavy_inflight < max_heavy)) return true;
+  }
   return false;
 }
 
@@ -210,10 +216,23 @@ Slot* dmpc_server::free_slot() {
 // group's workspace share or staging, so a large request is never overtaken.
 void dmpc_server::form_group(Slot* s) {
   s->reqs.clear();
+  // A group holds light or heavy requests, never both, and at most max_heavy
+  // heavy groups run at once: a heavy request (one whose bulk regions live in
+  // the workspace, far slower than the rest) never holds up light ones that
+  // share its group, and light requests always have a share to run in.  The
+  // class is that of the oldest request that can run now.
+  bool heavy = false;
+  for (const Request& r : pending) {
+    const Session& ss = sessions[r.session];
+    if (ss.busy || (ss.heavy && heavy_inflight >= max_heavy)) continue;
+    heavy = ss.heavy;
+    break;
+  }
+  s->heavy = heavy;
   int64_t ws = 0, in = 512, out = 512;
   for (auto it = pending.begin(); it != pending.end() && (int)s->reqs.size() < cfg.max_batch;) {
     Session& ss = sessions[it->session];
-    if (ss.busy) {
+    if (ss.busy || ss.heavy != heavy) {
       ++it;
       continue;
     }
@@ -245,6 +264,7 @@ void dmpc_server::run_dispatcher() {
     if (!s) continue;
     form_group(s);
     if (s->reqs.empty()) continue;
+    if (s->heavy) heavy_inflight += 1;
     s->busy = true;
     s->group_id = next_group++;
     s->t_launch = now();
@@ -476,6 +496,7 @@ void dmpc_server::finish_group(Slot* s) {
       st_completed += 1;
       st_bwd += r.backward ? 1 : 0;
       latencies.push_back(t - r.t_submit);
+      (ss.heavy ? lat_heavy : lat_light).push_back(t - r.t_submit);
       st_last_done = t;
     } else {
       st_failed += 1;
@@ -493,6 +514,8 @@ void dmpc_server::finish_group(Slot* s) {
   if ((int)trace.size() > kTraceKeep) trace.pop_front();
   s->reqs.clear();
   s->launched = false;
+  if (s->heavy) heavy_inflight -= 1;
+  s->heavy = false;
   s->busy = false;
   cv_disp.notify_one();
   cv_res.notify_all();
@@ -544,6 +567,7 @@ dmpc_status dmpc_server_create(const dmpc_server_config* cfg, dmpc_server** out)
     delete sv;
     return DMPC_ERR_NOMEM;
   }
+  sv->max_heavy = std::max(1, cfg->max_inflight / 4);
   sv->sessions.resize(cfg->max_sessions);
   sv->slots.resize(cfg->max_inflight);
   for (int i = 0; i < cfg->max_inflight; ++i) {
@@ -681,6 +705,7 @@ dmpc_status dmpc_server_add_session(dmpc_server* sv, int32_t session, const dmpc
   ss.p.sol_off = sbase;
   ss.cfg = c;
   ss.flags = flags;
+  ss.heavy = (flags & kRecBulkWs) != 0;
   ss.data_len = data_len;
   ss.sol_len = sol_len;
   ss.ws_floats = ws;
@@ -774,7 +799,7 @@ dmpc_status dmpc_server_drain(dmpc_server* sv, double timeout_s) {
 
 dmpc_status dmpc_server_get_stats(dmpc_server* sv, dmpc_server_stats* out) {
   if (!sv || !out) return DMPC_ERR_INVALID_ARG;
-  std::vector<double> lat;
+  std::vector<double> lat, lat_l, lat_h;
   {
     std::lock_guard<std::mutex> lk(sv->mu);
     std::memset(out, 0, sizeof(*out));
@@ -792,17 +817,25 @@ dmpc_status dmpc_server_get_stats(dmpc_server* sv, dmpc_server_stats* out) {
                           ? sv->st_completed / span
                           : 0.0;
     lat = sv->latencies;
+    lat_l = sv->lat_light;
+    lat_h = sv->lat_heavy;
+    out->heavy_completed = (int64_t)lat_h.size();
   }
-  if (!lat.empty()) {
-    std::sort(lat.begin(), lat.end());
-    auto q = [&](double f) {
-      const size_t i = (size_t)std::min<double>(lat.size() - 1, std::ceil(f * lat.size()) - 1);
-      return lat[i];
-    };
-    out->p50_latency_s = q(0.50);
-    out->p99_latency_s = q(0.99);
-    out->max_latency_s = lat.back();
-  }
+  auto q = [](std::vector<double>& v, double f) {
+    if (v.empty()) return 0.0;
+    const size_t i = (size_t)std::min<double>(v.size() - 1, std::ceil(f * v.size()) - 1);
+    return v[i];
+  };
+  std::sort(lat.begin(), lat.end());
+  std::sort(lat_l.begin(), lat_l.end());
+  std::sort(lat_h.begin(), lat_h.end());
+  out->p50_latency_s = q(lat, 0.50);
+  out->p99_latency_s = q(lat, 0.99);
+  out->max_latency_s = lat.empty() ? 0.0 : lat.back();
+  out->light_p50_latency_s = q(lat_l, 0.50);
+  out->light_p99_latency_s = q(lat_l, 0.99);
+  out->heavy_p50_latency_s = q(lat_h, 0.50);
+  out->heavy_p99_latency_s = q(lat_h, 0.99);
   return DMPC_OK;
 }
 
@@ -815,6 +848,8 @@ dmpc_status dmpc_server_reset_stats(dmpc_server* sv) {
   sv->st_first_submit = -1;
   sv->st_last_done = 0;
   sv->latencies.clear();
+  sv->lat_light.clear();
+  sv->lat_heavy.clear();
   sv->trace.clear();
   return DMPC_OK;
 }

@@ -229,3 +229,38 @@ def test_destroy_with_pending_requests():
     t0 = time.perf_counter()
     srv.close()
     assert time.perf_counter() - t0 < 5
+
+
+def test_heavy_sessions_run_in_groups_of_their_own():
+    # nx=32, T=256 problems do not fit a workgroup's LDS: their requests never
+    # share a group with the others, and at most one heavy group (4 shares /
+    # 4) runs at a time
+    rng = np.random.default_rng(9)
+    probs = [W.ltv_problem(rng, 256, 32, 8) if k % 4 == 0 else W.ltv_problem(rng, 32, 4, 2)
+             for k in range(12)]
+    srv = dry(max_sessions=12, max_T=256, max_nx=32, max_nu=8, max_inflight=4, max_batch=8,
+              hbm_budget=1 << 30, dry_run_us=3000)
+    try:
+        for k, p in enumerate(probs):
+            srv.add_session(k, p)
+        seq = [int(s) for s in rng.integers(0, 12, size=120)]
+        tickets = [srv.submit(s) for s in seq]
+        srv.drain(timeout=60)
+        heavy = {t: s % 4 == 0 for t, s in zip(tickets, seq)}
+        trace = srv.trace()
+        hg = []
+        for g in trace:
+            kinds = {heavy[t] for t in g["tickets"]}
+            assert len(kinds) == 1, g
+            if kinds == {True}:
+                hg.append(g)
+        assert hg and len(hg) < len(trace)
+        hg.sort(key=lambda g: g["t_launch"])
+        for a, b in zip(hg, hg[1:]):
+            assert b["t_launch"] >= a["t_done"]
+        st = srv.stats()
+        assert st["heavy_completed"] == sum(heavy.values())
+        assert st["completed"] == len(seq)
+        assert st["heavy_p50_latency_s"] > 0 and st["light_p50_latency_s"] > 0
+    finally:
+        srv.close()
