@@ -1306,7 +1306,8 @@ __device__ __forceinline__ ResNorms block_sum2(float a, float b, float* red, int
 // right-hand side [-b; d] = [-(q, r); (x_s, c)] (Eq. ocp:KKT), identical in
 // every thread.
 template <int NX>
-__device__ __noinline__ ResNorms fwd_residual64(const ProbRec* rec, const float* data, float* ws) {
+__device__ __forceinline__ ResNorms fwd_residual64_body(const ProbRec* rec, const float* data,
+                                                        float* ws) {
   extern __shared__ float smem[];
   const int tid = threadIdx.x, BT = blockDim.x;
   const Prob P = make_prob<NX>(*rec, data, ws);
@@ -1598,8 +1599,8 @@ __device__ __noinline__ void bwd_begin(const ProbRec* rec, const float* data, fl
 //   r_{t+1} = x~_{t+1} - A_t x~_t - B_t u~_t - dl/dlambda_{t+1}.
 // Result to w1; norms of r and of the adjoint right-hand side (dl/dz, dl/dlambda).
 template <int NX>
-__device__ __noinline__ ResNorms bwd_residual64(const ProbRec* rec, const float* data, float* ws,
-                                                const float* dl) {
+__device__ __forceinline__ ResNorms bwd_residual64_body(const ProbRec* rec, const float* data,
+                                                        float* ws, const float* dl) {
   extern __shared__ float smem[];
   const int tid = threadIdx.x, BT = blockDim.x;
   const Prob P = make_prob<NX>(*rec, data, ws);
@@ -1877,10 +1878,11 @@ __device__ __forceinline__ int qp_solve(const Prob& P, const Lds& sh, RowRegs<NX
   return its;
 }
 
-// The two per-SQP-iteration phases as calls (their registers are not live
-// across the PCG) or, for the smallest state sizes, inlined: the call frames
-// save and restore some sixty callee-saved registers per call through scratch,
-// and at nx <= 4 the inlined kernel still fits its registers without spills.
+// The phases that run every SQP iteration (and the refinement residuals) as
+// calls, so that their registers are not live across the PCG, or, for the
+// smallest state sizes, inlined: the call frames save and restore some sixty
+// callee-saved registers per call through scratch, and at nx <= 4 the inlined
+// kernels still fit their registers without spills.
 template <int NX>
 __device__ __noinline__ int fwd_blocks_call(const ProbRec* rec, const float* data, float* ws) {
   return fwd_blocks_body<NX>(rec, data, ws);
@@ -1889,6 +1891,28 @@ template <int NX>
 __device__ __noinline__ int fwd_recover_ls_call(const ProbRec* rec, const float* data, float* ws,
                                                 LsParams lp, int last) {
   return fwd_recover_ls_body<NX>(rec, data, ws, lp, last);
+}
+template <int NX>
+__device__ __noinline__ ResNorms fwd_residual64_call(const ProbRec* rec, const float* data,
+                                                     float* ws) {
+  return fwd_residual64_body<NX>(rec, data, ws);
+}
+template <int NX>
+__device__ __noinline__ ResNorms bwd_residual64_call(const ProbRec* rec, const float* data,
+                                                     float* ws, const float* dl) {
+  return bwd_residual64_body<NX>(rec, data, ws, dl);
+}
+template <int NX>
+__device__ __forceinline__ ResNorms fwd_residual64(const ProbRec* rec, const float* data,
+                                                   float* ws) {
+  if constexpr (NX <= 4) return fwd_residual64_body<NX>(rec, data, ws);
+  return fwd_residual64_call<NX>(rec, data, ws);
+}
+template <int NX>
+__device__ __forceinline__ ResNorms bwd_residual64(const ProbRec* rec, const float* data,
+                                                   float* ws, const float* dl) {
+  if constexpr (NX <= 4) return bwd_residual64_body<NX>(rec, data, ws, dl);
+  return bwd_residual64_call<NX>(rec, data, ws, dl);
 }
 template <int NX>
 __device__ __forceinline__ int fwd_blocks(const ProbRec* rec, const float* data, float* ws) {
