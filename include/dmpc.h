@@ -122,7 +122,8 @@ typedef struct dmpc_opts {
   float refine_tol;         /* relative tolerance of each refinement correction, relative
                                to the residual it corrects (0 = the pass's tol; default 1e-2) */
   float kkt_tol;            /* refinement stops once ||residual||_2 <= kkt_tol * ||KKT
-                               right-hand side||_2 (default 1e-6) */
+                               right-hand side||_2 (default 1e-6); a warm start that
+                               already meets it is kept without a PCG pass */
 } dmpc_opts;
 
 /* Fills *o with the defaults: 1 SQP iteration, PCG tol 1e-6, up to three
@@ -332,7 +333,10 @@ dmpc_status dmpc_server_trace(dmpc_server* srv, char* buf, size_t len);
 /* ------------------------------------------------------------------------ */
 /* A problem's rows (T+1)*nx are spread over the threads of one workgroup,
  * `slots` rows per thread, with the Schur and preconditioner rows held in
- * registers (register_rows = 1) or read from the workspace.  Without a
+ * registers (register_rows = 1) or read from the workspace (0); variants
+ * with register_rows = 2 run one wave per problem with a lane per stage block
+ * (rows (T+1)*nx <= 64 * slots) and exchange neighbouring blocks between lanes
+ * without LDS.  Without a
  * tuning-table entry the library picks the instantiated variant with the
  * lowest modelled cost.
  *
@@ -348,7 +352,8 @@ int32_t dmpc_list_variants(int32_t* out, int32_t max_rows);
  * (T+1)*nx, block_threads a multiple of 64 not above launch_bound); otherwise
  * the cost model decides.  Replaces the previous table; n_rows = 0 clears it.
  * Affects plans and sessions created afterwards.  INVALID_ARG on a malformed
- * row (nothing is installed then).  Host only; thread safe. */
+ * row (nothing is installed then); a row with register_rows = 2 must have
+ * launch_bound 64 and slots a multiple of nx.  Host only; thread safe. */
 dmpc_status dmpc_set_tuning(const int32_t* rows, int32_t n_rows);
 
 /* Copies up to max_rows rows of the installed table into the HOST array rows

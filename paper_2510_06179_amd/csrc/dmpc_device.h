@@ -871,13 +871,22 @@ __device__ __forceinline__ bool row_live(int s, int rho, int R, int BT) {
   return rho < R;
 }
 
-template <int SLOTS, bool FULL = false>
-__device__ __forceinline__ void publish(float* w, const float (&v)[SLOTS], int R, int nx) {
+// Row of the s-th value a thread holds.  Standard layout: rho = tid + s BT.
+// Wave-block layout (one wave per problem, a lane per stage block): value
+// s = b NX + i of lane l is row i of block l + 64 b.
+template <int NX, bool WAVE>
+__device__ __forceinline__ int row_of(int s, int tid, int BT) {
+  if constexpr (WAVE) return (tid + 64 * (s / NX)) * NX + (s % NX);
+  return tid + s * BT;
+}
+
+template <int NX, int SLOTS, bool FULL = false, bool WAVE = false>
+__device__ __forceinline__ void publish(float* w, const float (&v)[SLOTS], int R) {
   const int tid = threadIdx.x, BT = blockDim.x;
 #pragma unroll
   for (int s = 0; s < SLOTS; ++s) {
-    const int rho = tid + s * BT;
-    if (row_live<FULL>(s, rho, R, BT)) w[nx + rho] = v[s];
+    const int rho = row_of<NX, WAVE>(s, tid, BT);
+    if (row_live<FULL>(s, rho, R, BT)) w[NX + rho] = v[s];
   }
 }
 
@@ -1040,11 +1049,7 @@ __device__ __forceinline__ bool precond_rows(const Prob& P, float* piv) {
 }
 
 // ===========================================================================
-// PCG (Alg. pcg) on S^ d = rhs from d = 0, preconditioner Phi^-1; rows live
-// in registers (REG) or in the workspace.  Stops when eta = r'Phi^-1 r <=
-// max(rel_tol^2 * rhs'Phi^-1 rhs, abs_thresh), or at the iteration cap.
-// (The warm start of Alg. pcg enters through rhs = g - S^ lambda, which the
-// caller computes in double.)  Returns the iteration count; ORs status bits.
+// PCG (Alg. pcg) and its row products
 // ===========================================================================
 // Register copy of a thread's Schur / preconditioner rows; a placeholder of
 // one float when the rows are read from the workspace.
@@ -1070,34 +1075,104 @@ __device__ __forceinline__ float rdot(const float* coef, const float* win) {
   return row_dot_ws<NX>(coef, win);
 }
 
+// Wave-block neighbour exchange: for each value s = b NX + j, the value of
+// the previous and of the next stage block (lanes l - 1 and l + 1 through DPP
+// wave shifts; across the 64-block boundary through lane 63 / lane 0).
+// Blocks outside [0, N) read zeros (their entries are zero).
+__device__ __forceinline__ float wave_prev(float x) {   // lane l <- lane l - 1, lane 0 <- 0
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x138, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float wave_next(float x) {   // lane l <- lane l + 1, lane 63 <- 0
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x130, 0xf, 0xf, true));
+}
+template <int NX, int SLOTS>
+__device__ __forceinline__ void wave_neighbours(const float (&v)[SLOTS], float (&pv)[SLOTS],
+                                                float (&nv)[SLOTS]) {
+  constexpr int BPL = SLOTS / NX;
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int b = 0; b < BPL; ++b)
+#pragma unroll
+    for (int j = 0; j < NX; ++j) {
+      float a = wave_prev(v[b * NX + j]);
+      float c = wave_next(v[b * NX + j]);
+      if (b > 0) {
+        const float e = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[(b - 1) * NX + j]), 63));
+        a = lane == 0 ? e : a;
+      }
+      if (b < BPL - 1) {
+        const float e = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[(b + 1) * NX + j]), 0));
+        c = lane == 63 ? e : c;
+      }
+      pv[b * NX + j] = a;
+      nv[b * NX + j] = c;
+    }
+}
+
+// out[s] = (row of value s) . [v_{t-1}; v_t; v_{t+1}] for the coefficient
+// rows of S^ (PH = false) or Phi^-1 (PH = true): through an LDS window
+// (publish, barrier, row products) or, in the wave-block layout, with the
+// neighbour values in registers (same products in the same order).
+template <int NX, int SLOTS, bool REG, bool WAVE, bool PH>
+__device__ __forceinline__ void apply_rows(const Prob& P, float* win, RowRegs<NX, SLOTS, REG>& M,
+                                           const float (&v)[SLOTS], float (&out)[SLOTS]) {
+  const int tid = threadIdx.x, BT = blockDim.x, R = P.R;
+  if constexpr (WAVE) {
+    float pv[SLOTS], nv[SLOTS];
+    wave_neighbours<NX, SLOTS>(v, pv, nv);
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+      const int b = s / NX;
+      float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+#pragma unroll
+      for (int j = 0; j < NX; ++j) {
+        a0 = fmaf(M[s][j], pv[b * NX + j], a0);
+        a1 = fmaf(M[s][NX + j], v[b * NX + j], a1);
+        a2 = fmaf(M[s][2 * NX + j], nv[b * NX + j], a2);
+      }
+      out[s] = (a0 + a1) + a2;
+    }
+  } else {
+    publish<NX, SLOTS, REG>(win, v, R);
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+      const int rho = row_of<NX, false>(s, tid, BT);
+      out[s] = 0.f;
+      if (row_live<REG>(s, rho, R, BT)) {
+        const int t = rho / NX;
+        const float* coef = PH ? coefP<NX, SLOTS, REG>(P, M, s, rho) : coefS<NX, SLOTS, REG>(P, M, s, rho);
+        out[s] = rdot<NX, SLOTS, REG>(coef, win + t * NX);
+      }
+    }
+  }
+}
+
 // v' Phi^-1 v for a vector held in this thread's rows.
-template <int NX, int SLOTS, bool REG>
+template <int NX, int SLOTS, bool REG, bool WAVE>
 __device__ __forceinline__ float precond_norm(const Prob& P, const Lds& sh,
                                               RowRegs<NX, SLOTS, REG>& Ph, const float (&v)[SLOTS],
                                               int& redi) {
-  const int tid = threadIdx.x, BT = blockDim.x, nwv = (BT + 63) >> 6;
-  publish<SLOTS, REG>(sh.w0, v, P.R, NX);
-  __syncthreads();
+  const int nwv = (blockDim.x + 63) >> 6;
+  float z[SLOTS];
+  apply_rows<NX, SLOTS, REG, WAVE, true>(P, sh.w0, Ph, v, z);
   float part = 0.f;
 #pragma unroll
-  for (int s = 0; s < SLOTS; ++s) {
-    const int rho = tid + s * BT;
-    if (row_live<REG>(s, rho, P.R, BT)) {
-      const int t = rho / NX;
-      part = fmaf(v[s], rdot<NX, SLOTS, REG>(coefP<NX, SLOTS, REG>(P, Ph, s, rho), sh.w0 + t * NX),
-                  part);
-    }
-  }
+  for (int s = 0; s < SLOTS; ++s) part = fmaf(v[s], z[s], part);
   return block_sum(part, sh.red + 64 * (redi++ & 1), nwv);
 }
 
-template <int NX, int SLOTS, bool REG>
+// PCG (Alg. pcg) on S^ d = rhs from d = 0, preconditioner Phi^-1; rows live
+// in registers (REG) or in the workspace.  Stops when eta = r'Phi^-1 r <=
+// max(rel_tol^2 * rhs'Phi^-1 rhs, abs_thresh), or at the iteration cap.
+// (The warm start of Alg. pcg enters through rhs = g - S^ lambda, which the
+// caller computes in double.)  Returns the iteration count; ORs status bits.
+template <int NX, int SLOTS, bool REG, bool WAVE>
 __device__ __forceinline__ int pcg(const Prob& P, const Lds& sh, RowRegs<NX, SLOTS, REG>& S,
                                    RowRegs<NX, SLOTS, REG>& Ph, const float (&rhs)[SLOTS],
                                    float (&d)[SLOTS], int maxit, float rel_tol, float abs_thresh,
                                    int& flags, int& redi, int maxit_flag) {
-  const int tid = threadIdx.x, BT = blockDim.x, nwv = (BT + 63) >> 6;
-  const int R = P.R;
+  const int nwv = (blockDim.x + 63) >> 6;
   float r[SLOTS], p[SLOTS], z[SLOTS], y[SLOTS];
   // r = rhs (line 1 with d = 0), r~ = Phi^-1 r (2), p = r~ (3), eta = r'r~ (4)
 #pragma unroll
@@ -1105,17 +1180,10 @@ __device__ __forceinline__ int pcg(const Prob& P, const Lds& sh, RowRegs<NX, SLO
     r[s] = rhs[s];
     d[s] = 0.f;
   }
-  publish<SLOTS, REG>(sh.w1, r, R, NX);
-  __syncthreads();
+  apply_rows<NX, SLOTS, REG, WAVE, true>(P, sh.w1, Ph, r, z);
   float part = 0.f;
 #pragma unroll
   for (int s = 0; s < SLOTS; ++s) {
-    const int rho = tid + s * BT;
-    z[s] = 0.f;
-    if (row_live<REG>(s, rho, R, BT)) {
-      const int t = rho / NX;
-      z[s] = rdot<NX, SLOTS, REG>(coefP<NX, SLOTS, REG>(P, Ph, s, rho), sh.w1 + t * NX);
-    }
     p[s] = z[s];
     part = fmaf(r[s], z[s], part);
   }
@@ -1128,19 +1196,10 @@ __device__ __forceinline__ int pcg(const Prob& P, const Lds& sh, RowRegs<NX, SLO
   }
   while (it < maxit && eta > thresh) {
     // y = S^ p (line 6), v = p'y (7), alpha = eta / v (8)
-    publish<SLOTS, REG>(sh.w0, p, R, NX);
-    __syncthreads();
+    apply_rows<NX, SLOTS, REG, WAVE, false>(P, sh.w0, S, p, y);
     part = 0.f;
 #pragma unroll
-    for (int s = 0; s < SLOTS; ++s) {
-      const int rho = tid + s * BT;
-      y[s] = 0.f;
-      if (row_live<REG>(s, rho, R, BT)) {
-        const int t = rho / NX;
-        y[s] = rdot<NX, SLOTS, REG>(coefS<NX, SLOTS, REG>(P, S, s, rho), sh.w0 + t * NX);
-      }
-      part = fmaf(p[s], y[s], part);
-    }
+    for (int s = 0; s < SLOTS; ++s) part = fmaf(p[s], y[s], part);
     const float v = block_sum(part, sh.red + 64 * (redi++ & 1), nwv);
     if (!(v > 0.f)) {
       flags |= isfinite(v) ? DMPC_PROB_NONPD : DMPC_PROB_NONFINITE;
@@ -1154,19 +1213,10 @@ __device__ __forceinline__ int pcg(const Prob& P, const Lds& sh, RowRegs<NX, SLO
       r[s] = fmaf(-alpha, y[s], r[s]);
     }
     // r~ = Phi^-1 r (11), eta' = r'r~ (12)
-    publish<SLOTS, REG>(sh.w1, r, R, NX);
-    __syncthreads();
+    apply_rows<NX, SLOTS, REG, WAVE, true>(P, sh.w1, Ph, r, z);
     part = 0.f;
 #pragma unroll
-    for (int s = 0; s < SLOTS; ++s) {
-      const int rho = tid + s * BT;
-      z[s] = 0.f;
-      if (row_live<REG>(s, rho, R, BT)) {
-        const int t = rho / NX;
-        z[s] = rdot<NX, SLOTS, REG>(coefP<NX, SLOTS, REG>(P, Ph, s, rho), sh.w1 + t * NX);
-      }
-      part = fmaf(r[s], z[s], part);
-    }
+    for (int s = 0; s < SLOTS; ++s) part = fmaf(r[s], z[s], part);
     const float etan = block_sum(part, sh.red + 64 * (redi++ & 1), nwv);
     ++it;
     if (!isfinite(etan)) {
@@ -1810,7 +1860,7 @@ struct KEntry {
 };
 
 // Loads this thread's rows (Schur, preconditioner, right-hand side).
-template <int NX, int SLOTS, bool REG>
+template <int NX, int SLOTS, bool REG, bool WAVE>
 __device__ __forceinline__ void load_rows(const Prob& P, RowRegs<NX, SLOTS, REG>& S,
                                           RowRegs<NX, SLOTS, REG>& Ph, float (&g)[SLOTS]) {
   const int tid = threadIdx.x, BT = blockDim.x;
@@ -1818,7 +1868,7 @@ __device__ __forceinline__ void load_rows(const Prob& P, RowRegs<NX, SLOTS, REG>
   const float* gv = P.W + P.L.g;
 #pragma unroll
   for (int s = 0; s < SLOTS; ++s) {
-    const int rho = tid + s * BT;
+    const int rho = row_of<NX, WAVE>(s, tid, BT);
     const bool ok = rho < P.R;
     g[s] = ok ? gv[rho] : 0.f;
     if constexpr (REG) {
@@ -1837,9 +1887,10 @@ __device__ __forceinline__ void load_rows(const Prob& P, RowRegs<NX, SLOTS, REG>
 // in double, solves for the correction with the float PCG (Alg. pcg) and adds
 // it to (hi, lo).  Pass 0 stops at ||r||_{Phi^-1} <= tol ||g||_{Phi^-1} (the
 // paper's relative tolerance); then up to `steps` refinement passes, each to
-// relative tolerance ref_tol, stop once the residual meets the KKT target
-// (||r||_2 <= kkt_tol ||rhs||_2).
-template <int NX, int SLOTS, bool REG, typename ResidualFn>
+// relative tolerance ref_tol.  Passes stop once the residual meets the KKT
+// target (||r||_2 <= kkt_tol ||rhs||_2) -- before pass 0 too, when the warm
+// start already meets it (converged SQP iterates).
+template <int NX, int SLOTS, bool REG, bool WAVE, typename ResidualFn>
 __device__ __forceinline__ int qp_solve(const Prob& P, const Lds& sh, RowRegs<NX, SLOTS, REG>& S,
                                         RowRegs<NX, SLOTS, REG>& Ph, const float (&g)[SLOTS],
                                         float (&hi)[SLOTS], float (&lo)[SLOTS], int steps,
@@ -1847,27 +1898,27 @@ __device__ __forceinline__ int qp_solve(const Prob& P, const Lds& sh, RowRegs<NX
                                         float kkt_tol, int& flags, int& redi, int maxit_flag,
                                         ResidualFn residual) {
   const int tid = threadIdx.x, BT = blockDim.x;
-  const float etab = precond_norm<NX, SLOTS, REG>(P, sh, Ph, g, redi);
+  const float etab = precond_norm<NX, SLOTS, REG, WAVE>(P, sh, Ph, g, redi);
   int its = 0;
   for (int k = 0; k <= steps; ++k) {
-    publish<SLOTS>(sh.w0, hi, P.R, NX);
-    publish<SLOTS>(sh.w2, lo, P.R, NX);
+    publish<NX, SLOTS, false, WAVE>(sh.w0, hi, P.R);
+    publish<NX, SLOTS, false, WAVE>(sh.w2, lo, P.R);
     __syncthreads();
     const ResNorms nr = residual();
-    if (k > 0 && nr.r2 <= kkt_tol * kkt_tol * nr.rhs2) break;
+    if (nr.r2 <= kkt_tol * kkt_tol * nr.rhs2) break;   // (k = 0: the warm start already meets it)
     float rr[SLOTS], d[SLOTS];
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
-      const int rho = tid + s * BT;
+      const int rho = row_of<NX, WAVE>(s, tid, BT);
       rr[s] = rho < P.R ? sh.w1[NX + rho] : 0.f;
     }
     __syncthreads();
     if (k == 0)
-      its += pcg<NX, SLOTS, REG>(P, sh, S, Ph, rr, d, maxit, 0.f, fmaxf(tol * tol * etab, abs_tol),
-                                 flags, redi, maxit_flag);
+      its += pcg<NX, SLOTS, REG, WAVE>(P, sh, S, Ph, rr, d, maxit, 0.f,
+                                       fmaxf(tol * tol * etab, abs_tol), flags, redi, maxit_flag);
     else
-      its += pcg<NX, SLOTS, REG>(P, sh, S, Ph, rr, d, maxit, ref_tol, 0.f, flags, redi,
-                                 maxit_flag);
+      its += pcg<NX, SLOTS, REG, WAVE>(P, sh, S, Ph, rr, d, maxit, ref_tol, 0.f, flags, redi,
+                                       maxit_flag);
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
       const double v = ((double)hi[s] + (double)lo[s]) + (double)d[s];
@@ -1926,8 +1977,13 @@ __device__ __forceinline__ int fwd_recover_ls(const ProbRec* rec, const float* d
   return fwd_recover_ls_call<NX>(rec, data, ws, lp, last);
 }
 
-template <int NX, int SLOTS, int MAXBT, bool REG>
+// MODE: 0 = rows of S^ and Phi^-1 read from the workspace, 1 = rows in
+// registers, 2 = rows in registers in the wave-block layout (one wave per
+// problem, a lane per stage block, neighbour values by DPP wave shifts).
+template <int NX, int SLOTS, int MAXBT, int MODE>
 __global__ __launch_bounds__(MAXBT) void forward_kernel(KArgs a) {
+  constexpr bool REG = MODE != 0, WAVE = MODE == 2;
+  static_assert(!WAVE || (MAXBT == 64 && SLOTS % NX == 0), "wave-block kernels are one wave");
   extern __shared__ float smem[];
   const int tid = threadIdx.x, BT = blockDim.x;
   LsParams lp;
@@ -1944,7 +2000,7 @@ __global__ __launch_bounds__(MAXBT) void forward_kernel(KArgs a) {
     float lam[SLOTS], lo[SLOTS];
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
-      const int rho = tid + s * BT;
+      const int rho = row_of<NX, WAVE>(s, tid, BT);
       lam[s] = (rho < P.R && a.init == DMPC_INIT_GIVEN) ? soll[rho] : 0.f;
       lo[s] = 0.f;
     }
@@ -1955,13 +2011,13 @@ __global__ __launch_bounds__(MAXBT) void forward_kernel(KArgs a) {
       if (fwd_blocks<NX>(rec, a.data, a.ws)) flags |= DMPC_PROB_NONPD;
       RowRegs<NX, SLOTS, REG> S, Ph;
       float g[SLOTS];
-      load_rows<NX, SLOTS, REG>(P, S, Ph, g);
-      pcg_total += qp_solve<NX, SLOTS, REG>(
+      load_rows<NX, SLOTS, REG, WAVE>(P, S, Ph, g);
+      pcg_total += qp_solve<NX, SLOTS, REG, WAVE>(
           P, sh, S, Ph, g, lam, lo, a.refine_steps, maxit, a.pcg_tol, a.pcg_abs_tol, rtol,
           a.kkt_tol, flags, redi, DMPC_PROB_PCG_MAXITER,
           [&]() { return fwd_residual64<NX>(rec, a.data, a.ws); });
-      publish<SLOTS>(sh.w0, lam, P.R, NX);
-      publish<SLOTS>(sh.w2, lo, P.R, NX);
+      publish<NX, SLOTS, false, WAVE>(sh.w0, lam, P.R);
+      publish<NX, SLOTS, false, WAVE>(sh.w2, lo, P.R);
       __syncthreads();
       const int r = fwd_recover_ls<NX>(rec, a.data, a.ws, lp, k == a.sqp_iters - 1);
       sel = r & 0xff;
@@ -1970,7 +2026,7 @@ __global__ __launch_bounds__(MAXBT) void forward_kernel(KArgs a) {
     float* wlam = P.W + P.L.lam;
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
-      const int rho = tid + s * BT;
+      const int rho = row_of<NX, WAVE>(s, tid, BT);
       if (rho < P.R) {
         soll[rho] = lam[s];
         wlam[rho] = lam[s];
@@ -1988,8 +2044,10 @@ __global__ __launch_bounds__(MAXBT) void forward_kernel(KArgs a) {
   }
 }
 
-template <int NX, int SLOTS, int MAXBT, bool REG>
+template <int NX, int SLOTS, int MAXBT, int MODE>
 __global__ __launch_bounds__(MAXBT) void backward_kernel(KArgs a) {
+  constexpr bool REG = MODE != 0, WAVE = MODE == 2;
+  static_assert(!WAVE || (MAXBT == 64 && SLOTS % NX == 0), "wave-block kernels are one wave");
   extern __shared__ float smem[];
   const int tid = threadIdx.x, BT = blockDim.x;
   for (int pi = a.first + blockIdx.x; pi < a.first + a.count; pi += gridDim.x) {
@@ -1999,11 +2057,11 @@ __global__ __launch_bounds__(MAXBT) void backward_kernel(KArgs a) {
     bwd_begin<NX>(rec, a.data, a.ws, a.dl);
     RowRegs<NX, SLOTS, REG> S, Ph;
     float g[SLOTS], lt[SLOTS], lo[SLOTS];
-    load_rows<NX, SLOTS, REG>(P, S, Ph, g);
+    load_rows<NX, SLOTS, REG, WAVE>(P, S, Ph, g);
     const float* alv = a.adj + rec->sol_off + P.R + P.TM;
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
-      const int rho = tid + s * BT;
+      const int rho = row_of<NX, WAVE>(s, tid, BT);
       lt[s] = (rho < P.R && a.bwd_warm) ? alv[rho] : 0.f;
       lo[s] = 0.f;
     }
@@ -2011,12 +2069,12 @@ __global__ __launch_bounds__(MAXBT) void backward_kernel(KArgs a) {
     int flags = 0, redi = 0;
     const int maxit = a.bwd_max_iter > 0 ? a.bwd_max_iter : P.R + 10;
     const float rtol = a.refine_tol > 0.f ? a.refine_tol : a.bwd_tol;
-    const int its = qp_solve<NX, SLOTS, REG>(
+    const int its = qp_solve<NX, SLOTS, REG, WAVE>(
         P, sh, S, Ph, g, lt, lo, a.refine_steps, maxit, a.bwd_tol, 0.f, rtol, a.kkt_tol, flags,
         redi, DMPC_PROB_BWD_PCG_MAXITER,
         [&]() { return bwd_residual64<NX>(rec, a.data, a.ws, a.dl); });
-    publish<SLOTS>(sh.w0, lt, P.R, NX);
-    publish<SLOTS>(sh.w2, lo, P.R, NX);
+    publish<NX, SLOTS, false, WAVE>(sh.w0, lt, P.R);
+    publish<NX, SLOTS, false, WAVE>(sh.w2, lo, P.R);
     __syncthreads();
     bwd_finish<NX>(rec, a.data, a.ws, a.dl, a.adj, a.grad);
     if (tid == 0) {

@@ -128,7 +128,8 @@ dmpc_status check_problem(const dmpc_problem& p, int64_t data_len, int64_t sol_l
 }
 
 // Kernel mapping of one problem: its R = (T+1)*nx rows are spread over the
-// threads of a workgroup, `slots` rows per thread.  Among the instantiated
+// threads of a workgroup, `slots` rows per thread (wave-block variants: one
+// wave, `slots` = rows of the stage blocks a lane holds).  Among the instantiated
 // variants that hold the rows, the one with the fewest estimated instructions
 // per PCG iteration is taken: every wave repeats the per-iteration overhead
 // (reductions, divide, barriers), every row costs its two row products;
@@ -140,6 +141,7 @@ const Variant kVariants[] = {
     {1, 64, 1},  {2, 64, 1},  {4, 64, 1},  {8, 64, 1},  {1, 128, 1}, {2, 128, 1}, {4, 128, 1},
     {8, 128, 1}, {1, 256, 1}, {2, 256, 1}, {4, 256, 1}, {1, 512, 1}, {2, 512, 1}, {1, 1024, 1},
     {4, 256, 0}, {8, 256, 0}, {8, 512, 0}, {2, 1024, 0}, {4, 1024, 0}, {8, 1024, 0}, {12, 1024, 0},
+    {2, 64, 2},  {4, 64, 2},  {8, 64, 2},
 };
 
 // Process-wide tuning table (rows of 7 int32, see dmpc_set_tuning).
@@ -177,8 +179,9 @@ bool choose_cfg(const dmpc_problem& p, int force_bt, LaunchCfg* c) {
       if (bt > v.maxbt) continue;
     }
     const int waves = bt / 64;
-    const double cost =
-        waves * (per_wave + v.slots * per_row * (v.reg ? 1.0 : 3.0)) + 1e-3 * v.maxbt;
+    // wave-block variants (reg = 2) need no LDS round trip per row product
+    const double row_w = v.reg == 2 ? 0.7 : (v.reg ? 1.0 : 3.0);
+    const double cost = waves * (per_wave + v.slots * per_row * row_w) + 1e-3 * v.maxbt;
     if (cost < best) {
       best = cost;
       *c = LaunchCfg{p.nx, v.slots, v.maxbt, v.reg, bt, 0, 0};
@@ -293,8 +296,10 @@ dmpc_status dmpc_set_tuning(const int32_t* rows, int32_t n_rows) {
     for (int j = 0; j < 7; ++j) t[i][j] = rows[7 * i + j];
     const auto& r = t[i];
     if (!nx_supported(r[0]) || r[1] < 1 || r[2] < r[1] || r[3] < 1 || r[4] < 64 ||
-        r[4] > 1024 || (r[5] != 0 && r[5] != 1) || r[6] < 64 || r[6] > r[4] || r[6] % 64 != 0)
+        r[4] > 1024 || r[5] < 0 || r[5] > 2 || r[6] < 64 || r[6] > r[4] || r[6] % 64 != 0)
       return DMPC_ERR_INVALID_ARG;
+    // a wave-block row is one wave holding whole stage blocks per lane
+    if (r[5] == 2 && (r[4] != 64 || r[3] % r[0] != 0)) return DMPC_ERR_INVALID_ARG;
   }
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune.swap(t);

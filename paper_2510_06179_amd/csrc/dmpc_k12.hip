@@ -4,9 +4,10 @@
 namespace dmpc {
 
 #define DMPC_K(NX, SL, MB, RG) \
-  {NX, SL, MB, RG, forward_kernel<NX, SL, MB, (RG != 0)>, backward_kernel<NX, SL, MB, (RG != 0)>}
+  {NX, SL, MB, RG, forward_kernel<NX, SL, MB, RG>, backward_kernel<NX, SL, MB, RG>}
 
-// (rows per thread, launch bound, rows of S^ and Phi^-1 held in registers)
+// (values per thread, launch bound, mode: 0 rows read from the workspace,
+// 1 rows in registers, 2 rows in registers in the wave-block layout)
 static const KEntry kEntries[] = {
     DMPC_K(12, 1, 64, 1), DMPC_K(12, 2, 64, 1), DMPC_K(12, 1, 128, 1), DMPC_K(12, 2, 128, 1),
     DMPC_K(12, 1, 256, 1), DMPC_K(12, 2, 256, 1), DMPC_K(12, 1, 512, 1), DMPC_K(12, 2, 512, 1),

@@ -7,9 +7,10 @@
 namespace dmpc {
 
 #define DMPC_K(NX, SL, MB, RG) \
-  {NX, SL, MB, RG, forward_kernel<NX, SL, MB, (RG != 0)>, backward_kernel<NX, SL, MB, (RG != 0)>}
+  {NX, SL, MB, RG, forward_kernel<NX, SL, MB, RG>, backward_kernel<NX, SL, MB, RG>}
 
-// (rows per thread, launch bound, rows of S^ and Phi^-1 held in registers)
+// (values per thread, launch bound, mode: 0 rows read from the workspace,
+// 1 rows in registers, 2 rows in registers in the wave-block layout)
 static const KEntry kEntries[] = {
     DMPC_K(32, 2, 1024, 0), DMPC_K(32, 4, 1024, 0), DMPC_K(32, 8, 1024, 0),
     DMPC_K(32, 12, 1024, 0),

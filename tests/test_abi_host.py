@@ -164,7 +164,8 @@ def test_variants_cover_every_state_size():
     v = _lib.variants()
     assert {r[0] for r in v} == {2, 3, 4, 8, 12, 16, 32}
     for nx, slots, maxbt, reg in v:
-        assert slots >= 1 and maxbt in (64, 128, 256, 512, 1024) and reg in (0, 1)
+        assert slots >= 1 and maxbt in (64, 128, 256, 512, 1024) and reg in (0, 1, 2)
+        assert reg != 2 or (maxbt == 64 and slots % nx == 0)
 
 
 def test_mapping_holds_the_rows_and_respects_forced_threads():
@@ -211,7 +212,7 @@ def test_tuning_table_overrides_the_cost_model():
         _lib.install_tuning([(4, 40, 60, 1, 256, 1, 256)])
         assert _mapping(p, block_threads=64)[1][3] == 64
         # malformed rows are refused and leave the table as it was
-        for bad in [(5, 1, 9, 1, 64, 1, 64), (4, 9, 1, 1, 64, 1, 64), (4, 1, 9, 1, 64, 2, 64),
+        for bad in [(5, 1, 9, 1, 64, 1, 64), (4, 9, 1, 1, 64, 1, 64), (4, 1, 9, 1, 64, 3, 64), (4, 1, 9, 2, 64, 2, 64),
                     (4, 1, 9, 1, 64, 1, 96), (4, 1, 9, 1, 64, 1, 128)]:
             with pytest.raises(_lib.DmpcError):
                 _lib.install_tuning([bad])
