@@ -280,6 +280,38 @@ __device__ __forceinline__ float block_sum(float v, float* red, int nwv) {
 }
 
 // ===========================================================================
+// LDS carve
+// ===========================================================================
+struct Carve {
+  int xbar, ubar, xp, up, lam, w0, w1, w2, piv, red, ls, lin;
+};
+__device__ __forceinline__ int a4(int v) { return (v + 3) & ~3; }
+// Offsets: the bulk regions (iterate, QP solution, multipliers, line-search
+// region) from the bulk base -- the start of LDS, or the workspace's bulk
+// region for problems too large for LDS -- and the windows, pivot rows,
+// reduction slots and the QP-data copy in LDS after them (or from the start
+// of LDS).
+__device__ __forceinline__ Carve carve(int R, int TM, int N, int nx, int bt, int slots,
+                                       int flags) {
+  Carve C;
+  int o = 0;
+  C.xbar = o;  o += a4(R);            // forward: iterate;     backward: x~
+  C.ubar = o;  o += a4(TM);           //                                   u~
+  C.xp = o;    o += a4(R);            // QP solution
+  C.up = o;    o += a4(TM);
+  C.lam = o;   o += a4(R);            // backward: forward multipliers
+  C.ls = o;    o += a4((int)ls_floats(N, R, TM));   // doubles
+  if (flags & kRecBulkWs) o = 0;
+  const int wl = (int)win_floats(R, nx, bt, slots, flags);
+  C.w0 = o;    o += wl;
+  C.w1 = o;    o += wl;
+  C.w2 = o;    o += wl;               // low part of a double-float vector in w0
+  C.piv = o;   o += 4 * bt;
+  C.red = o;   o += 128;
+  C.lin = o;                          // kRecLinLds: the QP-data copy (lin_floats)
+  return C;
+}
+// ===========================================================================
 // Per-problem context
 // ===========================================================================
 struct Prob {
@@ -294,6 +326,7 @@ struct Prob {
   const double* Bd;
   const double* cd;
   float* W;            // problem workspace base
+  float* Wq;           // QP data (Qd .. cd at workspace offsets): W, or its LDS copy
   WsLayout L;
 };
 
@@ -329,7 +362,76 @@ __device__ __forceinline__ Prob make_prob(const ProbRec& pr, const float* data, 
     P.Bd = (const double*)(P.W + P.L.Bd);
     P.cd = (const double*)(P.W + P.L.cd);
   }
+  P.Wq = P.W;
+  if (pr.flags & kRecLinLds) {
+    // QP data, dynamics and costs from the LDS copy (staged by the kernels)
+    extern __shared__ float smem[];
+    const Carve C = carve(P.R, P.TM, P.N, NX, blockDim.x, P.slots, P.flags);
+    float* b = smem + C.lin;
+    P.Wq = b;
+    const int span = (int)a4h(lin_span(P.T, NX, P.m, P.dyn));
+    if (P.dyn == DMPC_DYN_LTV) {
+      P.A = b + span;
+      P.B = P.A + P.T * NX * NX;
+      P.c = P.B + P.T * NX * P.m;
+      P.costp = b + span + (int)a4h(dyn_block_len(P.T, NX, P.m, P.dyn));
+    } else {
+      P.A = b + P.L.A;
+      P.B = b + P.L.B;
+      P.c = b + P.L.c;
+      P.Ad = (const double*)(b + P.L.Ad);
+      P.Bd = (const double*)(b + P.L.Bd);
+      P.cd = (const double*)(b + P.L.cd);
+      P.costp = b + span;
+    }
+  }
   return P;
+}
+
+// Workgroup copy of n floats, four loads in flight per thread before their
+// stores (the copies below are latency bound).  VEC: both ends 16-byte
+// aligned and n a multiple of 4.
+template <bool VEC>
+__device__ __forceinline__ void copy_block(float* dst, const float* src, int n) {
+  const int BT = blockDim.x;
+  int i = threadIdx.x;
+  if constexpr (VEC) {
+    const float4* s4 = reinterpret_cast<const float4*>(src);
+    float4* d4 = reinterpret_cast<float4*>(dst);
+    const int n4 = n >> 2;
+    for (; i + 3 * BT < n4; i += 4 * BT) {
+      const float4 a = s4[i], b = s4[i + BT], c = s4[i + 2 * BT], e = s4[i + 3 * BT];
+      d4[i] = a;
+      d4[i + BT] = b;
+      d4[i + 2 * BT] = c;
+      d4[i + 3 * BT] = e;
+    }
+    for (; i < n4; i += BT) d4[i] = s4[i];
+  } else {
+    for (; i + 3 * BT < n; i += 4 * BT) {
+      const float a = src[i], b = src[i + BT], c = src[i + 2 * BT], e = src[i + 3 * BT];
+      dst[i] = a;
+      dst[i + BT] = b;
+      dst[i + 2 * BT] = c;
+      dst[i + 3 * BT] = e;
+    }
+    for (; i < n; i += BT) dst[i] = src[i];
+  }
+}
+
+// kRecLinLds staging (whole workgroup; the caller synchronises): the cost
+// block and, for LTV problems, the dynamics block from the data arena into
+// the LDS copy; with `qp` also the QP data span from the workspace.
+template <int NX>
+__device__ __forceinline__ void stage_lin(const Prob& P, const ProbRec& pr, const float* data,
+                                          bool qp) {
+  copy_block<false>(const_cast<float*>(P.costp), data + pr.cost_off,
+                    (int)cost_block_len(P.T, NX, P.m, P.cost, P.phases, P.nw));
+  if (P.dyn == DMPC_DYN_LTV)
+    copy_block<false>(const_cast<float*>(P.A), data + pr.dyn_off,
+                      (int)dyn_block_len(P.T, NX, P.m, P.dyn));
+  // (the span rounded up to 4 floats stays inside both regions)
+  if (qp) copy_block<true>(P.Wq, P.W, (int)a4h(lin_span(P.T, NX, P.m, P.dyn)));
 }
 
 // Linearised dynamics entries in precision R: the double copy where one
@@ -481,9 +583,10 @@ __device__ __forceinline__ void dyn_step(const Prob& P, int t, const double* x, 
 }
 
 // Jacobians of a nonlinear model at (xb, ub) by forward-mode duals in double;
-// writes A_t [NX][NX], B_t [NX][MU] rounded to float and the offset
-// c_t = phi(xb, ub) - A xb - B ub with the rounded A, B (so that the affine
-// model passes through phi at the linearisation point), formed in double.
+// writes A_t [NX][NX], B_t [NX][MU] and the offset c_t = phi(xb, ub) - A xb
+// - B ub (so that the affine model passes through phi at the linearisation
+// point), each in double and rounded to float; c_t is formed in double with
+// the double Jacobians.
 template <int NX, int MU, typename F>
 __device__ __forceinline__ void linearize_model(F step, const float* par, const float* xb,
                                                 const float* ub, float* A, float* B, float* c,
@@ -543,7 +646,7 @@ struct BicycleStepF {
 template <int NX>
 __device__ __forceinline__ void form_qp(const Prob& P, const float* xbar, const float* ubar) {
   const int tid = threadIdx.x, BT = blockDim.x;
-  float* W = P.W;
+  float* W = P.Wq;
   float* Qd = W + P.L.Qd;
   float* iQ = W + P.L.iQ;
   float* q = W + P.L.q;
@@ -631,7 +734,7 @@ __device__ __forceinline__ R rinv(const float* ih, const double* ihd, int idx) {
 
 template <int NX, typename R>
 __device__ __forceinline__ void schur_row(const Prob& P, int t, int i, R* S, R& g) {
-  const float* W = P.W;
+  const float* W = P.Wq;
   const float* iQ = W + P.L.iQ;
   const float* q = W + P.L.q;
   const float* iR = W + P.L.iR;
@@ -688,10 +791,10 @@ __device__ __forceinline__ void schur_row(const Prob& P, int t, int i, R* S, R& 
 template <int NX, typename R>
 __device__ __forceinline__ R adjoint_rhs_row(const Prob& P, int t, int i, const float* dlx,
                                              const float* dlu, const float* dll) {
-  const float* iQ = P.W + P.L.iQ;
-  const float* iR = P.W + P.L.iR;
-  const double* iQd = (const double*)(P.W + P.L.iQd);
-  const double* iRd = (const double*)(P.W + P.L.iRd);
+  const float* iQ = P.Wq + P.L.iQ;
+  const float* iR = P.Wq + P.L.iR;
+  const double* iQd = (const double*)(P.Wq + P.L.iQd);
+  const double* iRd = (const double*)(P.Wq + P.L.iRd);
   const int m = P.m;
   const int rho = t * NX + i;
   R v = (R)dlx[rho] * rinv<R>(iQ, iQd, rho) - (R)dll[rho];
@@ -793,33 +896,6 @@ __device__ __forceinline__ double row_dot64(const double* coef, const float* hi,
 // ===========================================================================
 // Shared-memory layout of a workgroup (float offsets)
 // ===========================================================================
-struct Carve {
-  int xbar, ubar, xp, up, lam, w0, w1, w2, piv, red, ls;
-};
-__device__ __forceinline__ int a4(int v) { return (v + 3) & ~3; }
-// Offsets: the bulk regions (iterate, QP solution, multipliers, line-search
-// region) from the bulk base -- the start of LDS, or the workspace's bulk
-// region for problems too large for LDS -- and the windows, pivot rows and
-// reduction slots in LDS after them (or from the start of LDS).
-__device__ __forceinline__ Carve carve(int R, int TM, int N, int nx, int bt, int slots,
-                                       int flags) {
-  Carve C;
-  int o = 0;
-  C.xbar = o;  o += a4(R);            // forward: iterate;     backward: x~
-  C.ubar = o;  o += a4(TM);           //                                   u~
-  C.xp = o;    o += a4(R);            // QP solution
-  C.up = o;    o += a4(TM);
-  C.lam = o;   o += a4(R);            // backward: forward multipliers
-  C.ls = o;    o += a4((int)ls_floats(N, R, TM));   // doubles
-  if (flags & kRecBulkWs) o = 0;
-  const int wl = (int)win_floats(R, nx, bt, slots, flags);
-  C.w0 = o;    o += wl;
-  C.w1 = o;    o += wl;
-  C.w2 = o;    o += wl;               // low part of a double-float vector in w0
-  C.piv = o;   o += 4 * bt;
-  C.red = o;   o += 128;
-  return C;
-}
 template <int NX>
 __device__ __forceinline__ Carve carve_of(const Prob& P) {
   return carve(P.R, P.TM, P.N, NX, blockDim.x, P.slots, P.flags);
@@ -907,7 +983,7 @@ __device__ __forceinline__ bool precond_rows(const Prob& P, float* piv) {
   const int BTb = nb * NX;
   float* blk = P.W + P.L.blk;
   float* Dinv = P.W + P.L.Dinv;
-  const float* iQ = P.W + P.L.iQ;
+  const float* iQ = P.Wq + P.L.iQ;
   bool nonpd = false;
   if constexpr (NX <= 8) {
     // small blocks: one thread inverts a whole D_t in registers (the same
@@ -1258,6 +1334,7 @@ __device__ __noinline__ void fwd_begin(const ProbRec* rec, const float* data, co
   for (int i = tid; i < R; i += BT) xbar[i] = (i < NX) ? P.x0[i] : solx[i];
   for (int i = tid; i < TM; i += BT) ubar[i] = solu[i];
   zero_pads<NX>(smem, C, P);
+  if (P.flags & kRecLinLds) stage_lin<NX>(P, *rec, data, false);
   __syncthreads();
   if (init != DMPC_INIT_ROLLOUT) return;
   if (P.dyn == DMPC_DYN_LTV) {
@@ -1369,10 +1446,10 @@ __device__ __forceinline__ ResNorms fwd_residual64_body(const ProbRec* rec, cons
   double* xz = (double*)(bulk_base(smem, P) + C.ls);  // primal point of lambda: x [R], u [TM]
   double* uz = xz + R;
   const int nwv = (BT + 63) >> 6;
-  const float* q = P.W + P.L.q;
-  const float* rr = P.W + P.L.r;
-  const double* iQd = (const double*)(P.W + P.L.iQd);
-  const double* iRd = (const double*)(P.W + P.L.iRd);
+  const float* q = P.Wq + P.L.q;
+  const float* rr = P.Wq + P.L.r;
+  const double* iQd = (const double*)(P.Wq + P.L.iQd);
+  const double* iRd = (const double*)(P.Wq + P.L.iRd);
   for (int rho = tid; rho < R; rho += BT) {
     const int t = rho / NX, i = rho - t * NX;
     double acc = (double)q[rho] + ((double)w0[rho] + (double)w2[rho]);
@@ -1443,10 +1520,10 @@ __device__ __forceinline__ int fwd_recover_ls_body(const ProbRec* rec, const flo
   const float* w0 = smem + C.w0;   // multipliers, high part
   const float* w2 = smem + C.w2;   // low part
   {
-    const double* iQd = (const double*)(P.W + P.L.iQd);
-    const double* iRd = (const double*)(P.W + P.L.iRd);
-    const float* q = P.W + P.L.q;
-    const float* rr = P.W + P.L.r;
+    const double* iQd = (const double*)(P.Wq + P.L.iQd);
+    const double* iRd = (const double*)(P.Wq + P.L.iRd);
+    const float* q = P.Wq + P.L.q;
+    const float* rr = P.Wq + P.L.r;
     for (int rho = tid; rho < R; rho += BT) {
       const int t = rho / NX, i = rho - t * NX;
       double acc = (double)q[rho] + ((double)w0[NX + rho] + (double)w2[NX + rho]);
@@ -1599,6 +1676,10 @@ __device__ __noinline__ int fwd_finish(const ProbRec* rec, const float* data, fl
   const float* ubar = bulk_base(smem, P) + C.ubar;
   float* solx = sol + rec->sol_off;
   float* solu = solx + P.R;
+  if (P.flags & kRecLinLds) {
+    // the last QP data to the workspace, where the backward pass reads it
+    copy_block<true>(P.W, P.Wq, (int)a4h(lin_span(P.T, NX, P.m, P.dyn)));
+  }
   int bad = 0;
   for (int i = tid; i < P.R; i += BT) {
     solx[i] = xbar[i];
@@ -1630,6 +1711,10 @@ __device__ __noinline__ void bwd_begin(const ProbRec* rec, const float* data, fl
     bulk_base(smem, P)[C.lam + i] = P.W[P.L.lam + i];
   }
   for (int i = tid; i < TM; i += BT) bulk_base(smem, P)[C.up + i] = P.W[P.L.up + i];
+  if (P.flags & kRecLinLds) {
+    stage_lin<NX>(P, *rec, data, true);
+    __syncthreads();
+  }
   const float* dlx = dl + rec->sol_off;
   const float* dlu = dlx + R;
   const float* dll = dlu + TM;
@@ -1664,8 +1749,8 @@ __device__ __forceinline__ ResNorms bwd_residual64_body(const ProbRec* rec, cons
   const float* dlx = dl + rec->sol_off;
   const float* dlu = dlx + R;
   const float* dll = dlu + TM;
-  const double* iQd = (const double*)(P.W + P.L.iQd);
-  const double* iRd = (const double*)(P.W + P.L.iRd);
+  const double* iQd = (const double*)(P.Wq + P.L.iQd);
+  const double* iRd = (const double*)(P.Wq + P.L.iRd);
   const int nwv = (BT + 63) >> 6;
   for (int rho = tid; rho < R; rho += BT) {
     const int t = rho / NX, i = rho - t * NX;
@@ -1731,8 +1816,8 @@ __device__ __noinline__ void bwd_finish(const ProbRec* rec, const float* data, f
   const float* w0 = smem + C.w0;
   const float* lw = w0 + NX;                // lambda~, high part (unpadded view)
   const float* lwl = smem + C.w2 + NX;      // low part
-  const double* iQd = (const double*)(P.W + P.L.iQd);
-  const double* iRd = (const double*)(P.W + P.L.iRd);
+  const double* iQd = (const double*)(P.Wq + P.L.iQd);
+  const double* iRd = (const double*)(P.Wq + P.L.iRd);
   const float* dlx = dl + rec->sol_off;
   const float* dlu = dlx + R;
   float* ax = adj + rec->sol_off;

@@ -194,7 +194,7 @@ bool choose_cfg(const dmpc_problem& p, int force_bt, LaunchCfg* c) {
 int problem_flags(const dmpc_problem& p, int force_bt) {
   LaunchCfg c;
   if (!nx_supported(p.nx) || !choose_cfg(p, force_bt, &c)) return 0;
-  return rec_flags(p.T, p.nx, p.nu, c.bt, c.slots, c.reg);
+  return rec_flags(p.T, p.nx, p.nu, c.bt, c.slots, c.reg, lin_floats_of(p), 0);
 }
 
 }  // namespace dmpc
@@ -452,7 +452,8 @@ dmpc_status dmpc_plan_create(dmpc_handle* h, const dmpc_problem* problems, int32
     r.sol_off = p.sol_off;
     r.ws_off = ws_off;
     r.slots = cfg[i].slots;
-    r.flags = rec_flags(p.T, p.nx, p.nu, cfg[i].bt, cfg[i].slots, cfg[i].reg);
+    r.flags = rec_flags(p.T, p.nx, p.nu, cfg[i].bt, cfg[i].slots, cfg[i].reg, lin_floats_of(p),
+                        lin_budget(count));
     ws_off += ws_layout(p.T, p.nx, p.nu, p.dyn, r.flags).total;
     pl->recs[k] = r;
     pl->pos[i] = k;
@@ -470,7 +471,8 @@ dmpc_status dmpc_plan_create(dmpc_handle* h, const dmpc_problem* problems, int32
     g.count += 1;
     g.cfg.lds_bytes = std::max(
         g.cfg.lds_bytes,
-        (size_t)lds_floats(p.T, p.nx, p.nu, g.cfg.bt, g.cfg.slots, r.flags) * sizeof(float));
+        (size_t)lds_floats(p.T, p.nx, p.nu, g.cfg.bt, g.cfg.slots, r.flags, lin_floats_of(p)) *
+            sizeof(float));
     g.work += (double)(p.T + 1) * p.nx * p.nx;
     pl->grp[k] = (int)pl->groups.size() - 1;
   }

@@ -22,12 +22,16 @@ constexpr int kMaxNx = 32;
 constexpr int kCartpoleParams = 5;
 constexpr int kBicycleParams = 16;
 constexpr int kAlignFloats = 64;  // per-problem workspace alignment (256 B)
-constexpr int kLdsBytes = 160 * 1024;   // LDS of one workgroup on gfx950
+// Dynamic LDS of one workgroup: gfx950's 160 KiB less 1 KiB kept for the
+// kernels' static LDS (up to 256 bytes); a launch over the total fails.
+constexpr int kLdsBytes = 159 * 1024;
 
 // ProbRec::flags
 constexpr int kRecRegRows = 1;   // the kernel keeps the Schur rows in registers
 constexpr int kRecBulkWs = 2;    // iterate, QP solution, multipliers and the line-search
                                  // region live in the workspace (too large for LDS)
+constexpr int kRecLinLds = 4;    // the QP data (see lin_floats) is read from an LDS copy
+constexpr int kComputeUnits = 256;   // CUs of an MI355X
 
 // Device record of one problem (96 bytes).
 struct ProbRec {
@@ -140,18 +144,52 @@ DMPC_HD inline int64_t bulk_floats(int64_t N, int64_t R, int64_t TM) {
 DMPC_HD inline int64_t win_floats(int64_t R, int nx, int bt, int slots, int flags) {
   return a4h(((flags & kRecRegRows) ? (int64_t)slots * bt : R) + 3 * nx);
 }
-DMPC_HD inline int64_t lds_floats(int T, int nx, int nu, int bt, int slots, int flags) {
+// QP data read by every phase of an SQP iteration, copied to LDS under
+// kRecLinLds (one region after the reductions): an image of the workspace
+// span [Qd, lin_span) -- diagonals, inverses (float and double), linear terms
+// and, for nonlinear models, the linearised dynamics in float and double --
+// then, for LTV problems, the dynamics block (A, B, c as in the data arena),
+// then the cost block.  Offsets of the image equal the workspace offsets.
+DMPC_HD inline int64_t lin_span(int T, int nx, int nu, int dyn) {
+  const WsLayout L = ws_layout(T, nx, nu, dyn, 0);
+  return dyn != DMPC_DYN_LTV ? L.cd + 2 * (int64_t)T * nx : L.iRd + 2 * (int64_t)T * nu;
+}
+DMPC_HD inline int64_t lin_floats(int T, int nx, int nu, int dyn, int64_t cost_len) {
+  int64_t n = a4h(lin_span(T, nx, nu, dyn));
+  if (dyn == DMPC_DYN_LTV) n += a4h(dyn_block_len(T, nx, nu, dyn));
+  return n + a4h(cost_len);
+}
+inline int64_t lin_floats_of(const dmpc_problem& p) {
+  return lin_floats(p.T, p.nx, p.nu, p.dyn,
+                    cost_block_len(p.T, p.nx, p.nu, p.cost, p.cost_phases, p.cost_nw));
+}
+DMPC_HD inline int64_t lds_floats(int T, int nx, int nu, int bt, int slots, int flags,
+                                  int64_t lin) {
   const int64_t N = T + 1, R = N * nx, TM = (int64_t)T * nu;
   return ((flags & kRecBulkWs) ? 0 : bulk_floats(N, R, TM))
          + 3 * win_floats(R, nx, bt, slots, flags)   // three padded windows
          + 4 * (int64_t)bt               // Gauss-Jordan pivot rows, double buffered
-         + 128;                          // reductions
+         + 128                           // reductions
+         + ((flags & kRecLinLds) ? lin : 0);
 }
 // Record flags of a problem run by a kernel variant: register rows as the
-// variant has them; the bulk regions go to the workspace when LDS is too small.
-DMPC_HD inline int rec_flags(int T, int nx, int nu, int bt, int slots, int reg) {
+// variant has them; the bulk regions go to the workspace when LDS is too
+// small; the QP data (lin floats) is copied to LDS when the workgroup's LDS
+// stays within lin_budget bytes (0: never).
+DMPC_HD inline int rec_flags(int T, int nx, int nu, int bt, int slots, int reg, int64_t lin,
+                             int64_t lin_budget) {
   const int f = reg ? kRecRegRows : 0;
-  return lds_floats(T, nx, nu, bt, slots, f) * 4 > kLdsBytes ? (f | kRecBulkWs) : f;
+  if (lds_floats(T, nx, nu, bt, slots, f, 0) * 4 > kLdsBytes) return f | kRecBulkWs;
+  if (lds_floats(T, nx, nu, bt, slots, f | kRecLinLds, lin) * 4 <= lin_budget) return f | kRecLinLds;
+  return f;
+}
+// LDS budget for the QP-data copy when `resident` problems share the chip at
+// once: the LDS of a CU divided among the problems each CU then holds (at
+// most four, the one-wave-per-SIMD case of the one-wave kernels).
+DMPC_HD inline int64_t lin_budget(int64_t resident) {
+  int64_t per_cu = (resident + kComputeUnits - 1) / kComputeUnits;
+  per_cu = per_cu < 1 ? 1 : (per_cu > 4 ? 4 : per_cu);
+  return kLdsBytes / per_cu;
 }
 
 // Launch-time arguments of the kernels.

@@ -407,7 +407,7 @@ bool dmpc_server::launch_group(Slot* s) {
     g.nbwd += s->reqs[k].backward ? 1 : 0;
     g.cfg.lds_bytes = std::max(g.cfg.lds_bytes,
                                (size_t)lds_floats(ss.p.T, ss.p.nx, ss.p.nu, g.cfg.bt, g.cfg.slots,
-                                                  ss.flags) *
+                                                  ss.flags, lin_floats_of(ss.p)) *
                                    sizeof(float));
   }
   for (const Range& g : ranges) {
@@ -671,8 +671,11 @@ dmpc_status dmpc_server_add_session(dmpc_server* sv, int32_t session, const dmpc
   if (st != DMPC_OK) return st;
   LaunchCfg c;
   if (!nx_supported(p.nx) || !choose_cfg(p, sv->cfg.opts.block_threads, &c)) return DMPC_ERR_UNSUPPORTED;
-  const int flags = rec_flags(p.T, p.nx, p.nu, c.bt, c.slots, c.reg);
-  if ((size_t)lds_floats(p.T, p.nx, p.nu, c.bt, c.slots, flags) * sizeof(float) > (size_t)kLdsBytes)
+  // batches of sessions fill the chip: the QP-data copy gets a quarter of a CU's LDS
+  const int flags = rec_flags(p.T, p.nx, p.nu, c.bt, c.slots, c.reg, lin_floats_of(p),
+                              lin_budget(4 * kComputeUnits));
+  if ((size_t)lds_floats(p.T, p.nx, p.nu, c.bt, c.slots, flags, lin_floats_of(p)) * sizeof(float) >
+      (size_t)kLdsBytes)
     return DMPC_ERR_UNSUPPORTED;
   const int64_t ws = ws_layout(p.T, p.nx, p.nu, p.dyn, flags).total;
   if (4 * ws > sv->ws_share) return DMPC_ERR_NOMEM;
