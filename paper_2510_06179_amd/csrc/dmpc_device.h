@@ -1797,6 +1797,119 @@ __device__ __forceinline__ ResNorms bwd_residual64_body(const ProbRec* rec, cons
   return n;
 }
 
+// Wave-block refinement residual: the factored residuals above with a lane
+// per stage block (block t = lane + 64 b of value slots b NX .. b NX + NX-1)
+// and everything in registers.  Lane t forms the primal point of stage t from
+// lambda_t and lambda_{t+1} (the next lane's values), then the prediction of
+// stage t+1 -- forward c_t + A_t x_t + B_t u_t, backward dl/dlambda_{t+1} +
+// A_t x~_t + B_t u~_t -- which the next lane subtracts from its own point; the
+// same operations in the same order as the workgroup versions.  rr gets the
+// residual rows; returns the norms as they do.
+__device__ __forceinline__ double wave_prev_d(double x) {   // lane l <- lane l - 1, lane 0 <- 0
+  const long long u = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)u, 0x138, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), 0x138, 0xf, 0xf, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double readlane_d(double x, int l) {
+  const long long u = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)u, l);
+  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int NX, int SLOTS, bool BWD>
+__device__ __forceinline__ ResNorms wave_residual(const Prob& P, const float (&hi)[SLOTS],
+                                                  const float (&lo)[SLOTS], float (&rr)[SLOTS],
+                                                  const float* dlx, const float* dlu,
+                                                  const float* dll) {
+  constexpr int BPL = SLOTS / NX;
+  const int lane = threadIdx.x & 63;
+  const int T = P.T, N = P.N, m = P.m;
+  const float* q = P.Wq + P.L.q;
+  const float* rv = P.Wq + P.L.r;
+  const double* iQd = (const double*)(P.Wq + P.L.iQd);
+  const double* iRd = (const double*)(P.Wq + P.L.iRd);
+  float nh[SLOTS], nl[SLOTS], unused[SLOTS];
+  wave_neighbours<NX, SLOTS>(hi, unused, nh);
+  wave_neighbours<NX, SLOTS>(lo, unused, nl);
+  double x[BPL][NX], v[BPL][NX];
+  float r2 = 0.f, b2 = 0.f;
+#pragma unroll
+  for (int b = 0; b < BPL; ++b) {
+    const int t = lane + 64 * b;
+    const int tc = t < N ? t : N - 1;   // lanes past the horizon load in bounds, count nothing
+    double ln[NX];
+#pragma unroll
+    for (int k = 0; k < NX; ++k) ln[k] = (double)nh[b * NX + k] + (double)nl[b * NX + k];
+    const int a0 = tc * NX * NX;
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+      const int rho = tc * NX + i;
+      const double lt = (double)hi[b * NX + i] + (double)lo[b * NX + i];
+      double acc = BWD ? (double)dlx[rho] - lt : (double)q[rho] + lt;
+      if (tc < T) {
+#pragma unroll
+        for (int k = 0; k < NX; ++k) {
+          if constexpr (BWD) acc += ldA<double>(P, a0 + k * NX + i) * ln[k];
+          else acc -= ldA<double>(P, a0 + k * NX + i) * ln[k];
+        }
+      }
+      x[b][i] = BWD ? acc * iQd[rho] : -acc * iQd[rho];
+    }
+    // prediction of stage t + 1
+    const int tp = tc < T ? tc : T - 1;   // (unused at the last stage)
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+      double acc = BWD ? (double)dll[(tp + 1) * NX + i] : ldc<double>(P, tp * NX + i);
+#pragma unroll
+      for (int j = 0; j < NX; ++j) acc += ldA<double>(P, tp * NX * NX + i * NX + j) * x[b][j];
+      v[b][i] = acc;
+    }
+    for (int l = 0; l < m; ++l) {
+      const int idx = tp * m + l;
+      double acc = BWD ? (double)dlu[idx] : (double)rv[idx];
+#pragma unroll
+      for (int k = 0; k < NX; ++k) {
+        if constexpr (BWD) acc += ldB<double>(P, tp * NX * m + k * m + l) * ln[k];
+        else acc -= ldB<double>(P, tp * NX * m + k * m + l) * ln[k];
+      }
+      const double uz = BWD ? acc * iRd[idx] : -acc * iRd[idx];
+#pragma unroll
+      for (int i = 0; i < NX; ++i) v[b][i] += ldB<double>(P, tp * NX * m + i * m + l) * uz;
+      if (t < T) {
+        const float bu = BWD ? dlu[idx] : rv[idx];
+        b2 += bu * bu;
+      }
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < BPL; ++b) {
+    const int t = lane + 64 * b;
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+      double vp = wave_prev_d(v[b][i]);
+      if (b > 0) vp = lane == 0 ? readlane_d(v[b - 1][i], 63) : vp;
+      float dv = 0.f;
+      if (t == 0) {
+        dv = BWD ? dll[i] : P.x0[i];
+        vp = (double)dv;
+      } else if (t < N && !BWD) {
+        dv = P.c[(t - 1) * NX + i];
+      }
+      const double res = x[b][i] - vp;
+      const bool live = t < N;
+      rr[b * NX + i] = live ? (float)res : 0.f;
+      if (live) {
+        const int rho = t * NX + i;
+        r2 += (float)(res * res);
+        b2 += BWD ? dlx[rho] * dlx[rho] + dll[rho] * dll[rho] : q[rho] * q[rho] + dv * dv;
+      }
+    }
+  }
+  return ResNorms{wave_sum(r2), wave_sum(b2)};
+}
+
 // z~ = G^-1 (dl/dz - H' lambda~) (Alg. backward line 3, in double), then the
 // VJP of Eq. loss_gradient, -dF/dtheta' [z~; lambda~], laid out like the data
 // arena.  lambda~ from the window w0.
@@ -1982,22 +2095,12 @@ __device__ __forceinline__ int qp_solve(const Prob& P, const Lds& sh, RowRegs<NX
                                         int maxit, float tol, float abs_tol, float ref_tol,
                                         float kkt_tol, int& flags, int& redi, int maxit_flag,
                                         ResidualFn residual) {
-  const int tid = threadIdx.x, BT = blockDim.x;
   const float etab = precond_norm<NX, SLOTS, REG, WAVE>(P, sh, Ph, g, redi);
   int its = 0;
   for (int k = 0; k <= steps; ++k) {
-    publish<NX, SLOTS, false, WAVE>(sh.w0, hi, P.R);
-    publish<NX, SLOTS, false, WAVE>(sh.w2, lo, P.R);
-    __syncthreads();
-    const ResNorms nr = residual();
-    if (nr.r2 <= kkt_tol * kkt_tol * nr.rhs2) break;   // (k = 0: the warm start already meets it)
     float rr[SLOTS], d[SLOTS];
-#pragma unroll
-    for (int s = 0; s < SLOTS; ++s) {
-      const int rho = row_of<NX, WAVE>(s, tid, BT);
-      rr[s] = rho < P.R ? sh.w1[NX + rho] : 0.f;
-    }
-    __syncthreads();
+    const ResNorms nr = residual(hi, lo, rr);
+    if (nr.r2 <= kkt_tol * kkt_tol * nr.rhs2) break;   // (k = 0: the warm start already meets it)
     if (k == 0)
       its += pcg<NX, SLOTS, REG, WAVE>(P, sh, S, Ph, rr, d, maxit, 0.f,
                                        fmaxf(tol * tol * etab, abs_tol), flags, redi, maxit_flag);
@@ -2062,6 +2165,36 @@ __device__ __forceinline__ int fwd_recover_ls(const ProbRec* rec, const float* d
   return fwd_recover_ls_call<NX>(rec, data, ws, lp, last);
 }
 
+// Refinement residual of the current multipliers (hi + lo) into rr, in the
+// thread's row layout: the wave-block version in registers, else through the
+// LDS windows and the workgroup residual.
+template <int NX, int SLOTS, bool WAVE, bool BWD>
+__device__ __forceinline__ ResNorms residual_rows(const ProbRec* rec, const KArgs& a,
+                                                  const Prob& P, const Lds& sh,
+                                                  const float (&hi)[SLOTS],
+                                                  const float (&lo)[SLOTS], float (&rr)[SLOTS]) {
+  const float* dlx = BWD ? a.dl + rec->sol_off : nullptr;
+  if constexpr (WAVE) {
+    return wave_residual<NX, SLOTS, BWD>(P, hi, lo, rr, dlx, BWD ? dlx + P.R : nullptr,
+                                         BWD ? dlx + P.R + P.TM : nullptr);
+  } else {
+    const int tid = threadIdx.x, BT = blockDim.x;
+    publish<NX, SLOTS, false, false>(sh.w0, hi, P.R);
+    publish<NX, SLOTS, false, false>(sh.w2, lo, P.R);
+    __syncthreads();
+    ResNorms nr;
+    if constexpr (BWD) nr = bwd_residual64<NX>(rec, a.data, a.ws, a.dl);
+    else nr = fwd_residual64<NX>(rec, a.data, a.ws);
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+      const int rho = row_of<NX, false>(s, tid, BT);
+      rr[s] = rho < P.R ? sh.w1[NX + rho] : 0.f;
+    }
+    __syncthreads();
+    return nr;
+  }
+}
+
 // MODE: 0 = rows of S^ and Phi^-1 read from the workspace, 1 = rows in
 // registers, 2 = rows in registers in the wave-block layout (one wave per
 // problem, a lane per stage block, neighbour values by DPP wave shifts).
@@ -2100,7 +2233,9 @@ __global__ __launch_bounds__(MAXBT) void forward_kernel(KArgs a) {
       pcg_total += qp_solve<NX, SLOTS, REG, WAVE>(
           P, sh, S, Ph, g, lam, lo, a.refine_steps, maxit, a.pcg_tol, a.pcg_abs_tol, rtol,
           a.kkt_tol, flags, redi, DMPC_PROB_PCG_MAXITER,
-          [&]() { return fwd_residual64<NX>(rec, a.data, a.ws); });
+          [&](const float (&h)[SLOTS], const float (&l)[SLOTS], float (&rr)[SLOTS]) {
+            return residual_rows<NX, SLOTS, WAVE, false>(rec, a, P, sh, h, l, rr);
+          });
       publish<NX, SLOTS, false, WAVE>(sh.w0, lam, P.R);
       publish<NX, SLOTS, false, WAVE>(sh.w2, lo, P.R);
       __syncthreads();
@@ -2157,7 +2292,9 @@ __global__ __launch_bounds__(MAXBT) void backward_kernel(KArgs a) {
     const int its = qp_solve<NX, SLOTS, REG, WAVE>(
         P, sh, S, Ph, g, lt, lo, a.refine_steps, maxit, a.bwd_tol, 0.f, rtol, a.kkt_tol, flags,
         redi, DMPC_PROB_BWD_PCG_MAXITER,
-        [&]() { return bwd_residual64<NX>(rec, a.data, a.ws, a.dl); });
+        [&](const float (&h)[SLOTS], const float (&l)[SLOTS], float (&rr)[SLOTS]) {
+          return residual_rows<NX, SLOTS, WAVE, true>(rec, a, P, sh, h, l, rr);
+        });
     publish<NX, SLOTS, false, WAVE>(sh.w0, lt, P.R);
     publish<NX, SLOTS, false, WAVE>(sh.w2, lo, P.R);
     __syncthreads();
