@@ -976,6 +976,42 @@ __device__ __forceinline__ void publish(float* w, const float (&v)[SLOTS], int R
 // thread) on a
 // non-positive pivot.
 // ===========================================================================
+// Gauss-Jordan inversion of one diagonal block in registers: b = a^-1 (a is
+// destroyed).  Returns true on a non-positive pivot (then taken as 1).
+template <int NX>
+__device__ __forceinline__ bool gj_invert(float (&a)[NX][NX], float (&b)[NX][NX]) {
+  bool nonpd = false;
+#pragma unroll
+  for (int i = 0; i < NX; ++i)
+#pragma unroll
+    for (int j = 0; j < NX; ++j) b[i][j] = (i == j) ? 1.f : 0.f;
+#pragma unroll
+  for (int kk = 0; kk < NX; ++kk) {
+    float pv = a[kk][kk];
+    if (!(pv > 0.f)) {
+      nonpd = true;
+      pv = 1.f;
+    }
+    const float inv = 1.f / pv;
+#pragma unroll
+    for (int j = 0; j < NX; ++j) {
+      a[kk][j] *= inv;
+      b[kk][j] *= inv;
+    }
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+      if (i == kk) continue;
+      const float f = a[i][kk];
+#pragma unroll
+      for (int j = 0; j < NX; ++j) {
+        a[i][j] = fmaf(-f, a[kk][j], a[i][j]);
+        b[i][j] = fmaf(-f, b[kk][j], b[i][j]);
+      }
+    }
+  }
+  return nonpd;
+}
+
 template <int NX>
 __device__ __forceinline__ bool precond_rows(const Prob& P, float* piv) {
   const int tid = threadIdx.x, BT = blockDim.x;
@@ -993,34 +1029,8 @@ __device__ __forceinline__ bool precond_rows(const Prob& P, float* piv) {
 #pragma unroll
       for (int i = 0; i < NX; ++i)
 #pragma unroll
-        for (int j = 0; j < NX; ++j) {
-          a[i][j] = blk[blk_at<NX>(t * NX + i, NX + j)];
-          b[i][j] = (i == j) ? 1.f : 0.f;
-        }
-#pragma unroll
-      for (int kk = 0; kk < NX; ++kk) {
-        float pv = a[kk][kk];
-        if (!(pv > 0.f)) {
-          nonpd = true;
-          pv = 1.f;
-        }
-        const float inv = 1.f / pv;
-#pragma unroll
-        for (int j = 0; j < NX; ++j) {
-          a[kk][j] *= inv;
-          b[kk][j] *= inv;
-        }
-#pragma unroll
-        for (int i = 0; i < NX; ++i) {
-          if (i == kk) continue;
-          const float f = a[i][kk];
-#pragma unroll
-          for (int j = 0; j < NX; ++j) {
-            a[i][j] = fmaf(-f, a[kk][j], a[i][j]);
-            b[i][j] = fmaf(-f, b[kk][j], b[i][j]);
-          }
-        }
-      }
+        for (int j = 0; j < NX; ++j) a[i][j] = blk[blk_at<NX>(t * NX + i, NX + j)];
+      if (gj_invert<NX>(a, b)) nonpd = true;
 #pragma unroll
       for (int i = 0; i < NX; ++i)
 #pragma unroll
@@ -1394,6 +1404,17 @@ __device__ __forceinline__ int fwd_blocks_body(const ProbRec* rec, const float* 
   __syncthreads();
   const bool bad = precond_rows<NX>(P, smem + C.piv);
   return __syncthreads_or(bad ? 1 : 0);
+}
+
+// QP data at the iterate (Eq. QPmatrices) only (the wave-block kernels
+// assemble the rows in registers).
+template <int NX>
+__device__ __forceinline__ void fwd_form_body(const ProbRec* rec, const float* data, float* ws) {
+  extern __shared__ float smem[];
+  const Prob P = make_prob<NX>(*rec, data, ws);
+  const Carve C = carve_of<NX>(P);
+  form_qp<NX>(P, bulk_base(smem, P) + C.xbar, bulk_base(smem, P) + C.ubar);
+  __syncthreads();
 }
 
 // Squared norms that steer the refinement: of the residual and of the KKT
@@ -1910,6 +1931,126 @@ __device__ __forceinline__ ResNorms wave_residual(const Prob& P, const float (&h
   return ResNorms{wave_sum(r2), wave_sum(b2)};
 }
 
+// Wave-block assembly (Eq. shurcomplement) and stair preconditioner (Eq.
+// S_Phiinv) in registers, a lane per stage block: the lane's Schur rows and
+// right-hand side from the QP data, D_t^-1 by Gauss-Jordan, and the
+// off-diagonal preconditioner blocks with the neighbouring lanes' inverses
+// (DPP wave shifts) -- the operations of fwd_blocks in the same order.
+// Lanes past the horizon hold zero rows.  With `save` the rows also go to the
+// workspace (the backward pass loads them).  Returns true (in every lane) on
+// a non-positive pivot.
+template <int NX, int SLOTS>
+__device__ __forceinline__ bool wave_blocks(const Prob& P, RowRegs<NX, SLOTS, true>& S,
+                                            RowRegs<NX, SLOTS, true>& Ph, float (&g)[SLOTS],
+                                            bool save) {
+  constexpr int BPL = SLOTS / NX;
+  const int lane = threadIdx.x & 63;
+  const int N = P.N, T = P.T;
+  const float* iQ = P.Wq + P.L.iQ;
+  bool nonpd = false;
+  float Dv[BPL][NX][NX];
+#pragma unroll
+  for (int b = 0; b < BPL; ++b) {
+    const int t = lane + 64 * b;
+    const bool live = t < N;
+    const int tc = live ? t : N - 1;
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+      float gi;
+      schur_row<NX, float>(P, tc, i, S[b * NX + i], gi);
+      g[b * NX + i] = live ? gi : 0.f;
+#pragma unroll
+      for (int j = 0; j < 3 * NX; ++j) S[b * NX + i][j] = live ? S[b * NX + i][j] : 0.f;
+    }
+    float a[NX][NX];
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+#pragma unroll
+      for (int j = 0; j < NX; ++j) a[i][j] = live ? S[b * NX + i][NX + j] : (i == j ? 1.f : 0.f);
+    if (gj_invert<NX>(a, Dv[b])) nonpd = true;
+  }
+#pragma unroll
+  for (int b = 0; b < BPL; ++b) {
+    const int t = lane + 64 * b;
+    const int tc = t < N ? t : N - 1;
+    // rows i of block t: [D_t^-1 E_{t,t-1} D_{t-1}^-1 (negated), D_t^-1, ... E_{t,t+1} D_{t+1}^-1]
+    float lo[NX][NX], up[NX][NX];
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+#pragma unroll
+      for (int j = 0; j < NX; ++j) {
+        lo[i][j] = 0.f;
+        up[i][j] = 0.f;
+      }
+    const float* Ap = P.A + (tc >= 1 ? tc - 1 : 0) * NX * NX;
+    const float* iQp = iQ + (tc >= 1 ? tc - 1 : 0) * NX;
+    const float* At = P.A + (tc < T ? tc : T - 1) * NX * NX;
+    const float* iQt = iQ + tc * NX;
+#pragma unroll
+    for (int k = 0; k < NX; ++k) {
+      // row k of D_{t-1}^-1 and of D_{t+1}^-1 from the neighbouring lanes
+      float dp[NX], dn[NX];
+#pragma unroll
+      for (int j = 0; j < NX; ++j) {
+        float x = wave_prev(Dv[b][k][j]);
+        float y = wave_next(Dv[b][k][j]);
+        if (b > 0) {
+          const float e = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(Dv[b > 0 ? b - 1 : 0][k][j]), 63));
+          x = lane == 0 ? e : x;
+        }
+        if (b < BPL - 1) {
+          const float e = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(Dv[b < BPL - 1 ? b + 1 : 0][k][j]), 0));
+          y = lane == 63 ? e : y;
+        }
+        dp[j] = x;
+        dn[j] = y;
+      }
+#pragma unroll
+      for (int i = 0; i < NX; ++i) {
+        if (tc >= 1) {
+          float w = 0.f;
+#pragma unroll
+          for (int j = 0; j < NX; ++j) w = fmaf(Dv[b][i][j], Ap[j * NX + k], w);
+          w *= iQp[k];
+#pragma unroll
+          for (int j = 0; j < NX; ++j) lo[i][j] = fmaf(w, dp[j], lo[i][j]);
+        }
+        if (tc < T) {
+          float w = 0.f;
+#pragma unroll
+          for (int j = 0; j < NX; ++j) w = fmaf(Dv[b][i][j] * iQt[j], At[k * NX + j], w);
+#pragma unroll
+          for (int j = 0; j < NX; ++j) up[i][j] = fmaf(w, dn[j], up[i][j]);
+        }
+      }
+    }
+    const bool live = t < N;
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+#pragma unroll
+      for (int j = 0; j < NX; ++j) {
+        Ph[b * NX + i][j] = live ? lo[i][j] : 0.f;
+        Ph[b * NX + i][NX + j] = live ? Dv[b][i][j] : 0.f;
+        Ph[b * NX + i][2 * NX + j] = live ? up[i][j] : 0.f;
+      }
+    if (save && live) {
+      float* blk = P.W + P.L.blk;
+      float* gv = P.W + P.L.g;
+#pragma unroll
+      for (int i = 0; i < NX; ++i) {
+        const int rho = t * NX + i;
+#pragma unroll
+        for (int j = 0; j < 3 * NX; ++j) {
+          blk[blk_at<NX>(rho, j)] = S[b * NX + i][j];
+          blk[blk_at<NX>(rho, 3 * NX + j)] = Ph[b * NX + i][j];
+        }
+        gv[rho] = g[b * NX + i];
+      }
+    }
+  }
+  return __ballot(nonpd ? 1 : 0) != 0;
+}
+
 // z~ = G^-1 (dl/dz - H' lambda~) (Alg. backward line 3, in double), then the
 // VJP of Eq. loss_gradient, -dF/dtheta' [z~; lambda~], laid out like the data
 // arena.  lambda~ from the window w0.
@@ -2127,6 +2268,10 @@ __device__ __noinline__ int fwd_blocks_call(const ProbRec* rec, const float* dat
   return fwd_blocks_body<NX>(rec, data, ws);
 }
 template <int NX>
+__device__ __noinline__ void fwd_form_call(const ProbRec* rec, const float* data, float* ws) {
+  fwd_form_body<NX>(rec, data, ws);
+}
+template <int NX>
 __device__ __noinline__ int fwd_recover_ls_call(const ProbRec* rec, const float* data, float* ws,
                                                 LsParams lp, int last) {
   return fwd_recover_ls_body<NX>(rec, data, ws, lp, last);
@@ -2157,6 +2302,11 @@ template <int NX>
 __device__ __forceinline__ int fwd_blocks(const ProbRec* rec, const float* data, float* ws) {
   if constexpr (NX <= 4) return fwd_blocks_body<NX>(rec, data, ws);
   return fwd_blocks_call<NX>(rec, data, ws);
+}
+template <int NX>
+__device__ __forceinline__ void fwd_form(const ProbRec* rec, const float* data, float* ws) {
+  if constexpr (NX <= 4) fwd_form_body<NX>(rec, data, ws);
+  else fwd_form_call<NX>(rec, data, ws);
 }
 template <int NX>
 __device__ __forceinline__ int fwd_recover_ls(const ProbRec* rec, const float* data, float* ws,
@@ -2226,10 +2376,15 @@ __global__ __launch_bounds__(MAXBT) void forward_kernel(KArgs a) {
     const int maxit = a.pcg_max_iter > 0 ? a.pcg_max_iter : P.R + 10;
     const float rtol = a.refine_tol > 0.f ? a.refine_tol : a.pcg_tol;
     for (int k = 0; k < a.sqp_iters; ++k) {
-      if (fwd_blocks<NX>(rec, a.data, a.ws)) flags |= DMPC_PROB_NONPD;
       RowRegs<NX, SLOTS, REG> S, Ph;
       float g[SLOTS];
-      load_rows<NX, SLOTS, REG, WAVE>(P, S, Ph, g);
+      if constexpr (WAVE) {
+        fwd_form<NX>(rec, a.data, a.ws);
+        if (wave_blocks<NX, SLOTS>(P, S, Ph, g, k == a.sqp_iters - 1)) flags |= DMPC_PROB_NONPD;
+      } else {
+        if (fwd_blocks<NX>(rec, a.data, a.ws)) flags |= DMPC_PROB_NONPD;
+        load_rows<NX, SLOTS, REG, WAVE>(P, S, Ph, g);
+      }
       pcg_total += qp_solve<NX, SLOTS, REG, WAVE>(
           P, sh, S, Ph, g, lam, lo, a.refine_steps, maxit, a.pcg_tol, a.pcg_abs_tol, rtol,
           a.kkt_tol, flags, redi, DMPC_PROB_PCG_MAXITER,
