@@ -234,29 +234,47 @@ __device__ __forceinline__ void bicycle_step(const float* p, const S* x, const S
 // ===========================================================================
 // Wave sum with DPP: xor-1 and xor-2 quad permutations, half-row and row
 // mirrors (each lane pairs with a distinct partner, so every lane of a row of
-// 16 holds the same bits), then the four row sums in a fixed order.
-template <int CTRL>
+// 16 holds the same bits), then row broadcasts: each row adds the last lane
+// of the row before it, then rows 2 and 3 add lane 31, so lane 63 holds
+// (r3 + r2) + (r1 + r0) (the other lanes hold partial sums), which is read
+// into a scalar (the same bits in every lane).
+template <int CTRL, int ROWS = 0xF>
 __device__ __forceinline__ float dpp(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, false));
 }
 __device__ __forceinline__ float wave_sum(float v) {
-  v += dpp<0xB1>(v);    // quad_perm [1,0,3,2]
-  v += dpp<0x4E>(v);    // quad_perm [2,3,0,1]
-  v += dpp<0x141>(v);   // row_half_mirror
-  v += dpp<0x140>(v);   // row_mirror
-  const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
-  const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
-  const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
-  const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
-  return (r0 + r1) + (r2 + r3);
+  v += dpp<0xB1>(v);         // quad_perm [1,0,3,2]
+  v += dpp<0x4E>(v);         // quad_perm [2,3,0,1]
+  v += dpp<0x141>(v);        // row_half_mirror
+  v += dpp<0x140>(v);        // row_mirror
+  v += dpp<0x142>(v);        // row_bcast:15
+  v += dpp<0x143>(v);        // row_bcast:31
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
-// Double wave sum (butterfly: partners add the same two values, so every
-// lane gets the same bits).
+__device__ __forceinline__ double readlane_d(double x, int l) {
+  const long long u = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)u, l);
+  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Double wave sum, the same pattern on the two halves of each double.
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)u, CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, ROWS, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 __device__ __forceinline__ double wave_sum_d(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_d<0xB1>(v);
+  v += dpp_d<0x4E>(v);
+  v += dpp_d<0x141>(v);
+  v += dpp_d<0x140>(v);
+  v += dpp_d<0x142>(v);
+  v += dpp_d<0x143>(v);
+  return readlane_d(v, 63);
 }
 __device__ __forceinline__ double block_sum_d(double v, double* red, int nwv) {
   v = wave_sum_d(v);
@@ -1234,6 +1252,13 @@ __device__ __forceinline__ void apply_rows(const Prob& P, float* win, RowRegs<NX
   }
 }
 
+// Workgroup sum of the PCG: one wave needs no LDS exchange.
+template <bool WAVE>
+__device__ __forceinline__ float pcg_sum(float part, const Lds& sh, int& redi, int nwv) {
+  if constexpr (WAVE) return wave_sum(part);
+  return block_sum(part, sh.red + 64 * (redi++ & 1), nwv);
+}
+
 // v' Phi^-1 v for a vector held in this thread's rows.
 template <int NX, int SLOTS, bool REG, bool WAVE>
 __device__ __forceinline__ float precond_norm(const Prob& P, const Lds& sh,
@@ -1245,7 +1270,7 @@ __device__ __forceinline__ float precond_norm(const Prob& P, const Lds& sh,
   float part = 0.f;
 #pragma unroll
   for (int s = 0; s < SLOTS; ++s) part = fmaf(v[s], z[s], part);
-  return block_sum(part, sh.red + 64 * (redi++ & 1), nwv);
+  return pcg_sum<WAVE>(part, sh, redi, nwv);
 }
 
 // PCG (Alg. pcg) on S^ d = rhs from d = 0, preconditioner Phi^-1; rows live
@@ -1273,7 +1298,7 @@ __device__ __forceinline__ int pcg(const Prob& P, const Lds& sh, RowRegs<NX, SLO
     p[s] = z[s];
     part = fmaf(r[s], z[s], part);
   }
-  float eta = block_sum(part, sh.red + 64 * (redi++ & 1), nwv);
+  float eta = pcg_sum<WAVE>(part, sh, redi, nwv);
   const float thresh = fmaxf(rel_tol * rel_tol * eta, abs_thresh);
   int it = 0;
   if (!isfinite(eta)) {
@@ -1286,7 +1311,7 @@ __device__ __forceinline__ int pcg(const Prob& P, const Lds& sh, RowRegs<NX, SLO
     part = 0.f;
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) part = fmaf(p[s], y[s], part);
-    const float v = block_sum(part, sh.red + 64 * (redi++ & 1), nwv);
+    const float v = pcg_sum<WAVE>(part, sh, redi, nwv);
     if (!(v > 0.f)) {
       flags |= isfinite(v) ? DMPC_PROB_NONPD : DMPC_PROB_NONFINITE;
       break;
@@ -1303,16 +1328,17 @@ __device__ __forceinline__ int pcg(const Prob& P, const Lds& sh, RowRegs<NX, SLO
     part = 0.f;
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) part = fmaf(r[s], z[s], part);
-    const float etan = block_sum(part, sh.red + 64 * (redi++ & 1), nwv);
+    const float etan = pcg_sum<WAVE>(part, sh, redi, nwv);
     ++it;
+    // beta (13), p = r~ + beta p (14), eta = eta' (15); (p is not used
+    // after a non-finite eta', so it is updated before that exit)
+    const float beta = etan / eta;
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) p[s] = fmaf(beta, p[s], z[s]);
     if (!isfinite(etan)) {
       flags |= DMPC_PROB_NONFINITE;
       break;
     }
-    // beta (13), p = r~ + beta p (14), eta = eta' (15)
-    const float beta = etan / eta;
-#pragma unroll
-    for (int s = 0; s < SLOTS; ++s) p[s] = fmaf(beta, p[s], z[s]);
     eta = etan;
   }
   if (it >= maxit && eta > thresh) flags |= maxit_flag;
@@ -1830,12 +1856,6 @@ __device__ __forceinline__ double wave_prev_d(double x) {   // lane l <- lane l 
   const long long u = __double_as_longlong(x);
   const int lo = __builtin_amdgcn_update_dpp(0, (int)u, 0x138, 0xf, 0xf, true);
   const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), 0x138, 0xf, 0xf, true);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-__device__ __forceinline__ double readlane_d(double x, int l) {
-  const long long u = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_readlane((int)u, l);
-  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
