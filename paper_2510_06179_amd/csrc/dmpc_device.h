@@ -1883,23 +1883,22 @@ __device__ __forceinline__ ResNorms wave_residual(const Prob& P, const float (&h
     double ln[NX];
 #pragma unroll
     for (int k = 0; k < NX; ++k) ln[k] = (double)nh[b * NX + k] + (double)nl[b * NX + k];
-    const int a0 = tc * NX * NX;
+    // (at the last stage lambda_{t+1} = 0: the clamped A_{T-1} adds exact zeros)
+    const int tp = tc < T ? tc : T - 1;
+    const int a0 = tp * NX * NX;
 #pragma unroll
     for (int i = 0; i < NX; ++i) {
       const int rho = tc * NX + i;
       const double lt = (double)hi[b * NX + i] + (double)lo[b * NX + i];
       double acc = BWD ? (double)dlx[rho] - lt : (double)q[rho] + lt;
-      if (tc < T) {
 #pragma unroll
-        for (int k = 0; k < NX; ++k) {
-          if constexpr (BWD) acc += ldA<double>(P, a0 + k * NX + i) * ln[k];
-          else acc -= ldA<double>(P, a0 + k * NX + i) * ln[k];
-        }
+      for (int k = 0; k < NX; ++k) {
+        if constexpr (BWD) acc += ldA<double>(P, a0 + k * NX + i) * ln[k];
+        else acc -= ldA<double>(P, a0 + k * NX + i) * ln[k];
       }
       x[b][i] = BWD ? acc * iQd[rho] : -acc * iQd[rho];
     }
-    // prediction of stage t + 1
-    const int tp = tc < T ? tc : T - 1;   // (unused at the last stage)
+    // prediction of stage t + 1 (unused at the last stage)
 #pragma unroll
     for (int i = 0; i < NX; ++i) {
       double acc = BWD ? (double)dll[(tp + 1) * NX + i] : ldc<double>(P, tp * NX + i);
@@ -1927,25 +1926,23 @@ __device__ __forceinline__ ResNorms wave_residual(const Prob& P, const float (&h
 #pragma unroll
   for (int b = 0; b < BPL; ++b) {
     const int t = lane + 64 * b;
+    const bool live = t < N;
+    const int tc = live ? t : N - 1;
+    const int tt = tc >= 1 ? tc - 1 : 0;
 #pragma unroll
     for (int i = 0; i < NX; ++i) {
+      const int rho = tc * NX + i;
+      const float d0 = BWD ? dll[i] : P.x0[i];
+      const float dc = BWD ? 0.f : P.c[tt * NX + i];
+      const float nb = BWD ? dlx[rho] * dlx[rho] + dll[rho] * dll[rho] : q[rho] * q[rho];
       double vp = wave_prev_d(v[b][i]);
       if (b > 0) vp = lane == 0 ? readlane_d(v[b - 1][i], 63) : vp;
-      float dv = 0.f;
-      if (t == 0) {
-        dv = BWD ? dll[i] : P.x0[i];
-        vp = (double)dv;
-      } else if (t < N && !BWD) {
-        dv = P.c[(t - 1) * NX + i];
-      }
+      const float dv = t == 0 ? d0 : dc;
+      vp = t == 0 ? (double)d0 : vp;
       const double res = x[b][i] - vp;
-      const bool live = t < N;
       rr[b * NX + i] = live ? (float)res : 0.f;
-      if (live) {
-        const int rho = t * NX + i;
-        r2 += (float)(res * res);
-        b2 += BWD ? dlx[rho] * dlx[rho] + dll[rho] * dll[rho] : q[rho] * q[rho] + dv * dv;
-      }
+      r2 += live ? (float)(res * res) : 0.f;
+      b2 += live ? (BWD ? nb : nb + dv * dv) : 0.f;
     }
   }
   return ResNorms{wave_sum(r2), wave_sum(b2)};
@@ -1955,8 +1952,11 @@ __device__ __forceinline__ ResNorms wave_residual(const Prob& P, const float (&h
 // S_Phiinv) in registers, a lane per stage block: the lane's Schur rows and
 // right-hand side from the QP data, D_t^-1 by Gauss-Jordan, and the
 // off-diagonal preconditioner blocks with the neighbouring lanes' inverses
-// (DPP wave shifts) -- the operations of fwd_blocks in the same order.
-// Lanes past the horizon hold zero rows.  With `save` the rows also go to the
+// (DPP wave shifts) -- the operations of schur_row and precond_rows in the
+// same order.  Branch free: every lane loads the data of stages t-1 and t
+// (indices clamped into the horizon) before any arithmetic, and the first
+// stage, the last stage and lanes past the horizon select their entries
+// (zero rows past the horizon).  With `save` the rows also go to the
 // workspace (the backward pass loads them).  Returns true (in every lane) on
 // a non-positive pivot.
 template <int NX, int SLOTS>
@@ -1965,22 +1965,73 @@ __device__ __forceinline__ bool wave_blocks(const Prob& P, RowRegs<NX, SLOTS, tr
                                             bool save) {
   constexpr int BPL = SLOTS / NX;
   const int lane = threadIdx.x & 63;
-  const int N = P.N, T = P.T;
+  const int N = P.N, T = P.T, m = P.m;
   const float* iQ = P.Wq + P.L.iQ;
+  const float* qv = P.Wq + P.L.q;
+  const float* iR = P.Wq + P.L.iR;
+  const float* rv = P.Wq + P.L.r;
   bool nonpd = false;
   float Dv[BPL][NX][NX];
+  float Ap[BPL][NX][NX], At[BPL][NX][NX], iQp[BPL][NX], iQt[BPL][NX];
 #pragma unroll
   for (int b = 0; b < BPL; ++b) {
     const int t = lane + 64 * b;
     const bool live = t < N;
     const int tc = live ? t : N - 1;
+    const int tt = tc >= 1 ? tc - 1 : 0;     // stage t - 1 (clamped)
+    const int tn = tc < T ? tc : T - 1;      // stage t as a dynamics stage (clamped)
+    float qp[NX], qt[NX], ct[NX], x0[NX];
 #pragma unroll
     for (int i = 0; i < NX; ++i) {
-      float gi;
-      schur_row<NX, float>(P, tc, i, S[b * NX + i], gi);
-      g[b * NX + i] = live ? gi : 0.f;
 #pragma unroll
-      for (int j = 0; j < 3 * NX; ++j) S[b * NX + i][j] = live ? S[b * NX + i][j] : 0.f;
+      for (int j = 0; j < NX; ++j) {
+        Ap[b][i][j] = ldA<float>(P, tt * NX * NX + i * NX + j);
+        At[b][i][j] = ldA<float>(P, tn * NX * NX + i * NX + j);
+      }
+      iQp[b][i] = iQ[tt * NX + i];
+      iQt[b][i] = iQ[tc * NX + i];
+      qp[i] = qv[tt * NX + i];
+      qt[i] = qv[tc * NX + i];
+      ct[i] = ldc<float>(P, tt * NX + i);
+      x0[i] = P.x0[i];
+    }
+    // rows of block t (schur_row): general stage, first stage, E_{t,t+1}
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+      float* Si = S[b * NX + i];
+      float ai[NX], gs = 0.f;
+#pragma unroll
+      for (int j = 0; j < NX; ++j) {
+        ai[j] = Ap[b][i][j] * iQp[b][j];
+        gs += ai[j] * qp[j];
+      }
+      float Dr[NX];
+#pragma unroll
+      for (int k = 0; k < NX; ++k) {
+        float acc = 0.f;
+#pragma unroll
+        for (int j = 0; j < NX; ++j) acc += ai[j] * Ap[b][k][j];
+        Dr[k] = acc;
+      }
+      for (int l = 0; l < m; ++l) {
+        const float bi = ldB<float>(P, tt * NX * m + i * m + l) * iR[tt * m + l];
+        gs += bi * rv[tt * m + l];
+#pragma unroll
+        for (int k = 0; k < NX; ++k) Dr[k] += bi * ldB<float>(P, tt * NX * m + k * m + l);
+      }
+      const float dq = iQt[b][i];
+#pragma unroll
+      for (int k = 0; k < NX; ++k) Dr[k] += (k == i) ? dq : 0.f;
+      const float gg = -(ct[i] - gs + qt[i] * dq);
+      const float g0 = -(x0[i] + qt[i] * dq);
+      const bool first = tc == 0;
+#pragma unroll
+      for (int j = 0; j < NX; ++j) {
+        Si[j] = (live && !first) ? -ai[j] : 0.f;
+        Si[NX + j] = live ? (first ? ((j == i) ? dq : 0.f) : Dr[j]) : 0.f;
+        Si[2 * NX + j] = (live && tc < T) ? -At[b][j][i] * dq : 0.f;
+      }
+      g[b * NX + i] = live ? (first ? g0 : gg) : 0.f;
     }
     float a[NX][NX];
 #pragma unroll
@@ -1992,34 +2043,35 @@ __device__ __forceinline__ bool wave_blocks(const Prob& P, RowRegs<NX, SLOTS, tr
 #pragma unroll
   for (int b = 0; b < BPL; ++b) {
     const int t = lane + 64 * b;
-    const int tc = t < N ? t : N - 1;
-    // rows i of block t: [D_t^-1 E_{t,t-1} D_{t-1}^-1 (negated), D_t^-1, ... E_{t,t+1} D_{t+1}^-1]
-    float lo[NX][NX], up[NX][NX];
+    const bool live = t < N;
+    const int tc = live ? t : N - 1;
+    // preconditioner rows of block t (precond_rows): lo = D_t^-1 E_{t,t-1}
+    // D_{t-1}^-1, up = D_t^-1 E_{t,t+1} D_{t+1}^-1 (both negated), from row k
+    // of the neighbouring inverses
+    float lo[NX][NX], up[NX][NX], bq[NX][NX];
 #pragma unroll
     for (int i = 0; i < NX; ++i)
 #pragma unroll
       for (int j = 0; j < NX; ++j) {
         lo[i][j] = 0.f;
         up[i][j] = 0.f;
+        bq[i][j] = Dv[b][i][j] * iQt[b][j];
       }
-    const float* Ap = P.A + (tc >= 1 ? tc - 1 : 0) * NX * NX;
-    const float* iQp = iQ + (tc >= 1 ? tc - 1 : 0) * NX;
-    const float* At = P.A + (tc < T ? tc : T - 1) * NX * NX;
-    const float* iQt = iQ + tc * NX;
 #pragma unroll
     for (int k = 0; k < NX; ++k) {
-      // row k of D_{t-1}^-1 and of D_{t+1}^-1 from the neighbouring lanes
       float dp[NX], dn[NX];
 #pragma unroll
       for (int j = 0; j < NX; ++j) {
         float x = wave_prev(Dv[b][k][j]);
         float y = wave_next(Dv[b][k][j]);
         if (b > 0) {
-          const float e = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(Dv[b > 0 ? b - 1 : 0][k][j]), 63));
+          const float e = __int_as_float(
+              __builtin_amdgcn_readlane(__float_as_int(Dv[b > 0 ? b - 1 : 0][k][j]), 63));
           x = lane == 0 ? e : x;
         }
         if (b < BPL - 1) {
-          const float e = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(Dv[b < BPL - 1 ? b + 1 : 0][k][j]), 0));
+          const float e = __int_as_float(
+              __builtin_amdgcn_readlane(__float_as_int(Dv[b < BPL - 1 ? b + 1 : 0][k][j]), 0));
           y = lane == 63 ? e : y;
         }
         dp[j] = x;
@@ -2027,31 +2079,27 @@ __device__ __forceinline__ bool wave_blocks(const Prob& P, RowRegs<NX, SLOTS, tr
       }
 #pragma unroll
       for (int i = 0; i < NX; ++i) {
-        if (tc >= 1) {
-          float w = 0.f;
+        float w = 0.f;
 #pragma unroll
-          for (int j = 0; j < NX; ++j) w = fmaf(Dv[b][i][j], Ap[j * NX + k], w);
-          w *= iQp[k];
+        for (int j = 0; j < NX; ++j) w = fmaf(Dv[b][i][j], Ap[b][j][k], w);
+        w *= iQp[b][k];
+        float v = 0.f;
 #pragma unroll
-          for (int j = 0; j < NX; ++j) lo[i][j] = fmaf(w, dp[j], lo[i][j]);
-        }
-        if (tc < T) {
-          float w = 0.f;
+        for (int j = 0; j < NX; ++j) v = fmaf(bq[i][j], At[b][k][j], v);
 #pragma unroll
-          for (int j = 0; j < NX; ++j) w = fmaf(Dv[b][i][j] * iQt[j], At[k * NX + j], w);
-#pragma unroll
-          for (int j = 0; j < NX; ++j) up[i][j] = fmaf(w, dn[j], up[i][j]);
+        for (int j = 0; j < NX; ++j) {
+          lo[i][j] = fmaf(w, dp[j], lo[i][j]);
+          up[i][j] = fmaf(v, dn[j], up[i][j]);
         }
       }
     }
-    const bool live = t < N;
 #pragma unroll
     for (int i = 0; i < NX; ++i)
 #pragma unroll
       for (int j = 0; j < NX; ++j) {
-        Ph[b * NX + i][j] = live ? lo[i][j] : 0.f;
+        Ph[b * NX + i][j] = (live && tc >= 1) ? lo[i][j] : 0.f;
         Ph[b * NX + i][NX + j] = live ? Dv[b][i][j] : 0.f;
-        Ph[b * NX + i][2 * NX + j] = live ? up[i][j] : 0.f;
+        Ph[b * NX + i][2 * NX + j] = (live && tc < T) ? up[i][j] : 0.f;
       }
     if (save && live) {
       float* blk = P.W + P.L.blk;
