@@ -1226,15 +1226,16 @@ __device__ __forceinline__ void apply_rows(const Prob& P, float* win, RowRegs<NX
     wave_neighbours<NX, SLOTS>(v, pv, nv);
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
+      // one fused chain per row (the rows of a lane give independent chains)
       const int b = s / NX;
-      float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+      float acc = M[s][0] * pv[b * NX];
 #pragma unroll
-      for (int j = 0; j < NX; ++j) {
-        a0 = fmaf(M[s][j], pv[b * NX + j], a0);
-        a1 = fmaf(M[s][NX + j], v[b * NX + j], a1);
-        a2 = fmaf(M[s][2 * NX + j], nv[b * NX + j], a2);
-      }
-      out[s] = (a0 + a1) + a2;
+      for (int j = 1; j < NX; ++j) acc = fmaf(M[s][j], pv[b * NX + j], acc);
+#pragma unroll
+      for (int j = 0; j < NX; ++j) acc = fmaf(M[s][NX + j], v[b * NX + j], acc);
+#pragma unroll
+      for (int j = 0; j < NX; ++j) acc = fmaf(M[s][2 * NX + j], nv[b * NX + j], acc);
+      out[s] = acc;
     }
   } else {
     publish<NX, SLOTS, REG>(win, v, R);
@@ -1316,7 +1317,9 @@ __device__ __forceinline__ int pcg(const Prob& P, const Lds& sh, RowRegs<NX, SLO
       flags |= isfinite(v) ? DMPC_PROB_NONPD : DMPC_PROB_NONFINITE;
       break;
     }
-    const float alpha = eta / v;
+    // (alpha and beta with the hardware reciprocal: within about one ulp of
+    // the quotient, and off the latency-bound critical path of a division)
+    const float alpha = eta * __builtin_amdgcn_rcpf(v);
     // d += alpha p (9), r -= alpha y (10)
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
@@ -1332,7 +1335,7 @@ __device__ __forceinline__ int pcg(const Prob& P, const Lds& sh, RowRegs<NX, SLO
     ++it;
     // beta (13), p = r~ + beta p (14), eta = eta' (15); (p is not used
     // after a non-finite eta', so it is updated before that exit)
-    const float beta = etan / eta;
+    const float beta = etan * __builtin_amdgcn_rcpf(eta);
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) p[s] = fmaf(beta, p[s], z[s]);
     if (!isfinite(etan)) {
