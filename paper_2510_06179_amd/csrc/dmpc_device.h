@@ -140,8 +140,57 @@ __device__ __forceinline__ Dual<K, R> chain(const Dual<K, R>& a, R fv, R dfv) {
   for (int k = 0; k < K; ++k) r.d[k] = dfv * a.d[k];
   return r;
 }
-__device__ __forceinline__ double sin_(double a) { return sin(a); }
-__device__ __forceinline__ double cos_(double a) { return cos(a); }
+// Sine and cosine in double, branch free, from one argument reduction
+// (Cody and Waite): x = k pi/2 + r with k = rint(2x/pi) and pi/2 split into
+// its leading 33 bits, the next 33 bits and the rounded remainder (so k P1
+// and k P2 are exact for |k| < 2^20), |r| <= pi/4; then the Taylor series of
+// sin r to r^19 and cos r to r^18 (truncation below 2^-70 relative), and the
+// quadrant k mod 4 selects and negates.  Within a few ulp of the exact values
+// for |x| < 2^20 pi/2 (the models' angles are far smaller); NaN for a
+// non-finite x.  Coefficients (-1)^k/(2k+1)! and (-1)^k/(2k)!, rounded.
+__device__ __forceinline__ void sincos_cw(double x, double& sn, double& cs) {
+  constexpr double kInvPio2 = 0x1.45f306dc9c883p-1;
+  constexpr double kP1 = 0x1.921fb54400000p+0, kP2 = 0x1.0b4611a600000p-34,
+                   kP3 = 0x1.3198a2e037073p-69;
+  const double k = rint(x * kInvPio2);
+  const double r = ((x - k * kP1) - k * kP2) - k * kP3;
+  const double z = r * r;
+  double ps = -0x1.2f49b46814157p-57;   // 1/19!
+  ps = fma(ps, z, 0x1.952c77030ad4ap-49);
+  ps = fma(ps, z, -0x1.ae7f3e733b81fp-41);
+  ps = fma(ps, z, 0x1.6124613a86d09p-33);
+  ps = fma(ps, z, -0x1.ae64567f544e4p-26);
+  ps = fma(ps, z, 0x1.71de3a556c734p-19);
+  ps = fma(ps, z, -0x1.a01a01a01a01ap-13);
+  ps = fma(ps, z, 0x1.1111111111111p-7);
+  ps = fma(ps, z, -0x1.5555555555555p-3);   // -1/3!
+  const double sr = fma(ps * z, r, r);
+  double pc = -0x1.6827863b97d97p-53;   // -1/18!
+  pc = fma(pc, z, 0x1.ae7f3e733b81fp-45);
+  pc = fma(pc, z, -0x1.93974a8c07c9dp-37);
+  pc = fma(pc, z, 0x1.1eed8eff8d898p-29);
+  pc = fma(pc, z, -0x1.27e4fb7789f5cp-22);
+  pc = fma(pc, z, 0x1.a01a01a01a01ap-16);
+  pc = fma(pc, z, -0x1.6c16c16c16c17p-10);
+  pc = fma(pc, z, 0x1.5555555555555p-5);
+  pc = fma(pc, z, -0.5);
+  const double cr = fma(pc, z, 1.0);
+  const int q = (int)(k - 4.0 * floor(k * 0.25));   // k mod 4 in 0..3
+  const double s0 = (q & 1) ? cr : sr;
+  const double c0 = (q & 1) ? sr : cr;
+  sn = (q & 2) ? -s0 : s0;
+  cs = ((q + 1) & 2) ? -c0 : c0;
+}
+__device__ __forceinline__ double sin_(double a) {
+  double s, c;
+  sincos_cw(a, s, c);
+  return s;
+}
+__device__ __forceinline__ double cos_(double a) {
+  double s, c;
+  sincos_cw(a, s, c);
+  return c;
+}
 __device__ __forceinline__ double atan_(double a) { return atan(a); }
 __device__ __forceinline__ double tanh_(double a) { return tanh(a); }
 __device__ __forceinline__ double sqrt_(double a) { return sqrt(a); }
@@ -566,10 +615,27 @@ __device__ __forceinline__ double dcost_u1(const Prob& P, int t, int l, float ub
   return (double)sp_weight(P, t, P.nw + l) * ub * ((double)uq - (double)ub);
 }
 
+// Parameters of a nonlinear model, loaded once per phase into registers
+// (through the scalar unit: the block is the same for the whole workgroup).
+struct ModelPar {
+  float v[kBicycleParams];
+};
+__device__ __forceinline__ ModelPar load_par(const Prob& P) {
+  ModelPar mp;
+  const uint64_t a = (uint64_t)P.dynp;
+  const float* dp = (const float*)(((uint64_t)__builtin_amdgcn_readfirstlane((int)(a >> 32)) << 32) |
+                                   (uint32_t)__builtin_amdgcn_readfirstlane((int)a));
+  const int np = P.dyn == DMPC_DYN_CARTPOLE ? kCartpoleParams
+                 : P.dyn == DMPC_DYN_BICYCLE ? kBicycleParams : 0;
+#pragma unroll
+  for (int i = 0; i < kBicycleParams; ++i) mp.v[i] = i < np ? dp[i] : 0.f;
+  return mp;
+}
+
 // Next state of the true dynamics, in double (rollout and merit function).
 template <int NX>
-__device__ __forceinline__ void dyn_step(const Prob& P, int t, const double* x, const double* u,
-                                         double* xn) {
+__device__ __forceinline__ void dyn_step(const Prob& P, const ModelPar& mp, int t,
+                                         const double* x, const double* u, double* xn) {
   if (P.dyn == DMPC_DYN_LTV) {
     const float* At = P.A + t * NX * NX;
     const float* Bt = P.B + t * NX * P.m;
@@ -586,13 +652,13 @@ __device__ __forceinline__ void dyn_step(const Prob& P, int t, const double* x, 
   }
   if constexpr (NX == 4) {
     if (P.dyn == DMPC_DYN_CARTPOLE) {
-      cartpole_step<double>(P.dynp, x, u, xn);
+      cartpole_step<double>(mp.v, x, u, xn);
       return;
     }
   }
   if constexpr (NX == 8) {
     if (P.dyn == DMPC_DYN_BICYCLE) {
-      bicycle_step<double>(P.dynp, x, u, xn);
+      bicycle_step<double>(mp.v, x, u, xn);
       return;
     }
   }
@@ -715,15 +781,16 @@ __device__ __forceinline__ void form_qp(const Prob& P, const float* xbar, const 
     double* Ad = (double*)(W + P.L.Ad);
     double* Bd = (double*)(W + P.L.Bd);
     double* cd = (double*)(W + P.L.cd);
+    const ModelPar mp = load_par(P);
     for (int t = tid; t < P.T; t += BT) {
       if constexpr (NX == 4) {
         if (P.dyn == DMPC_DYN_CARTPOLE)
-          linearize_model<4, 1>(CartpoleStepF<4>(), P.dynp, xbar + t * 4, ubar + t, A + t * 16,
+          linearize_model<4, 1>(CartpoleStepF<4>(), mp.v, xbar + t * 4, ubar + t, A + t * 16,
                                 B + t * 4, c + t * 4, Ad + t * 16, Bd + t * 4, cd + t * 4);
       }
       if constexpr (NX == 8) {
         if (P.dyn == DMPC_DYN_BICYCLE)
-          linearize_model<8, 2>(BicycleStepF<8>(), P.dynp, xbar + t * 8, ubar + t * 2,
+          linearize_model<8, 2>(BicycleStepF<8>(), mp.v, xbar + t * 8, ubar + t * 2,
                                 A + t * 64, B + t * 16, c + t * 8, Ad + t * 64, Bd + t * 16,
                                 cd + t * 8);
       }
@@ -1356,6 +1423,20 @@ struct LsParams {
   int n;
   float eta;
 };
+// alphas[a - 1] for a in 1..kMaxAlphas, 0 for a = 0: a select chain over
+// the (uniform) parameters, so that a per-lane index does not put the array
+// in scratch memory.
+__device__ __forceinline__ float pick_alpha(const LsParams& lp, int a) {
+  float v = 0.f;
+#pragma unroll
+  for (int i = 0; i < kMaxAlphas; ++i) v = (a == i + 1) ? lp.alphas[i] : v;
+  return v;
+}
+
+// Line-search outcome: selected step and flag bits.
+struct LsResult {
+  int sel, flags;
+};
 
 // Initial guess (Alg. sqp inputs) into LDS; x_0 = x_s; rollout if asked.
 template <int NX>
@@ -1390,6 +1471,7 @@ __device__ __noinline__ void fwd_begin(const ProbRec* rec, const float* data, co
       __syncthreads();
     }
   } else {
+    const ModelPar mp = load_par(P);
     if (tid == 0) {
       double xc[NX], xn[NX], uc[2];
 #pragma unroll
@@ -1397,7 +1479,7 @@ __device__ __noinline__ void fwd_begin(const ProbRec* rec, const float* data, co
       for (int t = 0; t < T; ++t) {
         uc[0] = ubar[t * m];
         uc[1] = (m > 1) ? ubar[t * m + 1] : 0.f;
-        dyn_step<NX>(P, t, xc, uc, xn);
+        dyn_step<NX>(P, mp, t, xc, uc, xn);
 #pragma unroll
         for (int i = 0; i < NX; ++i) {
           xbar[(t + 1) * NX + i] = (float)xn[i];
@@ -1556,8 +1638,8 @@ __device__ __forceinline__ ResNorms fwd_residual64_body(const ProbRec* rec, cons
 // lambda from the LDS window w0; then the line search (App. A.3, Alg.
 // linesearch) and the SQP update of (x, u).  Returns sel | flags << 8.
 template <int NX>
-__device__ __forceinline__ int fwd_recover_ls_body(const ProbRec* rec, const float* data,
-                                                   float* ws, LsParams lp, int last) {
+__device__ __forceinline__ LsResult fwd_recover_ls_body(const ProbRec* rec, const float* data,
+                                                        float* ws, LsParams lp, int last) {
   extern __shared__ float smem[];
   const int tid = threadIdx.x, BT = blockDim.x, nwv = (BT + 63) >> 6;
   const Prob P = make_prob<NX>(*rec, data, ws);
@@ -1601,98 +1683,117 @@ __device__ __forceinline__ int fwd_recover_ls_body(const ProbRec* rec, const flo
   }
   __syncthreads();
   // Task (ai, t): stage t at the current point (ai = 0) or at candidate
-  // alphas[ai-1]; its cost and dynamics defect (double) go to LDS, one wave
-  // then reduces each candidate in a fixed order.
+  // alphas[ai-1], in double; its cost and dynamics defect go to LDS, one wave
+  // then reduces each candidate in a fixed order.  Branch free: lanes past
+  // the end and the last stage evaluate clamped stages and discard the result.
   const int na = lp.n;
-  const int ntask = (na + 1) * N;
+  const int nrow = na + 1;
+  const int ntask = nrow * N;
   double* tc = (double*)(bulk_base(smem, P) + C.ls);
   double* td = tc + (kMaxAlphas + 1) * N;
   double* res = td + (kMaxAlphas + 1) * N;
-  double dn = 0.0;
-  for (int task = tid; task < ntask; task += BT) {
-    const int ai = task / N, t = task - ai * N;
-    const double al = (ai == 0) ? 0.0 : (double)lp.alphas[ai - 1];
-    double xa[NX];
+  double dn = 0.0;   // directional derivative of the cost at the current point
+  for (int t = tid; t < N; t += BT) {
+    dn += dcost_x<NX>(P, t, xbar + t * NX, xp + t * NX);
+    if (t < T)
+      for (int l = 0; l < m; ++l) dn += dcost_u1<NX>(P, t, l, ubar[t * m + l], up[t * m + l]);
+  }
+  const ModelPar mp = load_par(P);
+  int ai = tid / N, t = tid - (tid / N) * N;
+  for (int task0 = 0; task0 < ntask; task0 += BT) {
+    const int task = task0 + tid;
+    const bool live = task < ntask;
+    const int aic = live ? ai : na;
+    const int tcl = live ? t : N - 1;
+    const int tn = tcl < T ? tcl : T - 1;    // dynamics stage (clamped)
+    const double al = (double)pick_alpha(lp, aic);
+    double xa[NX], xa1[NX];
 #pragma unroll
-    for (int j = 0; j < NX; ++j)
-      xa[j] = (double)xbar[t * NX + j] + al * ((double)xp[t * NX + j] - (double)xbar[t * NX + j]);
-    double cst = cost_x<NX>(P, t, xa);
-    double dfc = 0.0;
-    if (t < T) {
-      const float* ub = ubar + t * m;
-      const float* uq = up + t * m;
-      for (int l = 0; l < m; ++l)
-        cst += cost_u1<NX>(P, t, l, (double)ub[l] + al * ((double)uq[l] - (double)ub[l]));
-      double xn[NX];
-      if (P.dyn == DMPC_DYN_LTV) {
-        const float* At = P.A + t * NX * NX;
-        const float* Bt = P.B + t * NX * m;
-#pragma unroll
-        for (int i = 0; i < NX; ++i) {
-          double sacc = P.c[t * NX + i];
-#pragma unroll
-          for (int j = 0; j < NX; ++j) sacc += (double)At[i * NX + j] * xa[j];
-          for (int l = 0; l < m; ++l)
-            sacc += (double)Bt[i * m + l] * ((double)ub[l] + al * ((double)uq[l] - (double)ub[l]));
-          xn[i] = sacc;
-        }
-      } else {
-        double ua[2];   // nonlinear models have at most two inputs
-        ua[0] = (double)ub[0] + al * ((double)uq[0] - (double)ub[0]);
-        ua[1] = (m > 1) ? (double)ub[1] + al * ((double)uq[1] - (double)ub[1]) : 0.0;
-        dyn_step<NX>(P, t, xa, ua, xn);
-      }
-#pragma unroll
-      for (int j = 0; j < NX; ++j) {
-        const double xa1 = (double)xbar[(t + 1) * NX + j] +
-                           al * ((double)xp[(t + 1) * NX + j] - (double)xbar[(t + 1) * NX + j]);
-        dfc += fabs(xa1 - xn[j]);
-      }
+    for (int j = 0; j < NX; ++j) {
+      const double b0 = xbar[tcl * NX + j], q0 = xp[tcl * NX + j];
+      const double b1 = xbar[(tn + 1) * NX + j], q1 = xp[(tn + 1) * NX + j];
+      xa[j] = b0 + al * (q0 - b0);
+      xa1[j] = b1 + al * (q1 - b1);
     }
-    tc[task] = cst;
-    td[task] = dfc;
-    if (ai == 0) {
-      dn += dcost_x<NX>(P, t, xbar + t * NX, xp + t * NX);
-      if (t < T)
-        for (int l = 0; l < m; ++l) dn += dcost_u1<NX>(P, t, l, ubar[t * m + l], up[t * m + l]);
+    double ua[2];   // nonlinear models have at most two inputs
+    double cst = cost_x<NX>(P, tcl, xa);
+    double cu = 0.0;
+    const float* ub = ubar + tn * m;
+    const float* uq = up + tn * m;
+    for (int l = 0; l < m; ++l) {
+      const double u = (double)ub[l] + al * ((double)uq[l] - (double)ub[l]);
+      cu += cost_u1<NX>(P, tn, l, u);
+      if (l < 2) ua[l] = u;
+    }
+    if (m < 2) ua[1] = 0.0;
+    double xn[NX];
+    if (P.dyn == DMPC_DYN_LTV) {
+      const float* At = P.A + tn * NX * NX;
+      const float* Bt = P.B + tn * NX * m;
+#pragma unroll
+      for (int i = 0; i < NX; ++i) {
+        double sacc = P.c[tn * NX + i];
+#pragma unroll
+        for (int j = 0; j < NX; ++j) sacc += (double)At[i * NX + j] * xa[j];
+        for (int l = 0; l < m; ++l)
+          sacc += (double)Bt[i * m + l] * ((double)ub[l] + al * ((double)uq[l] - (double)ub[l]));
+        xn[i] = sacc;
+      }
+    } else {
+      dyn_step<NX>(P, mp, tn, xa, ua, xn);
+    }
+    double dfc = 0.0;
+#pragma unroll
+    for (int j = 0; j < NX; ++j) dfc += fabs(xa1[j] - xn[j]);
+    const bool dyn_stage = tcl < T;
+    if (live) {
+      const int row = aic * N + tcl;
+      tc[row] = cst + (dyn_stage ? cu : 0.0);
+      td[row] = dyn_stage ? dfc : 0.0;
+    }
+    t += BT;
+    while (t >= N) {
+      t -= N;
+      ++ai;
     }
   }
   __syncthreads();
   {
     const int lane = tid & 63;
-    for (int ai = tid >> 6; ai <= na; ai += nwv) {
+    for (int r = tid >> 6; r < nrow; r += nwv) {
       double c0 = 0.0, d0 = 0.0;
-      for (int t = lane; t < N; t += 64) {
-        c0 += tc[ai * N + t];
-        d0 += td[ai * N + t];
+      for (int tt = lane; tt < N; tt += 64) {
+        c0 += tc[r * N + tt];
+        d0 += td[r * N + tt];
       }
       c0 = wave_sum_d(c0);
       d0 = wave_sum_d(d0);
       if (lane == 0) {
-        res[ai] = c0;
-        res[kMaxAlphas + 1 + ai] = d0;
+        res[r] = c0;
+        res[kMaxAlphas + 1 + r] = d0;
       }
     }
   }
   __syncthreads();
   const double num = block_sum_d(dn, (double*)(smem + C.red), nwv);
+  const double c_cur = res[0];
   const double fl1 = res[kMaxAlphas + 1];
   const double mu = fmax(num, 0.0) / fmax(0.5 * fl1, 1e-30);      // Eq. linesearch:penalty
   const double Dmu = num - mu * fl1;                               // Eq. linesearch:descent
-  const double phi0 = res[0] + mu * fl1;                           // Eq. linesearch:merit
+  const double phi0 = c_cur + mu * fl1;                            // Eq. linesearch:merit
   int sel = na - 1;                                                // min of the candidates
   bool passed = false;
-  for (int ai = 1; ai <= na && !passed; ++ai) {
-    const double al = lp.alphas[ai - 1];
-    const double dphi = (res[ai] + mu * res[kMaxAlphas + 1 + ai]) - phi0 - (double)lp.eta * al * Dmu;
+  for (int a = 1; a <= na && !passed; ++a) {
+    const double al = pick_alpha(lp, a);
+    const double dphi = (res[a] + mu * res[kMaxAlphas + 1 + a]) - phi0 - (double)lp.eta * al * Dmu;
     if (dphi < 0.f) {   // Eq. linesearch:decrease
-      sel = ai - 1;
+      sel = a - 1;
       passed = true;
     }
   }
   int flags = 0;
   if (last && !passed && na > 1) flags |= DMPC_PROB_LS_FALLBACK;
-  const float al = lp.alphas[sel];
+  const float al = pick_alpha(lp, sel + 1);
   if (last) {   // the last linearisation point and QP solution, for the backward pass
     float* xl = P.W + P.L.xlin;
     float* ul = P.W + P.L.ulin;
@@ -1711,7 +1812,7 @@ __device__ __forceinline__ int fwd_recover_ls_body(const ProbRec* rec, const flo
   for (int i = tid; i < R; i += BT) xbar[i] = fmaf(al, xp[i] - xbar[i], xbar[i]);
   for (int i = tid; i < TM; i += BT) ubar[i] = fmaf(al, up[i] - ubar[i], ubar[i]);
   __syncthreads();
-  return sel | (flags << 8);
+  return LsResult{sel, flags};
 }
 
 // Solution output (x, u after the last line search).  Returns NONFINITE bits.
@@ -2343,7 +2444,7 @@ __device__ __noinline__ void fwd_form_call(const ProbRec* rec, const float* data
   fwd_form_body<NX>(rec, data, ws);
 }
 template <int NX>
-__device__ __noinline__ int fwd_recover_ls_call(const ProbRec* rec, const float* data, float* ws,
+__device__ __noinline__ LsResult fwd_recover_ls_call(const ProbRec* rec, const float* data, float* ws,
                                                 LsParams lp, int last) {
   return fwd_recover_ls_body<NX>(rec, data, ws, lp, last);
 }
@@ -2380,7 +2481,7 @@ __device__ __forceinline__ void fwd_form(const ProbRec* rec, const float* data, 
   else fwd_form_call<NX>(rec, data, ws);
 }
 template <int NX>
-__device__ __forceinline__ int fwd_recover_ls(const ProbRec* rec, const float* data, float* ws,
+__device__ __forceinline__ LsResult fwd_recover_ls(const ProbRec* rec, const float* data, float* ws,
                                               LsParams lp, int last) {
   if constexpr (NX <= 4) return fwd_recover_ls_body<NX>(rec, data, ws, lp, last);
   return fwd_recover_ls_call<NX>(rec, data, ws, lp, last);
@@ -2465,9 +2566,9 @@ __global__ __launch_bounds__(MAXBT) void forward_kernel(KArgs a) {
       publish<NX, SLOTS, false, WAVE>(sh.w0, lam, P.R);
       publish<NX, SLOTS, false, WAVE>(sh.w2, lo, P.R);
       __syncthreads();
-      const int r = fwd_recover_ls<NX>(rec, a.data, a.ws, lp, k == a.sqp_iters - 1);
-      sel = r & 0xff;
-      flags |= r >> 8;
+      const LsResult r = fwd_recover_ls<NX>(rec, a.data, a.ws, lp, k == a.sqp_iters - 1);
+      sel = r.sel;
+      flags |= r.flags;
     }
     float* wlam = P.W + P.L.lam;
 #pragma unroll
