@@ -625,10 +625,16 @@ __device__ __forceinline__ ModelPar load_par(const Prob& P) {
   const uint64_t a = (uint64_t)P.dynp;
   const float* dp = (const float*)(((uint64_t)__builtin_amdgcn_readfirstlane((int)(a >> 32)) << 32) |
                                    (uint32_t)__builtin_amdgcn_readfirstlane((int)a));
-  const int np = P.dyn == DMPC_DYN_CARTPOLE ? kCartpoleParams
-                 : P.dyn == DMPC_DYN_BICYCLE ? kBicycleParams : 0;
 #pragma unroll
-  for (int i = 0; i < kBicycleParams; ++i) mp.v[i] = i < np ? dp[i] : 0.f;
+  for (int i = 0; i < kBicycleParams; ++i) mp.v[i] = 0.f;
+  // (whole blocks of unconditional loads: one wait for all of them)
+  if (P.dyn == DMPC_DYN_CARTPOLE) {
+#pragma unroll
+    for (int i = 0; i < kCartpoleParams; ++i) mp.v[i] = dp[i];
+  } else if (P.dyn == DMPC_DYN_BICYCLE) {
+#pragma unroll
+    for (int i = 0; i < kBicycleParams; ++i) mp.v[i] = dp[i];
+  }
   return mp;
 }
 
@@ -1758,7 +1764,28 @@ __device__ __forceinline__ LsResult fwd_recover_ls_body(const ProbRec* rec, cons
     }
   }
   __syncthreads();
-  {
+  // per-candidate sums in a fixed order, held in registers by every thread
+  double csum[kMaxAlphas + 1], dsum[kMaxAlphas + 1];
+  if (nwv == 1) {
+    // one wave: every row's partial sums first, then the wave sums side by side
+#pragma unroll
+    for (int r = 0; r <= kMaxAlphas; ++r) {
+      double c0 = 0.0, d0 = 0.0;
+      if (r < nrow)
+        for (int tt = tid; tt < N; tt += 64) {
+          c0 += tc[r * N + tt];
+          d0 += td[r * N + tt];
+        }
+      csum[r] = c0;
+      dsum[r] = d0;
+    }
+#pragma unroll
+    for (int r = 0; r <= kMaxAlphas; ++r)
+      if (r < nrow) {
+        csum[r] = wave_sum_d(csum[r]);
+        dsum[r] = wave_sum_d(dsum[r]);
+      }
+  } else {
     const int lane = tid & 63;
     for (int r = tid >> 6; r < nrow; r += nwv) {
       double c0 = 0.0, d0 = 0.0;
@@ -1773,22 +1800,30 @@ __device__ __forceinline__ LsResult fwd_recover_ls_body(const ProbRec* rec, cons
         res[kMaxAlphas + 1 + r] = d0;
       }
     }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r <= kMaxAlphas; ++r) {
+      csum[r] = r < nrow ? res[r] : 0.0;
+      dsum[r] = r < nrow ? res[kMaxAlphas + 1 + r] : 0.0;
+    }
   }
-  __syncthreads();
   const double num = block_sum_d(dn, (double*)(smem + C.red), nwv);
-  const double c_cur = res[0];
-  const double fl1 = res[kMaxAlphas + 1];
+  const double c_cur = csum[0];
+  const double fl1 = dsum[0];
   const double mu = fmax(num, 0.0) / fmax(0.5 * fl1, 1e-30);      // Eq. linesearch:penalty
   const double Dmu = num - mu * fl1;                               // Eq. linesearch:descent
   const double phi0 = c_cur + mu * fl1;                            // Eq. linesearch:merit
   int sel = na - 1;                                                // min of the candidates
   bool passed = false;
-  for (int a = 1; a <= na && !passed; ++a) {
-    const double al = pick_alpha(lp, a);
-    const double dphi = (res[a] + mu * res[kMaxAlphas + 1 + a]) - phi0 - (double)lp.eta * al * Dmu;
-    if (dphi < 0.f) {   // Eq. linesearch:decrease
-      sel = a - 1;
-      passed = true;
+#pragma unroll
+  for (int a = 1; a <= kMaxAlphas; ++a) {
+    if (a <= na && !passed) {
+      const double al = pick_alpha(lp, a);
+      const double dphi = (csum[a] + mu * dsum[a]) - phi0 - (double)lp.eta * al * Dmu;
+      if (dphi < 0.f) {   // Eq. linesearch:decrease
+        sel = a - 1;
+        passed = true;
+      }
     }
   }
   int flags = 0;
