@@ -120,14 +120,14 @@ typedef struct dmpc_opts {
                                correction with the float PCG; the first residual is that of
                                the warm start */
   float refine_tol;         /* relative tolerance of each refinement correction, relative
-                               to the residual it corrects (0 = the pass's tol; default 1e-2) */
+                               to the residual it corrects (0 = the pass's tol; default 1e-1) */
   float kkt_tol;            /* refinement stops once ||residual||_2 <= kkt_tol * ||KKT
                                right-hand side||_2 (default 1e-6); a warm start that
                                already meets it is kept without a PCG pass */
 } dmpc_opts;
 
 /* Fills *o with the defaults: 1 SQP iteration, PCG tol 1e-6, up to three
- * refinement passes (tol 1e-2, KKT target 1e-6), candidates {1, 0.7, 0.3, 0.1, 0.01}
+ * refinement passes (tol 1e-1, KKT target 1e-6), candidates {1, 0.7, 0.3, 0.1, 0.01}
  * (App. A.3), eta = 0.4, INIT_GIVEN. Host only. */
 void dmpc_default_opts(dmpc_opts* o);
 

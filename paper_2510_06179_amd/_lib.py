@@ -192,7 +192,7 @@ def check(rc, what=""):
 def make_opts(sqp_iters=1, pcg_tol=1e-6, pcg_abs_tol=0.0, pcg_max_iter=0,
               alphas=(1.0, 0.7, 0.3, 0.1, 0.01), ls_eta=0.4, init="given",
               bwd_warm_start=False, bwd_pcg_tol=None, bwd_pcg_max_iter=0, block_threads=0,
-              refine_steps=3, refine_tol=1e-2, kkt_tol=1e-6):
+              refine_steps=3, refine_tol=1e-1, kkt_tol=1e-6):
     o = Opts()
     load().dmpc_default_opts(ctypes.byref(o))
     o.sqp_iters = int(sqp_iters)

@@ -256,7 +256,7 @@ void dmpc_default_opts(dmpc_opts* o) {
   o->init = DMPC_INIT_GIVEN;
   o->bwd_pcg_tol = 1e-6f;
   o->refine_steps = 3;
-  o->refine_tol = 1e-2f;
+  o->refine_tol = 1e-1f;
   o->kkt_tol = 1e-6f;
 }
 
