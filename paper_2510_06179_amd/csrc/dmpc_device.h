@@ -560,9 +560,9 @@ __device__ __forceinline__ const float* sp_xref(const Prob& P) {
 // Stage costs at a point (the true costs, as used by the merit function),
 // evaluated in double.
 template <int NX>
-__device__ __forceinline__ double cost_x(const Prob& P, int t, const double* x) {
+__device__ __forceinline__ double cost_x(const Prob& P, int t, const double* x, int cost_kind) {
   double s = 0.0;
-  if (P.cost == DMPC_COST_DIAG) {
+  if (cost_kind == DMPC_COST_DIAG) {
     const float* Qd = P.costp + t * NX;
     const float* q = P.costp + P.N * NX + t * NX;
 #pragma unroll
@@ -578,8 +578,8 @@ __device__ __forceinline__ double cost_x(const Prob& P, int t, const double* x) 
   return s;
 }
 template <int NX>
-__device__ __forceinline__ double cost_u1(const Prob& P, int t, int l, double u) {
-  if (P.cost == DMPC_COST_DIAG) {
+__device__ __forceinline__ double cost_u1(const Prob& P, int t, int l, double u, int cost_kind) {
+  if (cost_kind == DMPC_COST_DIAG) {
     const float* Rd = P.costp + 2 * P.N * NX + t * P.m;
     const float* r = Rd + P.TM;
     return 0.5 * (double)Rd[l] * u * u + (double)r[l] * u;
@@ -641,8 +641,9 @@ __device__ __forceinline__ ModelPar load_par(const Prob& P) {
 // Next state of the true dynamics, in double (rollout and merit function).
 template <int NX>
 __device__ __forceinline__ void dyn_step(const Prob& P, const ModelPar& mp, int t,
-                                         const double* x, const double* u, double* xn) {
-  if (P.dyn == DMPC_DYN_LTV) {
+                                         const double* x, const double* u, double* xn,
+                                         int dyn_kind) {
+  if (dyn_kind == DMPC_DYN_LTV) {
     const float* At = P.A + t * NX * NX;
     const float* Bt = P.B + t * NX * P.m;
     const float* ct = P.c + t * NX;
@@ -657,13 +658,13 @@ __device__ __forceinline__ void dyn_step(const Prob& P, const ModelPar& mp, int 
     return;
   }
   if constexpr (NX == 4) {
-    if (P.dyn == DMPC_DYN_CARTPOLE) {
+    if (dyn_kind == DMPC_DYN_CARTPOLE) {
       cartpole_step<double>(mp.v, x, u, xn);
       return;
     }
   }
   if constexpr (NX == 8) {
-    if (P.dyn == DMPC_DYN_BICYCLE) {
+    if (dyn_kind == DMPC_DYN_BICYCLE) {
       bicycle_step<double>(mp.v, x, u, xn);
       return;
     }
@@ -1485,7 +1486,7 @@ __device__ __noinline__ void fwd_begin(const ProbRec* rec, const float* data, co
       for (int t = 0; t < T; ++t) {
         uc[0] = ubar[t * m];
         uc[1] = (m > 1) ? ubar[t * m + 1] : 0.f;
-        dyn_step<NX>(P, mp, t, xc, uc, xn);
+        dyn_step<NX>(P, mp, t, xc, uc, xn, P.dyn);
 #pragma unroll
         for (int i = 0; i < NX; ++i) {
           xbar[(t + 1) * NX + i] = (float)xn[i];
@@ -1639,6 +1640,99 @@ __device__ __forceinline__ ResNorms fwd_residual64_body(const ProbRec* rec, cons
   return n;
 }
 
+// Line-search tasks (ai, t) -- stage t at the current point (ai = 0) or at
+// candidate alphas[ai-1] -- for one dynamics and cost kind: cost and dynamics
+// defect in double to tc/td.  Two tasks per lane per pass, computed side by
+// side (branch free: lanes past the end and the last stage evaluate clamped
+// stages and discard the result), so that the long double-precision chains
+// of the two overlap.
+struct LsTaskArgs {
+  const float *xbar, *xp, *ubar, *up;
+  double *tc, *td;
+  int ntask, na;
+};
+template <int NX, int DYN, int COST>
+__device__ __forceinline__ void ls_tasks(const Prob& P, const ModelPar& mp, const LsParams& lp,
+                                         const LsTaskArgs& a) {
+  constexpr int MU = DYN == DMPC_DYN_CARTPOLE ? 1 : 2;   // inputs of the nonlinear models
+  const int tid = threadIdx.x, BT = blockDim.x;
+  const int N = P.N, T = P.T, m = P.m;
+  int ai[2], tt[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int task = tid + h * BT;
+    ai[h] = task / N;
+    tt[h] = task - ai[h] * N;
+  }
+  for (int task0 = 0; task0 < a.ntask; task0 += 2 * BT) {
+    double cst[2], dfc[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const bool live = task0 + h * BT + tid < a.ntask;
+      const int aic = live ? ai[h] : a.na;
+      const int tcl = live ? tt[h] : N - 1;
+      const int tn = tcl < T ? tcl : T - 1;    // dynamics stage (clamped)
+      const double al = (double)pick_alpha(lp, aic);
+      double xa[NX], xa1[NX];
+#pragma unroll
+      for (int j = 0; j < NX; ++j) {
+        const double b0 = a.xbar[tcl * NX + j], q0 = a.xp[tcl * NX + j];
+        const double b1 = a.xbar[(tn + 1) * NX + j], q1 = a.xp[(tn + 1) * NX + j];
+        xa[j] = b0 + al * (q0 - b0);
+        xa1[j] = b1 + al * (q1 - b1);
+      }
+      const float* ub = a.ubar + tn * m;
+      const float* uq = a.up + tn * m;
+      double c = cost_x<NX>(P, tcl, xa, COST), cu = 0.0;
+      double xn[NX];
+      if constexpr (DYN == DMPC_DYN_LTV) {
+        const float* At = P.A + tn * NX * NX;
+        const float* Bt = P.B + tn * NX * m;
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+          double sacc = P.c[tn * NX + i];
+#pragma unroll
+          for (int j = 0; j < NX; ++j) sacc += (double)At[i * NX + j] * xa[j];
+          xn[i] = sacc;
+        }
+        for (int l = 0; l < m; ++l) {
+          const double u = (double)ub[l] + al * ((double)uq[l] - (double)ub[l]);
+          cu += cost_u1<NX>(P, tn, l, u, COST);
+#pragma unroll
+          for (int i = 0; i < NX; ++i) xn[i] += (double)Bt[i * m + l] * u;
+        }
+      } else {
+        double ua[2];
+#pragma unroll
+        for (int l = 0; l < 2; ++l) {
+          ua[l] = l < MU ? (double)ub[l] + al * ((double)uq[l] - (double)ub[l]) : 0.0;
+          if (l < MU) cu += cost_u1<NX>(P, tn, l, ua[l], COST);
+        }
+        dyn_step<NX>(P, mp, tn, xa, ua, xn, DYN);
+      }
+      double d = 0.0;
+#pragma unroll
+      for (int j = 0; j < NX; ++j) d += fabs(xa1[j] - xn[j]);
+      const bool dyn_stage = tcl < T;
+      cst[h] = c + (dyn_stage ? cu : 0.0);
+      dfc[h] = dyn_stage ? d : 0.0;
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (task0 + h * BT + tid < a.ntask) {
+        const int row = ai[h] * N + tt[h];
+        a.tc[row] = cst[h];
+        a.td[row] = dfc[h];
+      }
+      tt[h] += 2 * BT;
+      while (tt[h] >= N) {
+        tt[h] -= N;
+        ++ai[h];
+      }
+    }
+  }
+}
+
 // QP primal solution (Eq. schur:xu, user signs; accumulated in double):
 //   x_t = -Q_t^-1 (q_t + lambda_t - A_t' lambda_{t+1}),  u_t = -R_t^-1 (r_t - B_t' lambda_{t+1})
 // lambda from the LDS window w0; then the line search (App. A.3, Alg.
@@ -1705,62 +1799,17 @@ __device__ __forceinline__ LsResult fwd_recover_ls_body(const ProbRec* rec, cons
       for (int l = 0; l < m; ++l) dn += dcost_u1<NX>(P, t, l, ubar[t * m + l], up[t * m + l]);
   }
   const ModelPar mp = load_par(P);
-  int ai = tid / N, t = tid - (tid / N) * N;
-  for (int task0 = 0; task0 < ntask; task0 += BT) {
-    const int task = task0 + tid;
-    const bool live = task < ntask;
-    const int aic = live ? ai : na;
-    const int tcl = live ? t : N - 1;
-    const int tn = tcl < T ? tcl : T - 1;    // dynamics stage (clamped)
-    const double al = (double)pick_alpha(lp, aic);
-    double xa[NX], xa1[NX];
-#pragma unroll
-    for (int j = 0; j < NX; ++j) {
-      const double b0 = xbar[tcl * NX + j], q0 = xp[tcl * NX + j];
-      const double b1 = xbar[(tn + 1) * NX + j], q1 = xp[(tn + 1) * NX + j];
-      xa[j] = b0 + al * (q0 - b0);
-      xa1[j] = b1 + al * (q1 - b1);
-    }
-    double ua[2];   // nonlinear models have at most two inputs
-    double cst = cost_x<NX>(P, tcl, xa);
-    double cu = 0.0;
-    const float* ub = ubar + tn * m;
-    const float* uq = up + tn * m;
-    for (int l = 0; l < m; ++l) {
-      const double u = (double)ub[l] + al * ((double)uq[l] - (double)ub[l]);
-      cu += cost_u1<NX>(P, tn, l, u);
-      if (l < 2) ua[l] = u;
-    }
-    if (m < 2) ua[1] = 0.0;
-    double xn[NX];
-    if (P.dyn == DMPC_DYN_LTV) {
-      const float* At = P.A + tn * NX * NX;
-      const float* Bt = P.B + tn * NX * m;
-#pragma unroll
-      for (int i = 0; i < NX; ++i) {
-        double sacc = P.c[tn * NX + i];
-#pragma unroll
-        for (int j = 0; j < NX; ++j) sacc += (double)At[i * NX + j] * xa[j];
-        for (int l = 0; l < m; ++l)
-          sacc += (double)Bt[i * m + l] * ((double)ub[l] + al * ((double)uq[l] - (double)ub[l]));
-        xn[i] = sacc;
-      }
-    } else {
-      dyn_step<NX>(P, mp, tn, xa, ua, xn);
-    }
-    double dfc = 0.0;
-#pragma unroll
-    for (int j = 0; j < NX; ++j) dfc += fabs(xa1[j] - xn[j]);
-    const bool dyn_stage = tcl < T;
-    if (live) {
-      const int row = aic * N + tcl;
-      tc[row] = cst + (dyn_stage ? cu : 0.0);
-      td[row] = dyn_stage ? dfc : 0.0;
-    }
-    t += BT;
-    while (t >= N) {
-      t -= N;
-      ++ai;
+  const LsTaskArgs ta{xbar, xp, ubar, up, tc, td, ntask, na};
+  // (the cart-pole has nx = 4 and the bicycle nx = 8: other pairs are refused
+  // when the problem is validated)
+  if (P.dyn == DMPC_DYN_LTV) {
+    if (P.cost == DMPC_COST_DIAG) ls_tasks<NX, DMPC_DYN_LTV, DMPC_COST_DIAG>(P, mp, lp, ta);
+    else ls_tasks<NX, DMPC_DYN_LTV, DMPC_COST_SOFTPLUS>(P, mp, lp, ta);
+  } else {
+    constexpr int D = NX == 4 ? DMPC_DYN_CARTPOLE : DMPC_DYN_BICYCLE;
+    if constexpr (NX == 4 || NX == 8) {
+      if (P.cost == DMPC_COST_DIAG) ls_tasks<NX, D, DMPC_COST_DIAG>(P, mp, lp, ta);
+      else ls_tasks<NX, D, DMPC_COST_SOFTPLUS>(P, mp, lp, ta);
     }
   }
   __syncthreads();
