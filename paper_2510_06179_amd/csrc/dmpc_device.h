@@ -311,9 +311,10 @@ __device__ __forceinline__ double readlane_d(double x, int l) {
 // Double wave sum, the same pattern on the two halves of each double.
 template <int CTRL, int ROWS = 0xF>
 __device__ __forceinline__ double dpp_d(double v) {
+  // (bound_ctrl: lanes without a source read zero, so no old value is needed)
   const long long u = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)u, CTRL, ROWS, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, ROWS, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp((int)u, CTRL, ROWS, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(u >> 32), CTRL, ROWS, 0xF, true);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 __device__ __forceinline__ double wave_sum_d(double v) {
@@ -1816,24 +1817,25 @@ __device__ __forceinline__ LsResult fwd_recover_ls_body(const ProbRec* rec, cons
   // per-candidate sums in a fixed order, held in registers by every thread
   double csum[kMaxAlphas + 1], dsum[kMaxAlphas + 1];
   if (nwv == 1) {
-    // one wave: every row's partial sums first, then the wave sums side by side
+    // one wave: every row's partial sums first (rows past the last read the
+    // last row and count zero), then all the wave sums in one branch-free
+    // block, side by side
 #pragma unroll
-    for (int r = 0; r <= kMaxAlphas; ++r) {
-      double c0 = 0.0, d0 = 0.0;
-      if (r < nrow)
-        for (int tt = tid; tt < N; tt += 64) {
-          c0 += tc[r * N + tt];
-          d0 += td[r * N + tt];
-        }
-      csum[r] = c0;
-      dsum[r] = d0;
+    for (int r = 0; r <= kMaxAlphas; ++r) csum[r] = dsum[r] = 0.0;
+    for (int tt = tid; tt < N; tt += 64) {
+#pragma unroll
+      for (int r = 0; r <= kMaxAlphas; ++r) {
+        const int rr = r < nrow ? r : nrow - 1;
+        const double cv = tc[rr * N + tt], dv = td[rr * N + tt];
+        csum[r] += r < nrow ? cv : 0.0;
+        dsum[r] += r < nrow ? dv : 0.0;
+      }
     }
 #pragma unroll
-    for (int r = 0; r <= kMaxAlphas; ++r)
-      if (r < nrow) {
-        csum[r] = wave_sum_d(csum[r]);
-        dsum[r] = wave_sum_d(dsum[r]);
-      }
+    for (int r = 0; r <= kMaxAlphas; ++r) {
+      csum[r] = wave_sum_d(csum[r]);
+      dsum[r] = wave_sum_d(dsum[r]);
+    }
   } else {
     const int lane = tid & 63;
     for (int r = tid >> 6; r < nrow; r += nwv) {
