@@ -317,6 +317,25 @@ __device__ __forceinline__ double dpp_d(double v) {
   const int hi = __builtin_amdgcn_mov_dpp((int)(u >> 32), CTRL, ROWS, 0xF, true);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
+// K independent double wave sums, step-major so that the K DPP exchanges of a
+// step are in flight together (the same pattern and order as wave_sum_d).
+template <int K>
+__device__ __forceinline__ void wave_sum_d_multi(double (&v)[K]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_d<0xB1>(v[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_d<0x4E>(v[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_d<0x141>(v[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_d<0x140>(v[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_d<0x142>(v[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_d<0x143>(v[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = readlane_d(v[k], 63);
+}
 __device__ __forceinline__ double wave_sum_d(double v) {
   v += dpp_d<0xB1>(v);
   v += dpp_d<0x4E>(v);
@@ -1740,7 +1759,8 @@ __device__ __forceinline__ void ls_tasks(const Prob& P, const ModelPar& mp, cons
 // linesearch) and the SQP update of (x, u).  Returns sel | flags << 8.
 template <int NX>
 __device__ __forceinline__ LsResult fwd_recover_ls_body(const ProbRec* rec, const float* data,
-                                                        float* ws, LsParams lp, int last) {
+                                                        float* ws, LsParams lp, int last,
+                                                        int recovered) {
   extern __shared__ float smem[];
   const int tid = threadIdx.x, BT = blockDim.x, nwv = (BT + 63) >> 6;
   const Prob P = make_prob<NX>(*rec, data, ws);
@@ -1752,7 +1772,7 @@ __device__ __forceinline__ LsResult fwd_recover_ls_body(const ProbRec* rec, cons
   float* up = bulk_base(smem, P) + C.up;
   const float* w0 = smem + C.w0;   // multipliers, high part
   const float* w2 = smem + C.w2;   // low part
-  {
+  if (!recovered) {   // (the wave-block kernels recover z in registers: wave_recover)
     const double* iQd = (const double*)(P.Wq + P.L.iQd);
     const double* iRd = (const double*)(P.Wq + P.L.iRd);
     const float* q = P.Wq + P.L.q;
@@ -1831,11 +1851,8 @@ __device__ __forceinline__ LsResult fwd_recover_ls_body(const ProbRec* rec, cons
         dsum[r] += r < nrow ? dv : 0.0;
       }
     }
-#pragma unroll
-    for (int r = 0; r <= kMaxAlphas; ++r) {
-      csum[r] = wave_sum_d(csum[r]);
-      dsum[r] = wave_sum_d(dsum[r]);
-    }
+    wave_sum_d_multi<kMaxAlphas + 1>(csum);
+    wave_sum_d_multi<kMaxAlphas + 1>(dsum);
   } else {
     const int lane = tid & 63;
     for (int r = tid >> 6; r < nrow; r += nwv) {
@@ -2136,6 +2153,54 @@ __device__ __forceinline__ ResNorms wave_residual(const Prob& P, const float (&h
     }
   }
   return ResNorms{wave_sum(r2), wave_sum(b2)};
+}
+
+// Wave-block recovery of the QP solution (Eq. schur:xu, user signs, in
+// double, rounded to float) from the multipliers in registers, a lane per
+// stage block: the operations of the recovery in fwd_recover_ls, with the
+// next stage's multipliers from the next lane and every load before the
+// arithmetic (clamped stages; at the last stage lambda_{t+1} = 0 and the
+// clamped A_{T-1} adds exact zeros).  Writes x and u to xp, up.
+template <int NX, int SLOTS>
+__device__ __forceinline__ void wave_recover(const Prob& P, const float (&hi)[SLOTS],
+                                             const float (&lo)[SLOTS], float* xp, float* up) {
+  constexpr int BPL = SLOTS / NX;
+  const int lane = threadIdx.x & 63;
+  const int T = P.T, N = P.N, m = P.m;
+  const float* q = P.Wq + P.L.q;
+  const float* rv = P.Wq + P.L.r;
+  const double* iQd = (const double*)(P.Wq + P.L.iQd);
+  const double* iRd = (const double*)(P.Wq + P.L.iRd);
+  float nh[SLOTS], nl[SLOTS], unused[SLOTS];
+  wave_neighbours<NX, SLOTS>(hi, unused, nh);
+  wave_neighbours<NX, SLOTS>(lo, unused, nl);
+#pragma unroll
+  for (int b = 0; b < BPL; ++b) {
+    const int t = lane + 64 * b;
+    const bool live = t < N;
+    const int tc = live ? t : N - 1;
+    const int tp = tc < T ? tc : T - 1;
+    double ln[NX];
+#pragma unroll
+    for (int k = 0; k < NX; ++k) ln[k] = (double)nh[b * NX + k] + (double)nl[b * NX + k];
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+      const int rho = tc * NX + i;
+      double acc = (double)q[rho] + ((double)hi[b * NX + i] + (double)lo[b * NX + i]);
+#pragma unroll
+      for (int k = 0; k < NX; ++k) acc -= ldA<double>(P, tp * NX * NX + k * NX + i) * ln[k];
+      const float x = (float)(-acc * iQd[rho]);
+      if (live) xp[rho] = x;
+    }
+    for (int l = 0; l < m; ++l) {
+      const int idx = tp * m + l;
+      double acc = (double)rv[idx];
+#pragma unroll
+      for (int k = 0; k < NX; ++k) acc -= ldB<double>(P, tp * NX * m + k * m + l) * ln[k];
+      const float u = (float)(-acc * iRd[idx]);
+      if (live && tc < T) up[idx] = u;
+    }
+  }
 }
 
 // Wave-block assembly (Eq. shurcomplement) and stair preconditioner (Eq.
@@ -2531,8 +2596,8 @@ __device__ __noinline__ void fwd_form_call(const ProbRec* rec, const float* data
 }
 template <int NX>
 __device__ __noinline__ LsResult fwd_recover_ls_call(const ProbRec* rec, const float* data, float* ws,
-                                                LsParams lp, int last) {
-  return fwd_recover_ls_body<NX>(rec, data, ws, lp, last);
+                                                LsParams lp, int last, int recovered) {
+  return fwd_recover_ls_body<NX>(rec, data, ws, lp, last, recovered);
 }
 template <int NX>
 __device__ __noinline__ ResNorms fwd_residual64_call(const ProbRec* rec, const float* data,
@@ -2568,9 +2633,9 @@ __device__ __forceinline__ void fwd_form(const ProbRec* rec, const float* data, 
 }
 template <int NX>
 __device__ __forceinline__ LsResult fwd_recover_ls(const ProbRec* rec, const float* data, float* ws,
-                                              LsParams lp, int last) {
-  if constexpr (NX <= 4) return fwd_recover_ls_body<NX>(rec, data, ws, lp, last);
-  return fwd_recover_ls_call<NX>(rec, data, ws, lp, last);
+                                              LsParams lp, int last, int recovered) {
+  if constexpr (NX <= 4) return fwd_recover_ls_body<NX>(rec, data, ws, lp, last, recovered);
+  return fwd_recover_ls_call<NX>(rec, data, ws, lp, last, recovered);
 }
 
 // Refinement residual of the current multipliers (hi + lo) into rr, in the
@@ -2621,6 +2686,7 @@ __global__ __launch_bounds__(MAXBT) void forward_kernel(KArgs a) {
     const ProbRec* rec = a.recs + pi;
     const Prob P = make_prob<NX>(*rec, a.data, a.ws);
     const Lds sh = lds_of<NX>(smem, P);
+    const Carve lds_carve = carve_of<NX>(P);
     float* soll = a.sol + rec->sol_off + P.R + P.TM;
     fwd_begin<NX>(rec, a.data, a.sol, a.ws, a.init);
     float lam[SLOTS], lo[SLOTS];
@@ -2649,10 +2715,15 @@ __global__ __launch_bounds__(MAXBT) void forward_kernel(KArgs a) {
           [&](const float (&h)[SLOTS], const float (&l)[SLOTS], float (&rr)[SLOTS]) {
             return residual_rows<NX, SLOTS, WAVE, false>(rec, a, P, sh, h, l, rr);
           });
-      publish<NX, SLOTS, false, WAVE>(sh.w0, lam, P.R);
-      publish<NX, SLOTS, false, WAVE>(sh.w2, lo, P.R);
+      if constexpr (WAVE) {
+        wave_recover<NX, SLOTS>(P, lam, lo, bulk_base(smem, P) + lds_carve.xp,
+                                bulk_base(smem, P) + lds_carve.up);
+      } else {
+        publish<NX, SLOTS, false, WAVE>(sh.w0, lam, P.R);
+        publish<NX, SLOTS, false, WAVE>(sh.w2, lo, P.R);
+      }
       __syncthreads();
-      const LsResult r = fwd_recover_ls<NX>(rec, a.data, a.ws, lp, k == a.sqp_iters - 1);
+      const LsResult r = fwd_recover_ls<NX>(rec, a.data, a.ws, lp, k == a.sqp_iters - 1, WAVE);
       sel = r.sel;
       flags |= r.flags;
     }
