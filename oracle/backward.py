@@ -10,6 +10,14 @@
                         matrices: dG = -z~ z', db = -z~, dH = -(lam z~' + lam~ z'),
                         dd = lam~; then read off at the positions where the QP
                         data sit in G, b, H, d (Eq. KKTmatrix).
+* ``jvp``            -- forward-mode sensitivity of the same solution map:
+                        differentiating K(theta) w(theta) = rhs(theta) along a
+                        tangent v gives K dw = d rhs - dK w, solved with the
+                        same LU factors.  K and rhs are affine in the inputs
+                        the tangent may move (linear dynamics A, B, c; diagonal
+                        costs Qd, q, Rd, r away from the PD clamp; x_s), so
+                        (dK, d rhs) are the symmetric differences of the
+                        dense KKT builders at theta +- s v divided by 2 s.
 * ``vjp``            -- cotangents of the problem's own inputs: x_s, the cost
                         parameters (through the QP cost data, by complex step
                         for the softplus weights; with the PD-projection mask
@@ -20,8 +28,9 @@
                         final QP's solution map.
 
 Pinned (tests): central finite differences of the oracle's QP solution map,
-the envelope identity (dl/dz = G z + b gives z~ = 0, lam~ = -lam), and
-dJ*/dx_s = -lam_0 on LQ problems.
+the envelope identity (dl/dz = G z + b gives z~ = 0, lam~ = -lam),
+dJ*/dx_s = -lam_0 on LQ problems, and the duality of the two modes:
+<g, JVP(v)> = <VJP(g), v> for random g and v.
 """
 from __future__ import annotations
 
@@ -127,3 +136,35 @@ def vjp(prob, xbar, ubar, qpd, sol, gx, gu, glam=None, h=1e-30):
         g["B"] = -np.array(cot["B"])
         g["c"] = np.array(cot["C"])
     return g, (xt, ut, lamt)
+
+
+JVP_KEYS_DIAG = ("Qd", "q", "Rd", "r")
+JVP_KEYS_LTV = ("A", "B", "c")
+
+
+def _moved(prob, tangent, s):
+    """The problem with its inputs moved by s * tangent (keys as the VJP's
+    gradient: A, B, c for linear dynamics, Qd, q, Rd, r for diagonal costs,
+    x0)."""
+    out = dict(prob)
+    keys = ("x0",) + (JVP_KEYS_DIAG if prob["cost"] == "diag" else ()) + \
+        (JVP_KEYS_LTV if prob["dyn"] == "ltv" else ())
+    for k in keys:
+        if k in tangent:
+            out[k] = np.asarray(prob[k], np.float64) + s * np.asarray(tangent[k], np.float64)
+    return out
+
+
+def jvp(prob, xbar, ubar, qpd, sol, tangent, s=1e-3):
+    """(dx [N,nx], du [T,nu], dlam [N,nx]): derivative of the final QP's
+    solution (x, u, lam) along `tangent`, linearisation point fixed.  Only
+    diagonal costs; a tangent of nonlinear model parameters is not read."""
+    if prob["cost"] != "diag":
+        raise ValueError("jvp: diagonal costs only")
+    T, nx, nu = qpd["T"], qpd["nx"], qpd["nu"]
+    Kp, rp, _ = qp.kkt(qp.qp_data(_moved(prob, tangent, s), xbar, ubar), _moved(prob, tangent, s)["x0"])
+    Km, rm, _ = qp.kkt(qp.qp_data(_moved(prob, tangent, -s), xbar, ubar), _moved(prob, tangent, -s)["x0"])
+    dK = (Kp - Km) / (2 * s)
+    drhs = (rp - rm) / (2 * s)
+    dw = sla.lu_solve(sol["lu"], drhs - dK @ sol["w"])
+    return qp.split_w(dw, T, nx, nu)

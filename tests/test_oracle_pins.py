@@ -363,3 +363,47 @@ def test_blockwise_kkt_residual_equals_dense():
             assert abs(a - b) <= 1e-12 * max(a, 1.0), (a, b)
         s = oracle.qp.solve_qp(qpd, p["x0"])
         assert oracle.qp.kkt_residual_blocks(qpd, p["x0"], s["x"], s["u"], s["lam"]) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Forward-mode sensitivity (JVP) of the final QP's solution map
+# ---------------------------------------------------------------------------
+def _jvp_case(p, seed):
+    from oracle import backward, qp, sqp
+    xb, ub, _ = sqp.initial_guess(p)
+    qpd = qp.qp_data(p, xb, ub)
+    sol = qp.solve_qp(qpd, p["x0"])
+    rng = np.random.default_rng(seed)
+    keys = ["x0", "Qd", "q", "Rd", "r"] + (["A", "B", "c"] if p["dyn"] == "ltv" else [])
+    tan = {k: rng.standard_normal(np.shape(p[k])) for k in keys}
+    return backward, qp, xb, ub, qpd, sol, tan, rng
+
+
+@pytest.mark.parametrize("which", ["lq", "cartpole"])
+def test_jvp_is_dual_to_the_vjp(which):
+    # <g, J v> = <J' g, v>: the forward and reverse modes are computed by
+    # different code (dK w versus the QP-data cotangents)
+    p = W.lq_batch(3)[1] if which == "lq" else W.cartpole_batch(2, batch=2)[0]
+    backward, qp, xb, ub, qpd, sol, tan, rng = _jvp_case(p, 5)
+    dx, du, dl = backward.jvp(p, xb, ub, qpd, sol, tan)
+    gx, gu, gl = (rng.standard_normal(a.shape) for a in (dx, du, dl))
+    g, _ = backward.vjp(p, xb, ub, qpd, sol, gx, gu, gl)
+    lhs = np.sum(gx * dx) + np.sum(gu * du) + np.sum(gl * dl)
+    rhs = sum(np.sum(g[k] * tan[k]) for k in tan)
+    assert abs(lhs - rhs) <= 1e-10 * max(abs(lhs), 1.0), (lhs, rhs)
+
+
+def test_jvp_matches_finite_differences_of_the_solution_map():
+    p = W.lq_batch(3)[2]
+    backward, qp, xb, ub, qpd, sol, tan, rng = _jvp_case(p, 6)
+    dw = backward.jvp(p, xb, ub, qpd, sol, tan)
+    h = 1e-6
+
+    def solve_at(s):
+        pm = backward._moved(p, tan, s)
+        so = qp.solve_qp(qp.qp_data(pm, xb, ub), pm["x0"])
+        return so["x"], so["u"], so["lam"]
+
+    fd = [(a - b) / (2 * h) for a, b in zip(solve_at(h), solve_at(-h))]
+    for f, j in zip(fd, dw):
+        assert np.max(np.abs(f - j)) <= 1e-7 * np.max(np.abs(j)), np.max(np.abs(f - j))
