@@ -187,6 +187,25 @@ dmpc_status dmpc_solve_backward(dmpc_plan* plan, const float* data, const float*
                                 float* adj, float* grad, void* workspace, int32_t* status,
                                 int32_t* info, void* stream);
 
+/* Forward-mode sensitivity (JVP) of the last QP's solution map, the
+ * linearisation point held fixed (as for the backward pass): the derivative
+ * of the last QP's x, u and lambda along a tangent of the inputs, from
+ * differentiating Eq. ocp:KKT (K dw = d rhs - dK w; K is symmetric, so the
+ * same adjoint PCG solves it, reusing the stored Schur and preconditioner
+ * blocks).  Needs the workspace of a dmpc_solve on the same plan.  Problems
+ * with SOFTPLUS costs: UNSUPPORTED.
+ *   tangent [data_len]  tangent laid out like the data arena; read: A, B, c
+ *                       (LTV), Qd, q, Rd, r (DIAG), x_s; the parameters of
+ *                       CARTPOLE/BICYCLE dynamics are not read (tangent 0)
+ *   rhs     [sol_len]   scratch: the right-hand side of the tangent system
+ *   out     [sol_len]   out: dx, du, dlambda laid out like the solution arena;
+ *                       in: the PCG warm start when opts->bwd_warm_start
+ *   grad    [data_len]  scratch (the backward kernel's VJP of rhs lands here)
+ * status / info as for dmpc_solve_backward (info[1]: PCG iterations). */
+dmpc_status dmpc_solve_jvp(dmpc_plan* plan, const float* data, const float* tangent, float* rhs,
+                           float* out, float* grad, void* workspace, int32_t* status,
+                           int32_t* info, void* stream);
+
 /* The same two passes for problem `index` of the plan alone, one launch each
  * (the plain one-problem-per-launch form). */
 dmpc_status dmpc_solve_one(dmpc_plan* plan, int32_t index, const float* data, float* sol,

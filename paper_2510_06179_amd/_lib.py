@@ -33,7 +33,7 @@ EXPORTED = (
     "dmpc_server_create", "dmpc_server_destroy", "dmpc_server_add_session", "dmpc_server_submit",
     "dmpc_server_wait", "dmpc_server_drain", "dmpc_server_get_stats", "dmpc_server_reset_stats",
     "dmpc_server_trace", "dmpc_list_variants", "dmpc_set_tuning", "dmpc_get_tuning",
-    "dmpc_choose_mapping",
+    "dmpc_choose_mapping", "dmpc_solve_jvp",
 )
 TUNING_PATH = os.path.join(PKG, "tuning_gfx950.json")
 REQ_PENDING, REQ_RUNNING, REQ_DONE, REQ_FAILED = range(4)
@@ -130,6 +130,7 @@ def load():
         "dmpc_plan_destroy": (i32, [vp]),
         "dmpc_solve": (i32, [vp, vp, vp, vp, vp, vp, vp]),
         "dmpc_solve_backward": (i32, [vp, vp, vp, vp, vp, vp, vp, vp, vp]),
+        "dmpc_solve_jvp": (i32, [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
         "dmpc_solve_one": (i32, [vp, i32, vp, vp, vp, vp, vp, vp]),
         "dmpc_solve_backward_one": (i32, [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]),
         "dmpc_status_string": (ctypes.c_char_p, [i32]),

@@ -645,6 +645,26 @@ dmpc_status dmpc_solve_backward(dmpc_plan* plan, const float* data, const float*
   return run(plan, -1, false, data, nullptr, dl_dsol, adj, grad, workspace, status, info, stream);
 }
 
+dmpc_status dmpc_solve_jvp(dmpc_plan* plan, const float* data, const float* tangent, float* rhs,
+                           float* out, float* grad, void* workspace, int32_t* status,
+                           int32_t* info, void* stream) {
+  if (!plan) return DMPC_ERR_INVALID_ARG;
+  if (plan->count == 0) return DMPC_OK;
+  if (!data || !tangent || !rhs || !out || !grad || !workspace || !status || !info)
+    return DMPC_ERR_INVALID_ARG;
+  for (const ProbRec& r : plan->recs)
+    if (r.cost != DMPC_COST_DIAG) return DMPC_ERR_UNSUPPORTED;
+  int prev = 0;
+  if (hipGetDevice(&prev) != hipSuccess) return DMPC_ERR_HIP;
+  if (prev != plan->h->device && hipSetDevice(plan->h->device) != hipSuccess) return DMPC_ERR_HIP;
+  const int rc = launch_jvp_rhs(plan->d_recs, plan->count, data, tangent, (const float*)workspace,
+                                rhs, stream);
+  if (prev != plan->h->device) hipSetDevice(prev);
+  if (rc != 0) return DMPC_ERR_HIP;
+  // K is symmetric: the adjoint solve with the JVP right-hand side returns dw
+  return run(plan, -1, false, data, nullptr, rhs, out, grad, workspace, status, info, stream);
+}
+
 dmpc_status dmpc_solve_one(dmpc_plan* plan, int32_t index, const float* data, float* sol,
                            void* workspace, int32_t* status, int32_t* info, void* stream) {
   if (index < 0) return DMPC_ERR_INVALID_ARG;

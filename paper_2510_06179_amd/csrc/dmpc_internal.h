@@ -228,6 +228,10 @@ dmpc_status check_opts(const dmpc_opts* o);
 dmpc_status check_problem(const dmpc_problem& p, int64_t data_len, int64_t sol_len);
 bool choose_cfg(const dmpc_problem& p, int force_bt, LaunchCfg* c);
 int problem_flags(const dmpc_problem& p, int force_bt);   // ProbRec::flags under choose_cfg
+// Right-hand side of the JVP system for every record (dmpc_jvp.hip); 0 or -2.
+int launch_jvp_rhs(const ProbRec* recs, int count, const float* data, const float* tangent,
+                   const float* ws, float* rhs, void* stream);
+
 KArgs make_kargs(const dmpc_opts& o, const ProbRec* recs, const float* data, float* sol, void* ws,
                  const float* dl, float* adj, float* grad, int32_t* status, int32_t* info);
 

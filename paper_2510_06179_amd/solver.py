@@ -97,6 +97,21 @@ class BatchSolver:
                                                 _stream(stream)), "dmpc_solve_backward")
         return adj, grad
 
+    def solve_jvp(self, tangent, data=None, out=None, rhs=None, grad=None, stream=None):
+        """dmpc_solve_jvp: derivative of the last QP's (x, u, lambda) along
+        ``tangent`` (laid out like the data arena).  Returns the arena of
+        (dx, du, dlambda), laid out like the solution arena."""
+        data = self.data if data is None else data
+        out = torch.zeros_like(self.sol) if out is None else out
+        rhs = torch.empty_like(self.sol) if rhs is None else rhs
+        grad = torch.empty_like(data) if grad is None else grad
+        tan = tangent.contiguous()
+        _lib.check(self.lib.dmpc_solve_jvp(self.plan, _ptr(data), _ptr(tan), _ptr(rhs),
+                                           _ptr(out), _ptr(grad), _ptr(self.workspace),
+                                           _ptr(self.status), _ptr(self.info),
+                                           _stream(stream)), "dmpc_solve_jvp")
+        return out
+
     def solve_backward_one(self, index, dl_dsol, data=None, adj=None, grad=None, stream=None):
         data = self.data if data is None else data
         _lib.check(self.lib.dmpc_solve_backward_one(
