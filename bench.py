@@ -135,7 +135,8 @@ def extra_workloads(steps=5, warmup=1):
     """Throughput of the other two batch workloads, fwd+bwd per step: the
     bicycle differentiation batch (512 OCPs, nx=8, nu=2, T=64, 10 SQP
     iterations, softplus cost weights) and the uneven LTV batch (4096 OCPs,
-    T in {16..128}, nx in {4..16}, nu in {2,4}, 8 SQP iterations)."""
+    T in {16..128}, nx in {4..16}, nu in {2,4}, 8 SQP iterations); and the
+    forward-mode sensitivity: the cart-pole batch, fwd + one JVP per OCP."""
     import torch
     from paper_2510_06179_amd import batch
     from paper_2510_06179_amd.solver import BatchSolver
@@ -173,6 +174,42 @@ def extra_workloads(steps=5, warmup=1):
                      "pcg_capped": int(np.count_nonzero(status & 1)),
                      "launch_groups": len(s.describe())}
         s.close()
+    # forward-mode sensitivities: the benchmark's cart-pole batch, forward plus
+    # one JVP per problem (a seeded tangent of the cost data and x_s)
+    probs = W.cartpole_batch(0, batch=1024)
+    s = BatchSolver(probs, sqp_iters=10, pcg_tol=PCG_TOL, bwd_pcg_tol=PCG_TOL)
+    rng = np.random.default_rng(0)
+    tps = []
+    for p in probs:
+        q = dict(p)
+        for k in ("x0", "Qd", "q", "Rd", "r"):
+            q[k] = W.f32(rng.standard_normal(np.shape(p[k])))
+        q["params"] = np.zeros_like(np.asarray(p["params"]))
+        tps.append(q)
+    tan = torch.from_numpy(batch.pack(tps).data).to(s.device)
+    sol = s.sol0.clone()
+    jout = torch.zeros_like(sol)
+    rhs = torch.empty_like(sol)
+    grad = torch.empty_like(s.data)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    for i in range(warmup + steps):
+        e = ev[i - warmup] if i >= warmup else None
+        sol.copy_(s.sol0)
+        if e:
+            e[0].record()
+        s.solve(sol=sol)
+        if e:
+            e[1].record()
+        s.solve_jvp(tan, out=jout, rhs=rhs, grad=grad)
+        if e:
+            e[2].record()
+    torch.cuda.synchronize()
+    fwd = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    jv = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+    info = s.info.cpu().numpy()
+    out["cartpole_b1024_fwd_jvp"] = {"solves_per_s": len(probs) / ((fwd + jv) / 1e3), "fwd_ms": fwd,
+                                     "jvp_ms": jv, "jvp_pcg_iters_mean": float(info[:, 1].mean())}
+    s.close()
     return out
 
 
@@ -403,6 +440,11 @@ def main():
         "serving": serving,
         "solver": {"fwd_pcg_iters_mean": float(info[:, 0].mean()),
                    "bwd_pcg_iters_mean": float(info[:, 1].mean()),
+                   # per-problem PCG iterations per solve: p10, p50, p90, p99, max
+                   "fwd_pcg_iters_pct": [float(v) for v in
+                                         np.percentile(info[:, 0], [10, 50, 90, 99, 100])],
+                   "bwd_pcg_iters_pct": [float(v) for v in
+                                         np.percentile(info[:, 1], [10, 50, 90, 99, 100])],
                    "nonpd_or_nonfinite": bad, "fwd_pcg_capped": capped_f,
                    "bwd_pcg_capped": capped_b, "ls_fallback_last_iter": ls_fb},
     }
