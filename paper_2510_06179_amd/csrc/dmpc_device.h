@@ -2561,10 +2561,15 @@ __device__ __forceinline__ int qp_solve(const Prob& P, const Lds& sh, RowRegs<NX
                                         ResidualFn residual) {
   const float etab = precond_norm<NX, SLOTS, REG, WAVE>(P, sh, Ph, g, redi);
   int its = 0;
+  float prev_r2 = 0.f;
   for (int k = 0; k <= steps; ++k) {
     float rr[SLOTS], d[SLOTS];
     const ResNorms nr = residual(hi, lo, rr);
     if (nr.r2 <= kkt_tol * kkt_tol * nr.rhs2) break;   // (k = 0: the warm start already meets it)
+    // a pass that did not halve the residual has reached the float32 floor
+    // of this system: further passes would not gain either
+    if (k > 0 && nr.r2 > 0.25f * prev_r2) break;
+    prev_r2 = nr.r2;
     if (k == 0)
       its += pcg<NX, SLOTS, REG, WAVE>(P, sh, S, Ph, rr, d, maxit, 0.f,
                                        fmaxf(tol * tol * etab, abs_tol), flags, redi, maxit_flag);
