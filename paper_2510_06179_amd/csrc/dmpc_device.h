@@ -608,9 +608,10 @@ __device__ __forceinline__ double cost_u1(const Prob& P, int t, int l, double u,
 }
 // directional derivative of the stage costs: grad c(xb)'(xq - xb)
 template <int NX>
-__device__ __forceinline__ double dcost_x(const Prob& P, int t, const float* xb, const float* xq) {
+__device__ __forceinline__ double dcost_x(const Prob& P, int t, const float* xb, const float* xq,
+                                          int cost_kind) {
   double s = 0.0;
-  if (P.cost == DMPC_COST_DIAG) {
+  if (cost_kind == DMPC_COST_DIAG) {
     const float* Qd = P.costp + t * NX;
     const float* q = P.costp + P.N * NX + t * NX;
 #pragma unroll
@@ -626,8 +627,9 @@ __device__ __forceinline__ double dcost_x(const Prob& P, int t, const float* xb,
   return s;
 }
 template <int NX>
-__device__ __forceinline__ double dcost_u1(const Prob& P, int t, int l, float ub, float uq) {
-  if (P.cost == DMPC_COST_DIAG) {
+__device__ __forceinline__ double dcost_u1(const Prob& P, int t, int l, float ub, float uq,
+                                           int cost_kind) {
+  if (cost_kind == DMPC_COST_DIAG) {
     const float* Rd = P.costp + 2 * P.N * NX + t * P.m;
     const float* r = Rd + P.TM;
     return ((double)Rd[l] * ub + (double)r[l]) * ((double)uq - (double)ub);
@@ -1669,6 +1671,7 @@ __device__ __forceinline__ ResNorms fwd_residual64_body(const ProbRec* rec, cons
 struct LsTaskArgs {
   const float *xbar, *xp, *ubar, *up;
   double *tc, *td;
+  double* dn;   // this thread's share of grad c(z)'(z+ - z), from its row-0 tasks
   int ntask, na;
 };
 template <int NX, int DYN, int COST>
@@ -1736,6 +1739,12 @@ __device__ __forceinline__ void ls_tasks(const Prob& P, const ModelPar& mp, cons
       const bool dyn_stage = tcl < T;
       cst[h] = c + (dyn_stage ? cu : 0.0);
       dfc[h] = dyn_stage ? d : 0.0;
+      // row 0 (the current point): the directional derivative of its costs
+      double g = dcost_x<NX>(P, tcl, a.xbar + tcl * NX, a.xp + tcl * NX, COST);
+      double gu = 0.0;
+      for (int l = 0; l < m; ++l) gu += dcost_u1<NX>(P, tn, l, ub[l], uq[l], COST);
+      g += dyn_stage ? gu : 0.0;
+      *a.dn += (live && aic == 0) ? g : 0.0;
     }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -1813,14 +1822,9 @@ __device__ __forceinline__ LsResult fwd_recover_ls_body(const ProbRec* rec, cons
   double* tc = (double*)(bulk_base(smem, P) + C.ls);
   double* td = tc + (kMaxAlphas + 1) * N;
   double* res = td + (kMaxAlphas + 1) * N;
-  double dn = 0.0;   // directional derivative of the cost at the current point
-  for (int t = tid; t < N; t += BT) {
-    dn += dcost_x<NX>(P, t, xbar + t * NX, xp + t * NX);
-    if (t < T)
-      for (int l = 0; l < m; ++l) dn += dcost_u1<NX>(P, t, l, ubar[t * m + l], up[t * m + l]);
-  }
   const ModelPar mp = load_par(P);
-  const LsTaskArgs ta{xbar, xp, ubar, up, tc, td, ntask, na};
+  double dn = 0.0;   // directional derivative of the cost at the current point (row 0 tasks)
+  const LsTaskArgs ta{xbar, xp, ubar, up, tc, td, &dn, ntask, na};
   // (the cart-pole has nx = 4 and the bicycle nx = 8: other pairs are refused
   // when the problem is validated)
   if (P.dyn == DMPC_DYN_LTV) {
