@@ -757,7 +757,8 @@ struct BicycleStepF {
 // QP data (Eq. QPmatrices) at the iterate held in LDS
 // ===========================================================================
 template <int NX>
-__device__ __forceinline__ void form_qp(const Prob& P, const float* xbar, const float* ubar) {
+__device__ __forceinline__ void form_qp(const Prob& P, const float* xbar, const float* ubar,
+                                        bool first) {
   const int tid = threadIdx.x, BT = blockDim.x;
   float* W = P.Wq;
   float* Qd = W + P.L.Qd;
@@ -770,6 +771,15 @@ __device__ __forceinline__ void form_qp(const Prob& P, const float* xbar, const 
   double* iRd = (double*)(W + P.L.iRd);
   // cost Hessians projected onto {H >= eps I} and linear terms
   // q = grad c(xb) - Q_proj xb  (written so that q = q_raw exactly when no clamp)
+  if (P.cost == DMPC_COST_DIAG && !first) {
+    // diagonal costs: the Hessians (and their reciprocals) do not depend on
+    // the iterate and stay from the first SQP iteration; only the linear
+    // terms of clamped entries do
+    for (int idx = tid; idx < P.R; idx += BT)
+      q[idx] = P.costp[P.R + idx] + (P.costp[idx] - Qd[idx]) * xbar[idx];
+    for (int idx = tid; idx < P.TM; idx += BT)
+      r[idx] = P.costp[2 * P.R + P.TM + idx] + (P.costp[2 * P.R + idx] - Rd[idx]) * ubar[idx];
+  } else {
   for (int idx = tid; idx < P.R; idx += BT) {
     const int t = idx / NX, i = idx - t * NX;
     float h, qq;
@@ -801,6 +811,7 @@ __device__ __forceinline__ void form_qp(const Prob& P, const float* xbar, const 
     iR[idx] = 1.f / hp;
     iRd[idx] = 1.0 / (double)hp;
     r[idx] = rr + (h - hp) * ubar[idx];
+  }
   }
   // dynamics Jacobians for nonlinear models, one thread per stage
   if (P.dyn != DMPC_DYN_LTV) {
@@ -1524,12 +1535,13 @@ __device__ __noinline__ void fwd_begin(const ProbRec* rec, const float* data, co
 // (Eq. shurcomplement) and preconditioner rows (Eq. S_Phiinv) into the
 // workspace.  Returns non-zero (in every thread) on a non-positive pivot.
 template <int NX>
-__device__ __forceinline__ int fwd_blocks_body(const ProbRec* rec, const float* data, float* ws) {
+__device__ __forceinline__ int fwd_blocks_body(const ProbRec* rec, const float* data, float* ws,
+                                               int first) {
   extern __shared__ float smem[];
   const int tid = threadIdx.x, BT = blockDim.x;
   const Prob P = make_prob<NX>(*rec, data, ws);
   const Carve C = carve_of<NX>(P);
-  form_qp<NX>(P, bulk_base(smem, P) + C.xbar, bulk_base(smem, P) + C.ubar);
+  form_qp<NX>(P, bulk_base(smem, P) + C.xbar, bulk_base(smem, P) + C.ubar, first);
   __syncthreads();
   float* blk = P.W + P.L.blk;
   float* gv = P.W + P.L.g;
@@ -1549,11 +1561,12 @@ __device__ __forceinline__ int fwd_blocks_body(const ProbRec* rec, const float* 
 // QP data at the iterate (Eq. QPmatrices) only (the wave-block kernels
 // assemble the rows in registers).
 template <int NX>
-__device__ __forceinline__ void fwd_form_body(const ProbRec* rec, const float* data, float* ws) {
+__device__ __forceinline__ void fwd_form_body(const ProbRec* rec, const float* data, float* ws,
+                                              int first) {
   extern __shared__ float smem[];
   const Prob P = make_prob<NX>(*rec, data, ws);
   const Carve C = carve_of<NX>(P);
-  form_qp<NX>(P, bulk_base(smem, P) + C.xbar, bulk_base(smem, P) + C.ubar);
+  form_qp<NX>(P, bulk_base(smem, P) + C.xbar, bulk_base(smem, P) + C.ubar, first);
   __syncthreads();
 }
 
@@ -2596,12 +2609,14 @@ __device__ __forceinline__ int qp_solve(const Prob& P, const Lds& sh, RowRegs<NX
 // callee-saved registers per call through scratch, and at nx <= 4 the inlined
 // kernels still fit their registers without spills.
 template <int NX>
-__device__ __noinline__ int fwd_blocks_call(const ProbRec* rec, const float* data, float* ws) {
-  return fwd_blocks_body<NX>(rec, data, ws);
+__device__ __noinline__ int fwd_blocks_call(const ProbRec* rec, const float* data, float* ws,
+                                            int first) {
+  return fwd_blocks_body<NX>(rec, data, ws, first);
 }
 template <int NX>
-__device__ __noinline__ void fwd_form_call(const ProbRec* rec, const float* data, float* ws) {
-  fwd_form_body<NX>(rec, data, ws);
+__device__ __noinline__ void fwd_form_call(const ProbRec* rec, const float* data, float* ws,
+                                           int first) {
+  fwd_form_body<NX>(rec, data, ws, first);
 }
 template <int NX>
 __device__ __noinline__ LsResult fwd_recover_ls_call(const ProbRec* rec, const float* data, float* ws,
@@ -2631,14 +2646,16 @@ __device__ __forceinline__ ResNorms bwd_residual64(const ProbRec* rec, const flo
   return bwd_residual64_call<NX>(rec, data, ws, dl);
 }
 template <int NX>
-__device__ __forceinline__ int fwd_blocks(const ProbRec* rec, const float* data, float* ws) {
-  if constexpr (NX <= 4) return fwd_blocks_body<NX>(rec, data, ws);
-  return fwd_blocks_call<NX>(rec, data, ws);
+__device__ __forceinline__ int fwd_blocks(const ProbRec* rec, const float* data, float* ws,
+                                          int first) {
+  if constexpr (NX <= 4) return fwd_blocks_body<NX>(rec, data, ws, first);
+  return fwd_blocks_call<NX>(rec, data, ws, first);
 }
 template <int NX>
-__device__ __forceinline__ void fwd_form(const ProbRec* rec, const float* data, float* ws) {
-  if constexpr (NX <= 4) fwd_form_body<NX>(rec, data, ws);
-  else fwd_form_call<NX>(rec, data, ws);
+__device__ __forceinline__ void fwd_form(const ProbRec* rec, const float* data, float* ws,
+                                         int first) {
+  if constexpr (NX <= 4) fwd_form_body<NX>(rec, data, ws, first);
+  else fwd_form_call<NX>(rec, data, ws, first);
 }
 template <int NX>
 __device__ __forceinline__ LsResult fwd_recover_ls(const ProbRec* rec, const float* data, float* ws,
@@ -2712,10 +2729,10 @@ __global__ __launch_bounds__(MAXBT) void forward_kernel(KArgs a) {
       RowRegs<NX, SLOTS, REG> S, Ph;
       float g[SLOTS];
       if constexpr (WAVE) {
-        fwd_form<NX>(rec, a.data, a.ws);
+        fwd_form<NX>(rec, a.data, a.ws, k == 0);
         if (wave_blocks<NX, SLOTS>(P, S, Ph, g, k == a.sqp_iters - 1)) flags |= DMPC_PROB_NONPD;
       } else {
-        if (fwd_blocks<NX>(rec, a.data, a.ws)) flags |= DMPC_PROB_NONPD;
+        if (fwd_blocks<NX>(rec, a.data, a.ws, k == 0)) flags |= DMPC_PROB_NONPD;
         load_rows<NX, SLOTS, REG, WAVE>(P, S, Ph, g);
       }
       pcg_total += qp_solve<NX, SLOTS, REG, WAVE>(
