@@ -251,7 +251,7 @@ dmpc_status dmpc_plan_describe(const dmpc_plan* plan, char* buf, size_t len);
  * flight; its later requests wait and run in submission order.  A result does
  * not depend on which other requests share its group.  Sessions too large for
  * a workgroup's LDS are "heavy": their requests form groups of their own, and
- * at most max(1, max_inflight / 4) heavy groups run at once, so that they
+ * at most max(1, max_inflight / 2) heavy groups run at once, so that they
  * never hold up the other requests.
  *
  * Device memory is allocated in dmpc_server_create only: per-session stores

@@ -567,7 +567,7 @@ dmpc_status dmpc_server_create(const dmpc_server_config* cfg, dmpc_server** out)
     delete sv;
     return DMPC_ERR_NOMEM;
   }
-  sv->max_heavy = std::max(1, cfg->max_inflight / 4);
+  sv->max_heavy = std::max(1, cfg->max_inflight / 2);
   sv->sessions.resize(cfg->max_sessions);
   sv->slots.resize(cfg->max_inflight);
   for (int i = 0; i < cfg->max_inflight; ++i) {

@@ -233,8 +233,8 @@ def test_destroy_with_pending_requests():
 
 def test_heavy_sessions_run_in_groups_of_their_own():
     # nx=32, T=256 problems do not fit a workgroup's LDS: their requests never
-    # share a group with the others, and at most one heavy group (4 shares /
-    # 4) runs at a time
+    # share a group with the others, and at most two heavy groups (4 shares /
+    # 2) run at a time
     rng = np.random.default_rng(9)
     probs = [W.ltv_problem(rng, 256, 32, 8) if k % 4 == 0 else W.ltv_problem(rng, 32, 4, 2)
              for k in range(12)]
@@ -255,9 +255,10 @@ def test_heavy_sessions_run_in_groups_of_their_own():
             if kinds == {True}:
                 hg.append(g)
         assert hg and len(hg) < len(trace)
-        hg.sort(key=lambda g: g["t_launch"])
-        for a, b in zip(hg, hg[1:]):
-            assert b["t_launch"] >= a["t_done"]
+        # heavy groups in flight at every launch of one: at most 2
+        for g in hg:
+            live = [h for h in hg if h["t_launch"] <= g["t_launch"] < h["t_done"]]
+            assert len(live) <= 2, (g, live)
         st = srv.stats()
         assert st["heavy_completed"] == sum(heavy.values())
         assert st["completed"] == len(seq)
