@@ -334,7 +334,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); "
-              "problems are independent, see DESIGN.md for how the batch shards", file=sys.stderr)
+              "the problems are independent, so a batch would shard across GPUs by problems "
+              "with no exchange in either pass", file=sys.stderr)
         sys.exit(2)
     if args.traffic_reference:
         traffic_reference()
