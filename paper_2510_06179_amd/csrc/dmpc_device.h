@@ -911,7 +911,7 @@ __device__ __forceinline__ void schur_row(const Prob& P, int t, int i, R* S, R& 
   }
 }
 
-// Right-hand side of the adjoint Schur system (Alg. backward line 1 with
+// Right-hand side of the adjoint Schur system (the first step of Alg. backward, with
 // (-b, d) <- (dl/dz, dl/dlambda)):  g~ = H G^-1 dl/dz - dl/dlambda, row (t, i).
 template <int NX, typename R>
 __device__ __forceinline__ R adjoint_rhs_row(const Prob& P, int t, int i, const float* dlx,
@@ -1393,7 +1393,7 @@ __device__ __forceinline__ int pcg(const Prob& P, const Lds& sh, RowRegs<NX, SLO
                                    int& flags, int& redi, int maxit_flag) {
   const int nwv = (blockDim.x + 63) >> 6;
   float r[SLOTS], p[SLOTS], z[SLOTS], y[SLOTS];
-  // r = rhs (line 1 with d = 0), r~ = Phi^-1 r (2), p = r~ (3), eta = r'r~ (4)
+  // initial residual r = rhs (d = 0), r~ = Phi^-1 r, p = r~, eta = r'r~
 #pragma unroll
   for (int s = 0; s < SLOTS; ++s) {
     r[s] = rhs[s];
@@ -1414,7 +1414,7 @@ __device__ __forceinline__ int pcg(const Prob& P, const Lds& sh, RowRegs<NX, SLO
     return 0;
   }
   while (it < maxit && eta > thresh) {
-    // y = S^ p (line 6), v = p'y (7), alpha = eta / v (8)
+    // y = S^ p, v = p'y, alpha = eta / v
     apply_rows<NX, SLOTS, REG, WAVE, false>(P, sh.w0, S, p, y);
     part = 0.f;
 #pragma unroll
@@ -1427,20 +1427,20 @@ __device__ __forceinline__ int pcg(const Prob& P, const Lds& sh, RowRegs<NX, SLO
     // (alpha and beta with the hardware reciprocal: within about one ulp of
     // the quotient, and off the latency-bound critical path of a division)
     const float alpha = eta * __builtin_amdgcn_rcpf(v);
-    // d += alpha p (9), r -= alpha y (10)
+    // d += alpha p, r -= alpha y
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
       d[s] = fmaf(alpha, p[s], d[s]);
       r[s] = fmaf(-alpha, y[s], r[s]);
     }
-    // r~ = Phi^-1 r (11), eta' = r'r~ (12)
+    // r~ = Phi^-1 r, eta' = r'r~
     apply_rows<NX, SLOTS, REG, WAVE, true>(P, sh.w1, Ph, r, z);
     part = 0.f;
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) part = fmaf(r[s], z[s], part);
     const float etan = pcg_sum<WAVE>(part, sh, redi, nwv);
     ++it;
-    // beta (13), p = r~ + beta p (14), eta = eta' (15); (p is not used
+    // beta, p = r~ + beta p, eta = eta'; (p is not used
     // after a non-finite eta', so it is updated before that exit)
     const float beta = etan * __builtin_amdgcn_rcpf(eta);
 #pragma unroll
@@ -2391,7 +2391,7 @@ __device__ __forceinline__ bool wave_blocks(const Prob& P, RowRegs<NX, SLOTS, tr
   return __ballot(nonpd ? 1 : 0) != 0;
 }
 
-// z~ = G^-1 (dl/dz - H' lambda~) (Alg. backward line 3, in double), then the
+// z~ = G^-1 (dl/dz - H' lambda~) (the recovery step of Alg. backward, in double), then the
 // VJP of Eq. loss_gradient, -dF/dtheta' [z~; lambda~], laid out like the data
 // arena.  lambda~ from the window w0.
 template <int NX>
