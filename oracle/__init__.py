@@ -20,6 +20,9 @@ What it computes, each step citing the paper's passage it follows:
                   Eq. ocp:backward, Alg. backward) through the same dense KKT
                   matrix, expressed as cotangents of the QP data and chained to
                   the cost parameters by complex-step differentiation.
+* ``exact``    -- the exact-Hessian (Newton) variant of the KKT system and
+                  its gradient of the fully converged solution map (Sec. 3.4,
+                  "Exact SQP vs iLQR"); reported beside Gauss-Newton, never gated.
 * ``models``/``costs`` -- the dynamics and costs of the benchmark problems,
                   written so that complex arguments propagate (complex-step
                   Jacobians, Squire & Trapp 1998).
@@ -31,4 +34,4 @@ QPmatrices), so every KKT block is exactly the paper's.
 
 Parity status per function is listed in each module header.
 """
-from . import models, costs, qp, sqp, backward  # noqa: F401
+from . import models, costs, qp, sqp, backward, exact  # noqa: F401

@@ -20,17 +20,21 @@
                         dense KKT builders at theta +- s v divided by 2 s.
 * ``vjp``            -- cotangents of the problem's own inputs: x_s, the cost
                         parameters (through the QP cost data, by complex step
-                        for the softplus weights; with the PD-projection mask
-                        for diagonal costs), and for linear dynamics A, B, c
+                        for the softplus weights; for diagonal costs an entry
+                        clamped by the PD projection reaches the linear term
+                        only, q = Qd xbar + q_raw - Q_proj xbar), and for
+                        linear dynamics A, B, c
                         (the constraint's Jacobians are A+ = I, -A, -B and
                         C_t = c_t by definition of f_t).  The linearisation
                         point is held fixed: the backward is the VJP of the
                         final QP's solution map.
 
-Pinned (tests): central finite differences of the oracle's QP solution map,
-the envelope identity (dl/dz = G z + b gives z~ = 0, lam~ = -lam),
-dJ*/dx_s = -lam_0 on LQ problems, and the duality of the two modes:
-<g, JVP(v)> = <VJP(g), v> for random g and v.
+Pinned (tests): central finite differences of the oracle's QP solution map
+(also with cost entries below the PD floor, where the clamp moves the linear
+terms: a hand-worked instance gives d lam_0 / d Qd_0 = -xbar_0 exactly), the
+envelope identity (dl/dz = G z + b gives z~ = 0, lam~ = -lam), dJ*/dx_s =
+-lam_0 on LQ problems, and the duality of the two modes: <g, JVP(v)> =
+<VJP(g), v> for random g and v, with and without clamped entries.
 """
 from __future__ import annotations
 
@@ -115,12 +119,18 @@ def vjp(prob, xbar, ubar, qpd, sol, gx, gu, glam=None, h=1e-30):
     g = {"x0": np.array(cot["xs"])}
     cp = costs.cost_params(prob)
     if prob["cost"] == "diag":
-        # the cost parameters are the QP cost data; the projection clamps entries
+        # the cost parameters are the QP cost data, through the projection of
+        # Sec. 3.1: an entry at or above the floor is the Hessian entry itself;
+        # a clamped entry leaves the Hessian at the floor and moves the linear
+        # term q = Qd xbar + q_raw - Q_proj xbar by xbar (r likewise by ubar)
         Qd, Rd = np.asarray(cp["Qd"]), np.asarray(cp["Rd"])
-        g["Qd"] = np.array([np.diag(a) for a in cot["Q"]]) * (Qd >= qp.PD_EPS)
-        g["Rd"] = np.array([np.diag(a) for a in cot["R"]]) * (Rd >= qp.PD_EPS)
-        g["q"] = np.array(cot["q"])
-        g["r"] = np.array(cot["r"])
+        cq, cr = np.array(cot["q"]), np.array(cot["r"])
+        g["Qd"] = np.where(Qd >= qp.PD_EPS, np.array([np.diag(a) for a in cot["Q"]]),
+                           cq * np.asarray(xbar, np.float64))
+        g["Rd"] = np.where(Rd >= qp.PD_EPS, np.array([np.diag(a) for a in cot["R"]]),
+                           cr * np.asarray(ubar, np.float64))
+        g["q"] = cq
+        g["r"] = cr
     else:
         for key, val in cp.items():
             val = np.asarray(val, dtype=np.float64)
@@ -155,6 +165,20 @@ def _moved(prob, tangent, s):
     return out
 
 
+def _clamp_safe_step(prob, tangent, s):
+    """The largest step <= s along which no diagonal cost entry crosses the
+    PD floor (K and rhs are affine in the inputs on each side of it)."""
+    for k in ("Qd", "Rd"):
+        if k in tangent and prob["cost"] == "diag":
+            h = np.asarray(prob[k], np.float64)
+            v = np.abs(np.asarray(tangent[k], np.float64))
+            gap = np.abs(h - qp.PD_EPS)
+            moving = v > 0
+            if np.any(moving):
+                s = min(s, 0.5 * float(np.min(gap[moving] / v[moving])))
+    return s
+
+
 def jvp(prob, xbar, ubar, qpd, sol, tangent, s=1e-3):
     """(dx [N,nx], du [T,nu], dlam [N,nx]): derivative of the final QP's
     solution (x, u, lam) along `tangent`, linearisation point fixed.  Only
@@ -162,6 +186,7 @@ def jvp(prob, xbar, ubar, qpd, sol, tangent, s=1e-3):
     if prob["cost"] != "diag":
         raise ValueError("jvp: diagonal costs only")
     T, nx, nu = qpd["T"], qpd["nx"], qpd["nu"]
+    s = _clamp_safe_step(prob, tangent, s)
     Kp, rp, _ = qp.kkt(qp.qp_data(_moved(prob, tangent, s), xbar, ubar), _moved(prob, tangent, s)["x0"])
     Km, rm, _ = qp.kkt(qp.qp_data(_moved(prob, tangent, -s), xbar, ubar), _moved(prob, tangent, -s)["x0"])
     dK = (Kp - Km) / (2 * s)
