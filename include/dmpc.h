@@ -20,7 +20,7 @@
  *   - All floating point data is float32, row-major, stage-major.
  *   - The caller owns every buffer (arenas, workspace, status arrays).  The
  *     library allocates device memory only in dmpc_plan_create (the plan's
- *     descriptor table), never in a solve call.
+ *     descriptor table) and dmpc_server_create, never in a solve call.
  *   - Calls return a dmpc_status; they never throw.  Numeric trouble of a
  *     single problem is reported in its per-problem status word, not as a call
  *     failure.  Solve calls are asynchronous on the given stream.
@@ -53,7 +53,11 @@ enum {
   DMPC_PROB_NONPD = 2,            /* a Schur diagonal block had a non-positive pivot, or p'Sp <= 0 */
   DMPC_PROB_NONFINITE = 4,        /* NaN/Inf met in the iterate or in PCG scalars */
   DMPC_PROB_LS_FALLBACK = 8,      /* no step size passed the decrease test; the smallest was taken */
-  DMPC_PROB_BWD_PCG_MAXITER = 16  /* backward PCG hit its iteration cap */
+  DMPC_PROB_BWD_PCG_MAXITER = 16, /* backward PCG hit its iteration cap */
+  DMPC_PROB_KKT_UNMET = 32,       /* the last QP's refinement ended with its residual above
+                                     kkt_tol x its right-hand side (a pass no longer halved it:
+                                     the float32 floor of an ill-conditioned system) */
+  DMPC_PROB_BWD_KKT_UNMET = 64    /* the same for the backward pass's adjoint solve */
 };
 
 /* Dynamics x_{t+1} = phi_t(x_t, u_t) of a problem.  The data block at dyn_off holds:
@@ -124,11 +128,16 @@ typedef struct dmpc_opts {
   float kkt_tol;            /* refinement stops once ||residual||_2 <= kkt_tol * ||KKT
                                right-hand side||_2 (default 1e-6); a warm start that
                                already meets it is kept without a PCG pass */
+  int32_t graph;            /* 1 (default): a batched call replays a HIP graph of the
+                               plan's launch groups (built at the plan's first batched
+                               call, its kernel arguments updated when the buffers
+                               change); 0: the groups are launched one by one on side
+                               streams forked from and joined into the caller's stream */
 } dmpc_opts;
 
 /* Fills *o with the defaults: 1 SQP iteration, PCG tol 1e-6, up to three
  * refinement passes (tol 1e-1, KKT target 1e-6), candidates {1, 0.7, 0.3, 0.1, 0.01}
- * (App. A.3), eta = 0.4, INIT_GIVEN. Host only. */
+ * (App. A.3), eta = 0.4, INIT_GIVEN, graph replay on. Host only. */
 void dmpc_default_opts(dmpc_opts* o);
 
 typedef struct dmpc_handle dmpc_handle;

@@ -20,6 +20,7 @@ DYN_LTV, DYN_CARTPOLE, DYN_BICYCLE = 0, 1, 2
 COST_DIAG, COST_SOFTPLUS = 0, 1
 INIT_GIVEN, INIT_ROLLOUT = 0, 1
 PROB_PCG_MAXITER, PROB_NONPD, PROB_NONFINITE, PROB_LS_FALLBACK, PROB_BWD_PCG_MAXITER = 1, 2, 4, 8, 16
+PROB_KKT_UNMET, PROB_BWD_KKT_UNMET = 32, 64
 
 DYN_KIND = {"ltv": DYN_LTV, "cartpole": DYN_CARTPOLE, "bicycle": DYN_BICYCLE}
 COST_KIND = {"diag": COST_DIAG, "softplus": COST_SOFTPLUS}
@@ -66,7 +67,7 @@ class Opts(ctypes.Structure):
         ("bwd_warm_start", ctypes.c_int32), ("bwd_pcg_max_iter", ctypes.c_int32),
         ("bwd_pcg_tol", ctypes.c_float), ("block_threads", ctypes.c_int32),
         ("refine_steps", ctypes.c_int32), ("refine_tol", ctypes.c_float),
-        ("kkt_tol", ctypes.c_float),
+        ("kkt_tol", ctypes.c_float), ("graph", ctypes.c_int32),
     ]
 
 
@@ -193,7 +194,7 @@ def check(rc, what=""):
 def make_opts(sqp_iters=1, pcg_tol=1e-6, pcg_abs_tol=0.0, pcg_max_iter=0,
               alphas=(1.0, 0.7, 0.3, 0.1, 0.01), ls_eta=0.4, init="given",
               bwd_warm_start=False, bwd_pcg_tol=None, bwd_pcg_max_iter=0, block_threads=0,
-              refine_steps=3, refine_tol=1e-1, kkt_tol=1e-6):
+              refine_steps=3, refine_tol=1e-1, kkt_tol=1e-6, graph=True):
     o = Opts()
     load().dmpc_default_opts(ctypes.byref(o))
     o.sqp_iters = int(sqp_iters)
@@ -212,4 +213,5 @@ def make_opts(sqp_iters=1, pcg_tol=1e-6, pcg_abs_tol=0.0, pcg_max_iter=0,
     o.refine_steps = int(refine_steps)
     o.refine_tol = float(refine_tol)
     o.kkt_tol = float(kkt_tol)
+    o.graph = int(bool(graph))
     return o

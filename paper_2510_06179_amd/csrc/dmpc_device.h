@@ -857,7 +857,7 @@ __device__ __forceinline__ R rinv(const float* ih, const double* ihd, int idx) {
   }
 }
 
-template <int NX, typename R>
+template <int NX, typename R, bool SKIP_D = false>
 __device__ __forceinline__ void schur_row(const Prob& P, int t, int i, R* S, R& g) {
   const float* W = P.Wq;
   const float* iQ = W + P.L.iQ;
@@ -885,22 +885,28 @@ __device__ __forceinline__ void schur_row(const Prob& P, int t, int i, R* S, R& 
       gs += ai[j] * (R)q[tt * NX + j];
       S[j] = -ai[j];
     }
+    if constexpr (!SKIP_D) {
 #pragma unroll
-    for (int k = 0; k < NX; ++k) {
-      R acc = R(0);
+      for (int k = 0; k < NX; ++k) {
+        R acc = R(0);
 #pragma unroll
-      for (int j = 0; j < NX; ++j) acc += ai[j] * ldA<R>(P, a0 + k * NX + j);
-      S[NX + k] = acc;
+        for (int j = 0; j < NX; ++j) acc += ai[j] * ldA<R>(P, a0 + k * NX + j);
+        S[NX + k] = acc;
+      }
     }
     for (int l = 0; l < m; ++l) {
       const R bi = ldB<R>(P, b0 + i * m + l) * rinv<R>(iR, iRd, tt * m + l);
       gs += bi * (R)r[tt * m + l];
+      if constexpr (!SKIP_D) {
 #pragma unroll
-      for (int k = 0; k < NX; ++k) S[NX + k] += bi * ldB<R>(P, b0 + k * m + l);
+        for (int k = 0; k < NX; ++k) S[NX + k] += bi * ldB<R>(P, b0 + k * m + l);
+      }
     }
     const R dq = rinv<R>(iQ, iQd, t * NX + i);
+    if constexpr (!SKIP_D) {
 #pragma unroll
-    for (int k = 0; k < NX; ++k) S[NX + k] += (k == i) ? dq : R(0);
+      for (int k = 0; k < NX; ++k) S[NX + k] += (k == i) ? dq : R(0);
+    }
     g = -(ldc<R>(P, tt * NX + i) - gs + (R)q[t * NX + i] * dq);
   }
   if (t < P.T) {
@@ -909,6 +915,27 @@ __device__ __forceinline__ void schur_row(const Prob& P, int t, int i, R* S, R& 
 #pragma unroll
     for (int k = 0; k < NX; ++k) S[2 * NX + k] = -ldA<R>(P, a0 + k * NX + i) * d;
   }
+}
+
+// The right-hand side entry g (row (t, i)) of schur_row alone: for problems
+// whose QP matrices do not change between SQP iterations only the linear
+// terms (and with them g) move.
+template <int NX>
+__device__ __forceinline__ float schur_rhs_row(const Prob& P, int t, int i) {
+  const float* W = P.Wq;
+  const float* iQ = W + P.L.iQ;
+  const float* q = W + P.L.q;
+  const float* iR = W + P.L.iR;
+  const float* r = W + P.L.r;
+  const int m = P.m;
+  if (t == 0) return -(P.x0[i] + q[i] * iQ[i]);
+  const int tt = t - 1;
+  const int a0 = tt * NX * NX, b0 = tt * NX * m;
+  float gs = 0.f;
+#pragma unroll
+  for (int j = 0; j < NX; ++j) gs += (P.A[a0 + i * NX + j] * iQ[tt * NX + j]) * q[tt * NX + j];
+  for (int l = 0; l < m; ++l) gs += (P.B[b0 + i * m + l] * iR[tt * m + l]) * r[tt * m + l];
+  return -(P.c[tt * NX + i] - gs + q[t * NX + i] * iQ[t * NX + i]);
 }
 
 // Right-hand side of the adjoint Schur system (the first step of Alg. backward, with
@@ -1207,6 +1234,21 @@ __device__ __forceinline__ bool precond_rows(const Prob& P, float* piv) {
     }
     __syncthreads();
   }
+  if constexpr (NX >= 16) {
+    // the off-diagonal blocks come from the matrix cores (mfma_precond_blocks);
+    // here only the diagonal block and the zero blocks at both ends
+    for (int rho = tid; rho < P.R; rho += BT) {
+      const int t = rho / NX;
+      float* b = blk + blk_at<NX>(rho, 3 * NX);
+#pragma unroll
+      for (int j = 0; j < NX; ++j) {
+        b[NX + j] = Dinv[rho * NX + j];
+        if (t == 0) b[j] = 0.f;
+        if (t == P.T) b[2 * NX + j] = 0.f;
+      }
+    }
+    return nonpd;
+  }
   for (int rho = tid; rho < P.R; rho += BT) {
     const int t = rho / NX;
     const float* Dt = Dinv + rho * NX;   // row i of D_t^-1
@@ -1257,6 +1299,139 @@ __device__ __forceinline__ bool precond_rows(const Prob& P, float* piv) {
     }
   }
   return nonpd;
+}
+
+// ===========================================================================
+// Matrix-core assembly for nx >= 16 (Eq. shurcomplement, Eq. S_Phiinv)
+// ===========================================================================
+// The dense n x n x n contractions of the assembly -- the diagonal Schur
+// blocks D_{t+1} = chi_t = A_t Q_t^-1 A_t' + B_t R_t^-1 B_t' + Q_{t+1}^-1 and
+// the preconditioner's off-diagonal blocks
+//   L_t := -D_t^-1 E_{t,t-1} D_{t-1}^-1 = D_t^-1 (A_{t-1} Q_{t-1}^-1) D_{t-1}^-1
+// (and its transpose, the block -D_{t-1}^-1 E_{t-1,t} D_t^-1 of the row above)
+// -- run on v_mfma_f32_16x16x4_f32 in 16 x 16 tiles, one wave per stage.
+// Operand layout of one 16x16x4 step (lane l, q = l / 16, c = l % 16):
+// lane l supplies a = A[c][4s + q] and b = B[4s + q][c]; the accumulator
+// holds D[4q + r][c] in its register r.
+typedef float mfma_v4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ mfma_v4 mfma16(float a, float b, mfma_v4 acc) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+}
+
+// Per-wave staging tile for a change of operand layout (16 x 16 floats in
+// the pivot-row region, which the Gauss-Jordan inversion no longer needs):
+// element (row, col) at row * 16 + (col ^ row), so that the transposed
+// reads of a 16-lane group fall in distinct banks.
+__device__ __forceinline__ int stg_at(int row, int col) { return row * 16 + (col ^ row); }
+
+// Diagonal Schur blocks D_t, t = 1..T, into coefficients NX..2NX-1 of the
+// rows (D_0 = Q_0^-1 comes from the row pass).  chi_{t-1} = F G' + Q_t^-1
+// with G = [A_{t-1} B_{t-1}] and F = G diag(Q_{t-1}^-1, R_{t-1}^-1): tile
+// (I, J) sums over the NX + m columns of F and G in steps of four.
+template <int NX>
+__device__ __forceinline__ void mfma_diag_blocks(const Prob& P, float* blk) {
+  constexpr int TW = NX / 16;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, W = blockDim.x >> 6;
+  const int q = lane >> 4, c = lane & 15;
+  const float* iQ = P.Wq + P.L.iQ;
+  const float* iR = P.Wq + P.L.iR;
+  const int m = P.m;
+  for (int t = 1 + w; t < P.N; t += W) {
+    const int tt = t - 1;
+    const float* At = P.A + tt * NX * NX;
+    const float* Bt = P.B + tt * NX * m;
+#pragma unroll
+    for (int I = 0; I < TW; ++I) {
+#pragma unroll
+      for (int J = 0; J < TW; ++J) {
+        mfma_v4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < NX / 4; ++s) {
+          const int k = 4 * s + q;
+          const float sc = iQ[tt * NX + k];
+          acc = mfma16(At[(16 * I + c) * NX + k] * sc, At[(16 * J + c) * NX + k], acc);
+        }
+        for (int s = 0; 4 * s < m; ++s) {
+          const int k = 4 * s + q;
+          const bool ok = k < m;
+          const float g1 = ok ? Bt[(16 * I + c) * m + k] * iR[tt * m + k] : 0.f;
+          const float g2 = ok ? Bt[(16 * J + c) * m + k] : 0.f;
+          acc = mfma16(g1, g2, acc);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * I + 4 * q + r, col = 16 * J + c;
+          const float d = (row == col) ? iQ[t * NX + row] : 0.f;
+          blk[blk_at<NX>(t * NX + row, NX + col)] = acc[r] + d;
+        }
+      }
+    }
+  }
+}
+
+// Off-diagonal preconditioner blocks from the inverted diagonal blocks
+// (Dinv, row-major [N][NX][NX]): for t = 1..T, M = D_t^-1 A_{t-1}
+// Q_{t-1}^-1 tile by tile, staged through LDS into operand layout, then
+// L_t = M D_{t-1}^-1.  L_t fills coefficients 3NX..4NX-1 of the rows of
+// stage t and, transposed, coefficients 5NX..6NX-1 of the rows of stage t-1.
+// The stage loop has the same trip count in every wave (barriers inside).
+template <int NX>
+__device__ __forceinline__ void mfma_precond_blocks(const Prob& P, float* blk, const float* Dinv,
+                                                    float* stage_lds) {
+  constexpr int TW = NX / 16;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, W = blockDim.x >> 6;
+  const int q = lane >> 4, c = lane & 15;
+  const float* iQ = P.Wq + P.L.iQ;
+  float* stg = stage_lds + 256 * w;
+  for (int t0 = 1; t0 < P.N; t0 += W) {
+    const int t = t0 + w;
+    const bool act = t < P.N;
+    const int ts = act ? t : 1;   // idle waves compute a valid stage and store nothing
+    const float* Dt = Dinv + ts * NX * NX;
+    const float* Dp = Dinv + (ts - 1) * NX * NX;
+    const float* Ap = P.A + (ts - 1) * NX * NX;
+    const float* iQp = iQ + (ts - 1) * NX;
+#pragma unroll
+    for (int I = 0; I < TW; ++I) {
+      mfma_v4 accL[TW];
+#pragma unroll
+      for (int J = 0; J < TW; ++J) accL[J] = mfma_v4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int K = 0; K < TW; ++K) {
+        // tile (I, K) of M = D_t^-1 A_{t-1} Q_{t-1}^-1
+        mfma_v4 accM = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < NX / 4; ++s) {
+          const int k = 4 * s + q;
+          accM = mfma16(Dt[(16 * I + c) * NX + k], Ap[k * NX + 16 * K + c], accM);
+        }
+        const float sc = iQp[16 * K + c];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) stg[stg_at(4 * q + r, c)] = accM[r] * sc;
+        __syncthreads();
+        // L(I, J) += M(I, K) D_{t-1}^-1(K, J)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const float a = stg[stg_at(c, 4 * s + q)];
+#pragma unroll
+          for (int J = 0; J < TW; ++J)
+            accL[J] = mfma16(a, Dp[(16 * K + 4 * s + q) * NX + 16 * J + c], accL[J]);
+        }
+        __syncthreads();
+      }
+      if (act) {
+#pragma unroll
+        for (int J = 0; J < TW; ++J)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int a = 16 * I + 4 * q + r, b = 16 * J + c;
+            blk[blk_at<NX>(t * NX + a, 3 * NX + b)] = accL[J][r];
+            blk[blk_at<NX>((t - 1) * NX + b, 5 * NX + a)] = accL[J][r];
+          }
+      }
+    }
+  }
 }
 
 // ===========================================================================
@@ -1545,16 +1720,34 @@ __device__ __forceinline__ int fwd_blocks_body(const ProbRec* rec, const float* 
   __syncthreads();
   float* blk = P.W + P.L.blk;
   float* gv = P.W + P.L.g;
+  if (!first && P.dyn == DMPC_DYN_LTV && P.cost == DMPC_COST_DIAG) {
+    // linear dynamics and diagonal costs: the Schur and preconditioner blocks
+    // depend on A, B and the projected Hessians only, which do not change
+    // between SQP iterations; the rows of the first iteration stay, and only
+    // the right-hand side follows the linear terms
+    for (int rho = tid; rho < P.R; rho += BT) {
+      const int t = rho / NX, i = rho - t * NX;
+      gv[rho] = schur_rhs_row<NX>(P, t, i);
+    }
+    __syncthreads();
+    return 0;
+  }
+  // nx >= 16: the diagonal blocks of stages 1..T and the preconditioner's
+  // off-diagonal blocks are dense contractions, formed on the matrix cores
+  constexpr bool MX = NX >= 16;
   for (int rho = tid; rho < P.R; rho += BT) {
     const int t = rho / NX, i = rho - t * NX;
     float row[3 * NX], g;
-    schur_row<NX, float>(P, t, i, row, g);
+    schur_row<NX, float, MX>(P, t, i, row, g);
 #pragma unroll
-    for (int j = 0; j < 3 * NX; ++j) blk[blk_at<NX>(rho, j)] = row[j];
+    for (int j = 0; j < 3 * NX; ++j)
+      if (!MX || t == 0 || j < NX || j >= 2 * NX) blk[blk_at<NX>(rho, j)] = row[j];
     gv[rho] = g;
   }
+  if constexpr (MX) mfma_diag_blocks<NX>(P, blk);
   __syncthreads();
   const bool bad = precond_rows<NX>(P, smem + C.piv);
+  if constexpr (MX) mfma_precond_blocks<NX>(P, blk, P.W + P.L.Dinv, smem + C.piv);
   return __syncthreads_or(bad ? 1 : 0);
 }
 
@@ -2575,14 +2768,18 @@ __device__ __forceinline__ int qp_solve(const Prob& P, const Lds& sh, RowRegs<NX
                                         float (&hi)[SLOTS], float (&lo)[SLOTS], int steps,
                                         int maxit, float tol, float abs_tol, float ref_tol,
                                         float kkt_tol, int& flags, int& redi, int maxit_flag,
-                                        ResidualFn residual) {
+                                        int unmet_flag, ResidualFn residual) {
   const float etab = precond_norm<NX, SLOTS, REG, WAVE>(P, sh, Ph, g, redi);
   int its = 0;
   float prev_r2 = 0.f;
+  bool met = false;
   for (int k = 0; k <= steps; ++k) {
     float rr[SLOTS], d[SLOTS];
     const ResNorms nr = residual(hi, lo, rr);
-    if (nr.r2 <= kkt_tol * kkt_tol * nr.rhs2) break;   // (k = 0: the warm start already meets it)
+    if (nr.r2 <= kkt_tol * kkt_tol * nr.rhs2) {   // (k = 0: the warm start already meets it)
+      met = true;
+      break;
+    }
     // a pass that did not halve the residual has reached the float32 floor
     // of this system: further passes would not gain either
     if (k > 0 && nr.r2 > 0.25f * prev_r2) break;
@@ -2599,7 +2796,14 @@ __device__ __forceinline__ int qp_solve(const Prob& P, const Lds& sh, RowRegs<NX
       hi[s] = (float)v;
       lo[s] = (float)(v - (double)hi[s]);
     }
+    if (k == steps) {
+      // the passes ran out: one more residual tells whether the last met it
+      float rr2[SLOTS];
+      const ResNorms nl = residual(hi, lo, rr2);
+      met = nl.r2 <= kkt_tol * kkt_tol * nl.rhs2;
+    }
   }
+  if (!met) flags |= unmet_flag;
   return its;
 }
 
@@ -2738,6 +2942,7 @@ __global__ __launch_bounds__(MAXBT) void forward_kernel(KArgs a) {
       pcg_total += qp_solve<NX, SLOTS, REG, WAVE>(
           P, sh, S, Ph, g, lam, lo, a.refine_steps, maxit, a.pcg_tol, a.pcg_abs_tol, rtol,
           a.kkt_tol, flags, redi, DMPC_PROB_PCG_MAXITER,
+          k == a.sqp_iters - 1 ? DMPC_PROB_KKT_UNMET : 0,
           [&](const float (&h)[SLOTS], const float (&l)[SLOTS], float (&rr)[SLOTS]) {
             return residual_rows<NX, SLOTS, WAVE, false>(rec, a, P, sh, h, l, rr);
           });
@@ -2801,7 +3006,7 @@ __global__ __launch_bounds__(MAXBT) void backward_kernel(KArgs a) {
     const float rtol = a.refine_tol > 0.f ? a.refine_tol : a.bwd_tol;
     const int its = qp_solve<NX, SLOTS, REG, WAVE>(
         P, sh, S, Ph, g, lt, lo, a.refine_steps, maxit, a.bwd_tol, 0.f, rtol, a.kkt_tol, flags,
-        redi, DMPC_PROB_BWD_PCG_MAXITER,
+        redi, DMPC_PROB_BWD_PCG_MAXITER, DMPC_PROB_BWD_KKT_UNMET,
         [&](const float (&h)[SLOTS], const float (&l)[SLOTS], float (&rr)[SLOTS]) {
           return residual_rows<NX, SLOTS, WAVE, true>(rec, a, P, sh, h, l, rr);
         });

@@ -10,6 +10,7 @@
 #include <string>
 #include <cmath>
 #include <cstring>
+#include <cstdlib>
 #include <new>
 #include <vector>
 
@@ -22,17 +23,48 @@ struct dmpc_handle {
   int device;
 };
 
+
 struct Group {
   LaunchCfg cfg;
   int first, count;
-  double work;     // estimated cost: sum over its problems of (T+1) nx^2
+  double work;     // estimated duration (see group_estimate)
   int lane;        // side stream it runs on in a batched call
 };
 
 // Groups of one batched call run concurrently on up to kLanes side streams
 // (fork/join through events on the caller's stream), heaviest first onto the
-// least-loaded stream.  Four matches the hardware queues a process gets.
-constexpr int kLanes = 4;
+// least-loaded stream.  Four matches the hardware queues a process gets by
+// default; DMPC_LANES (1..kLanes) in the environment at plan creation sets
+// the number for processes given more queues.
+constexpr int kLanes = 16;
+constexpr int kDefaultLanes = 4;
+
+// Estimated duration of one problem, for ordering and balancing the groups:
+// a workgroup per problem, so a group lasts about as long as its slowest
+// problem (once per wave of workgroups over the chip).  Per PCG iteration a
+// thread does slots rows of 6 nx coefficients, rows read from the workspace
+// cost about four times as much as rows in registers, and the iteration
+// count grows with the state size and slowly with the horizon.
+static double problem_estimate(const dmpc_problem& p, const LaunchCfg& c) {
+  const double row_work = (double)c.slots * 6.0 * p.nx + 40.0;
+  const double mode = c.reg == 0 ? 4.0 : 1.0;
+  const double iters = 10.0 * p.nx * std::cbrt((double)(p.T + 1));
+  return row_work * mode * iters;
+}
+
+// A HIP graph of one pass (forward or backward) over every launch group of a
+// plan: one kernel node per group, chained per side-stream lane as the
+// fork/join launches run them (so at most kLanes groups run at once), built
+// at the plan's first batched call of that pass.  Replays reuse it; when the
+// caller's buffers differ from the last call's, the nodes' kernel arguments
+// are updated in the instantiated graph.
+struct PassGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<hipGraphNode_t> nodes;   // one per group
+  KArgs key;                           // the arguments of the last call
+  bool failed = false;                 // building failed: launch directly
+};
 
 struct dmpc_plan {
   dmpc_handle* h;
@@ -48,6 +80,7 @@ struct dmpc_plan {
   hipStream_t side[kLanes] = {};
   hipEvent_t joined[kLanes] = {};
   hipEvent_t fork = nullptr;
+  PassGraph pass_graph[2];             // [0] backward, [1] forward
 };
 
 namespace dmpc {
@@ -83,6 +116,7 @@ dmpc_status check_opts(const dmpc_opts* o) {
   if (o->refine_steps < 0 || o->refine_steps > 8 || !finite_nonneg(o->refine_tol) ||
       !finite_nonneg(o->kkt_tol))
     return DMPC_ERR_INVALID_ARG;
+  if (o->graph != 0 && o->graph != 1) return DMPC_ERR_INVALID_ARG;
   return DMPC_OK;
 }
 
@@ -140,6 +174,7 @@ struct Variant {
 const Variant kVariants[] = {
     {1, 64, 1},  {2, 64, 1},  {4, 64, 1},  {8, 64, 1},  {1, 128, 1}, {2, 128, 1}, {4, 128, 1},
     {8, 128, 1}, {1, 256, 1}, {2, 256, 1}, {4, 256, 1}, {1, 512, 1}, {2, 512, 1}, {1, 1024, 1},
+    {3, 512, 1}, {2, 1024, 1},
     {4, 256, 0}, {8, 256, 0}, {8, 512, 0}, {2, 1024, 0}, {4, 1024, 0}, {8, 1024, 0}, {12, 1024, 0},
     {2, 64, 2},  {4, 64, 2},  {8, 64, 2},
 };
@@ -258,6 +293,7 @@ void dmpc_default_opts(dmpc_opts* o) {
   o->refine_steps = 3;
   o->refine_tol = 1e-1f;
   o->kkt_tol = 1e-6f;
+  o->graph = 1;
 }
 
 const char* dmpc_status_string(dmpc_status s) {
@@ -473,11 +509,13 @@ dmpc_status dmpc_plan_create(dmpc_handle* h, const dmpc_problem* problems, int32
         g.cfg.lds_bytes,
         (size_t)lds_floats(p.T, p.nx, p.nu, g.cfg.bt, g.cfg.slots, r.flags, lin_floats_of(p)) *
             sizeof(float));
-    g.work += (double)(p.T + 1) * p.nx * p.nx;
+    g.work = std::max(g.work, problem_estimate(p, cfg[i]));
     pl->grp[k] = (int)pl->groups.size() - 1;
   }
   pl->ws_bytes = (size_t)ws_off * sizeof(float);
   for (Group& g : pl->groups) {
+    // one more slowest-problem duration per extra wave of workgroups
+    g.work *= (double)((g.count + kComputeUnits - 1) / kComputeUnits);
     g.cfg.grid = g.count;
     if (g.cfg.lds_bytes > (size_t)kLdsBytes ||
         !kernel_available(g.cfg.nx, g.cfg.slots, g.cfg.maxbt, g.cfg.reg)) {
@@ -504,14 +542,22 @@ dmpc_status dmpc_plan_create(dmpc_handle* h, const dmpc_problem* problems, int32
       return DMPC_ERR_HIP;
     }
     if (pl->groups.size() > 1) {
-      // longest-processing-time assignment of groups to side streams
-      const int lanes = std::min<int>(kLanes, (int)pl->groups.size());
+      // longest-processing-time assignment of groups to side streams; the
+      // groups are kept heaviest first, which is also their launch order
+      int want = kDefaultLanes;
+      if (const char* e = std::getenv("DMPC_LANES")) {
+        const int v = std::atoi(e);
+        if (v >= 1 && v <= kLanes) want = v;
+      }
+      const int lanes = std::min<int>(want, (int)pl->groups.size());
+      std::stable_sort(pl->groups.begin(), pl->groups.end(),
+                       [](const Group& a, const Group& b) { return a.work > b.work; });
+      for (size_t g = 0; g < pl->groups.size(); ++g)
+        for (int k = pl->groups[g].first; k < pl->groups[g].first + pl->groups[g].count; ++k)
+          pl->grp[k] = (int)g;
       std::vector<int> gi(pl->groups.size());
       for (size_t g = 0; g < gi.size(); ++g) gi[g] = (int)g;
-      std::stable_sort(gi.begin(), gi.end(), [&](int a, int b) {
-        return pl->groups[a].work > pl->groups[b].work;
-      });
-      double load[kLanes] = {0, 0, 0, 0};
+      double load[kLanes] = {};
       for (int g : gi) {
         int best = 0;
         for (int l = 1; l < lanes; ++l)
@@ -571,6 +617,10 @@ dmpc_status dmpc_plan_describe(const dmpc_plan* plan, char* buf, size_t len) {
 
 dmpc_status dmpc_plan_destroy(dmpc_plan* plan) {
   if (!plan) return DMPC_OK;
+  for (PassGraph& g : plan->pass_graph) {
+    if (g.exec) hipGraphExecDestroy(g.exec);
+    if (g.graph) hipGraphDestroy(g.graph);
+  }
   for (int l = 0; l < kLanes; ++l) {
     if (plan->side[l]) hipStreamDestroy(plan->side[l]);
     if (plan->joined[l]) hipEventDestroy(plan->joined[l]);
@@ -579,6 +629,75 @@ dmpc_status dmpc_plan_destroy(dmpc_plan* plan) {
   if (plan->d_recs) hipFree(plan->d_recs);
   delete plan;
   return DMPC_OK;
+}
+
+static bool same_buffers(const KArgs& a, const KArgs& b) {
+  return a.data == b.data && a.sol == b.sol && a.ws == b.ws && a.dl == b.dl && a.adj == b.adj &&
+         a.grad == b.grad && a.status == b.status && a.info == b.info;
+}
+
+static hipKernelNodeParams node_params(const Group& g, const void* fn, KArgs* a) {
+  hipKernelNodeParams p;
+  std::memset(&p, 0, sizeof(p));
+  p.func = const_cast<void*>(fn);
+  p.gridDim = dim3(g.cfg.grid);
+  p.blockDim = dim3(g.cfg.bt);
+  p.sharedMemBytes = (unsigned)g.cfg.lds_bytes;
+  static thread_local void* args[1];
+  args[0] = a;
+  p.kernelParams = args;
+  p.extra = nullptr;
+  return p;
+}
+
+// Replays the pass's graph on `stream` (building or updating it first).
+// Returns 0, or -2 when a HIP call failed; -3 when the graph cannot be built
+// (the caller then launches the groups directly).
+static int run_graph(dmpc_plan* pl, bool fwd, const KArgs& a, hipStream_t stream) {
+  PassGraph& pg = pl->pass_graph[fwd ? 1 : 0];
+  if (pg.failed) return -3;
+  const size_t ng = pl->groups.size();
+  if (!pg.exec) {
+    if (hipGraphCreate(&pg.graph, 0) != hipSuccess) {
+      pg.failed = true;
+      return -3;
+    }
+    pg.nodes.assign(ng, nullptr);
+    std::vector<hipGraphNode_t> last(kLanes, nullptr);
+    for (size_t i = 0; i < ng; ++i) {
+      const Group& g = pl->groups[i];
+      const void* fn = kernel_function(g.cfg, fwd);
+      KArgs ai = a;
+      ai.first = g.first;
+      ai.count = g.count;
+      const int lane = pl->lanes ? g.lane : 0;
+      hipKernelNodeParams p = node_params(g, fn, &ai);
+      hipGraphNode_t dep = last[lane];
+      if (!fn || hipGraphAddKernelNode(&pg.nodes[i], pg.graph, dep ? &dep : nullptr, dep ? 1 : 0,
+                                       &p) != hipSuccess) {
+        pg.failed = true;
+        return -3;
+      }
+      last[lane] = pg.nodes[i];
+    }
+    if (hipGraphInstantiate(&pg.exec, pg.graph, nullptr, nullptr, 0) != hipSuccess) {
+      pg.exec = nullptr;
+      pg.failed = true;
+      return -3;
+    }
+    pg.key = a;
+  } else if (!same_buffers(a, pg.key)) {
+    for (size_t i = 0; i < ng; ++i) {
+      const Group& g = pl->groups[i];
+      KArgs ai = a;
+      ai.first = g.first;
+      ai.count = g.count;
+      hipKernelNodeParams p = node_params(g, kernel_function(g.cfg, fwd), &ai);
+      if (hipGraphExecKernelNodeSetParams(pg.exec, pg.nodes[i], &p) != hipSuccess) return -2;
+    }
+    pg.key = a;
+  }
+  return hipGraphLaunch(pg.exec, stream) == hipSuccess ? 0 : -2;
 }
 
 static dmpc_status run(dmpc_plan* pl, int index, bool fwd, const float* data, float* sol,
@@ -595,6 +714,14 @@ static dmpc_status run(dmpc_plan* pl, int index, bool fwd, const float* data, fl
   if (prev != pl->h->device && hipSetDevice(pl->h->device) != hipSuccess) return DMPC_ERR_HIP;
   KArgs a = make_args(pl, data, sol, ws, dl, adj, grad, status, info);
   int rc = 0;
+  if (index < 0 && pl->opts.graph) {
+    rc = run_graph(pl, fwd, a, (hipStream_t)stream);
+    if (rc != -3) {
+      if (prev != pl->h->device) hipSetDevice(prev);
+      return rc == 0 ? DMPC_OK : DMPC_ERR_HIP;
+    }
+    rc = 0;   // the graph could not be built: launch the groups directly
+  }
   if (index >= 0) {
     const int k = pl->pos[index];
     LaunchCfg c = pl->groups[pl->grp[k]].cfg;

@@ -250,5 +250,9 @@ int launch_seg_copy(const Seg* segs, int n, void* stream);
 bool kernel_available(int nx, int slots, int maxbt, int reg);
 int launch_forward(const LaunchCfg& cfg, const KArgs& a, void* stream);
 int launch_backward(const LaunchCfg& cfg, const KArgs& a, void* stream);
+// The kernel of a launch group (with its dynamic-LDS limit raised as the
+// launch functions do), for graph nodes; nullptr if not instantiated or the
+// limit cannot be set.
+const void* kernel_function(const LaunchCfg& cfg, bool fwd);
 
 }  // namespace dmpc

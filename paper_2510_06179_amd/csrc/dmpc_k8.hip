@@ -12,7 +12,7 @@ static const KEntry kEntries[] = {
     DMPC_K(8, 1, 64, 1), DMPC_K(8, 2, 64, 1), DMPC_K(8, 4, 64, 1),
     DMPC_K(8, 1, 128, 1), DMPC_K(8, 2, 128, 1), DMPC_K(8, 4, 128, 1),
     DMPC_K(8, 1, 256, 1), DMPC_K(8, 2, 256, 1), DMPC_K(8, 4, 256, 1), DMPC_K(8, 1, 512, 1), DMPC_K(8, 2, 512, 1),
-    DMPC_K(8, 1, 1024, 1),
+    DMPC_K(8, 1, 1024, 1), DMPC_K(8, 3, 512, 1), DMPC_K(8, 2, 1024, 1),
     DMPC_K(8, 4, 256, 0), DMPC_K(8, 8, 256, 0), DMPC_K(8, 8, 512, 0),
     DMPC_K(8, 8, 64, 2),
 };

@@ -51,6 +51,17 @@ static int launch(const LaunchCfg& c, const KArgs& a, void* stream, bool fwd) {
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
+const void* kernel_function(const LaunchCfg& c, bool fwd) {
+  const KEntry* e = find_entry(c.nx, c.slots, c.maxbt, c.reg);
+  if (!e) return nullptr;
+  KernelFn fn = fwd ? e->fwd : e->bwd;
+  if (c.lds_bytes > 64 * 1024 &&
+      hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)c.lds_bytes) != hipSuccess)
+    return nullptr;
+  return (const void*)fn;
+}
+
 int launch_forward(const LaunchCfg& c, const KArgs& a, void* stream) { return launch(c, a, stream, true); }
 int launch_backward(const LaunchCfg& c, const KArgs& a, void* stream) { return launch(c, a, stream, false); }
 

@@ -115,14 +115,23 @@ def cartpole_batch(seed=0, batch=1024, T=50, dt=0.05):
 # Uneven LTV batch: T in {16,32,64,128}, nx in {4,8,12,16}, nu in {2,4}
 # ---------------------------------------------------------------------------
 def ltv_uneven_batch(seed=0, batch=4096, Ts=(16, 32, 64, 128), nxs=(4, 8, 12, 16),
-                     nus=(2, 4)):
+                     nus=(2, 4), init="rollout"):
+    """The uneven batch.  Its initial guess is the zero-input rollout from x0
+    (as for the cart-pole batch): a feasible start, from which the first
+    full QP step passes the decrease test and later iterations stay at the
+    solution.  (From the infeasible guess x = 0, u = 0 with x_0 = x0 the
+    penalty of the merit function is zero whenever the cost's directional
+    derivative is negative, and most problems then take the smallest step
+    size at every iteration.)"""
     rng = np.random.default_rng(seed)
     probs = []
     for _ in range(batch):
         T = int(rng.choice(Ts))
         nx = int(rng.choice(nxs))
         nu = int(rng.choice(nus))
-        probs.append(ltv_problem(rng, T, nx, nu))
+        p = ltv_problem(rng, T, nx, nu)
+        p["init"] = init
+        probs.append(p)
     return probs
 
 
@@ -164,7 +173,14 @@ BICYCLE_NOMINAL = dict(
 BICYCLE_XREF = np.array([0.7583, 12.13287, -0.3, 39.47268, 0.3, 0.0, -0.07232, 1.15019])
 
 
-def bicycle_batch(seed=0, batch=512, T=64, phases=4, perturb=0.2):
+def bicycle_batch(seed=0, batch=512, T=64, phases=4, perturb=0.2, variant="nominal"):
+    """variant "nominal": every learned weight has scale 1 and the two
+    actuator states (steering angle, torque) weight 1e-2.  variant
+    "conditioned": per-state scales that make the weights O(1) in the scaled
+    units and unit actuator weights; its preconditioned Schur complement is
+    about ten times better conditioned (~3e4 instead of ~4e5)."""
+    if variant not in ("nominal", "conditioned"):
+        raise ValueError(variant)
     rng = np.random.default_rng(seed)
     nx, nu, N = 8, 2, T + 1
     nw = 6
@@ -172,11 +188,12 @@ def bicycle_batch(seed=0, batch=512, T=64, phases=4, perturb=0.2):
     base = np.array([BICYCLE_NOMINAL[k] for k in BICYCLE_PARAM_NAMES])
     tire_idx = [BICYCLE_PARAM_NAMES.index(k) for k in ("Bf", "Cf", "Df", "Br", "Cr", "Dr")]
     theta = f32(rng.normal(0.0, 0.1, size=phases * (nw + nu)))
-    # per-state scale so that weights are O(1) in the scaled units
-    wscale = f32([1.0, 0.5, 4.0, 0.01, 2.0, 0.5, 2.0, 2.0])
-    # unit weights on the actuator states (delta, tau): with 1e-2 there the
-    # preconditioned Schur complement's condition number is ~4e5 instead of ~3e4
-    wfix = f32([1.0, 1.0])
+    if variant == "nominal":
+        wscale = f32(np.ones(nw + nu))
+        wfix = f32([1e-2, 1e-2])
+    else:
+        wscale = f32([1.0, 0.5, 4.0, 0.01, 2.0, 0.5, 2.0, 2.0])
+        wfix = f32([1.0, 1.0])
     ranges = np.array([0.1, 0.5, 0.05, 1.0, 0.05, 0.2, 0.02, 0.05])
     for _ in range(batch):
         par = base.copy()

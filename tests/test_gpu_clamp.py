@@ -1,0 +1,121 @@
+"""GPU parity where the positive-definite projection of Sec. 3.1 fires: cost
+Hessian entries at or below the floor (negative, zero, tiny positive) are
+clamped to 1e-6 and the linear term of each clamped entry moves with the
+linearisation point (q = Qd xbar + q_raw - Q_proj xbar).  Forward (the last
+QP of three SQP iterations, so that the later iterations' update of the
+clamped linear terms runs), VJP (a clamped entry's gradient is the linear
+term's cotangent times xbar) and JVP, each against the FP64 oracle at the
+GPU's last linearisation point."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2510_06179_amd import _lib, batch
+from paper_2510_06179_amd import workloads as W
+from _parity import REL_TOL, gpu_only, gpu_solve, oracle_kkt_of_gpu_qp, rel_err
+
+pytestmark = [pytest.mark.gpu, gpu_only]
+
+BAD = _lib.PROB_NONPD | _lib.PROB_NONFINITE | _lib.PROB_BWD_PCG_MAXITER
+PD_FLOOR = 1e-6
+
+
+def clamped_batch(seed, middle=False):
+    """LTV problems whose input weights are clamped at ~10% of the entries
+    and whose state weights are clamped at the last stage; a nonzero initial
+    guess, so that the first QP's clamped linear terms differ from the raw
+    ones too.  middle: also a clamped state weight at a middle stage."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for (T, nx, nu) in ((16, 4, 2), (24, 8, 2), (20, 12, 4), (12, 16, 4)):
+        p = W.ltv_problem(rng, T, nx, nu)
+        Qd, Rd = p["Qd"].copy(), p["Rd"].copy()
+        m = rng.random(Rd.shape) < 0.1
+        m[T // 3, 0] = True
+        Rd[m] = W.f32(rng.choice([-0.5, 0.0, 1e-8], size=int(m.sum())))
+        Qd[T, :2] = W.f32([-0.2, 5e-7])
+        if middle:
+            Qd[T // 2, 1] = W.f32(1e-7)
+        p["Qd"], p["Rd"] = Qd, Rd
+        p["xbar"] = W.f32(rng.normal(0.0, 0.3, (T + 1, nx)))
+        p["xbar"][0] = p["x0"]
+        p["ubar"] = W.f32(rng.normal(0.0, 0.3, (T, nu)))
+        out.append(p)
+    return out
+
+
+def _tangent_arena(probs, seed):
+    rng = np.random.default_rng(seed)
+    tans, tps = [], []
+    for p in probs:
+        t = {k: W.f32(rng.standard_normal(np.shape(p[k])))
+             for k in ("x0", "Qd", "q", "Rd", "r", "A", "B", "c")}
+        q = dict(p)
+        q.update(t)
+        tans.append(t)
+        tps.append(q)
+    return tans, torch.from_numpy(batch.pack(tps).data)
+
+
+def test_clamped_costs_forward_vjp_jvp():
+    probs = clamped_batch(5)
+    s, res, status, info = gpu_solve(probs, sqp_iters=3, pcg_tol=1e-6, bwd_pcg_tol=1e-6)
+    assert not np.any(status & (BAD | _lib.PROB_PCG_MAXITER | _lib.PROB_KKT_UNMET)), (status, info)
+    cots = W.loss_cotangents(probs, seed=5)
+    dl = torch.from_numpy(batch.sol_like(s.packed, [(c["gx"], c["gu"], c["glam"]) for c in cots]))
+    _, grad = s.solve_backward(dl.to(s.device))
+    torch.cuda.synchronize()
+    bst, binfo = s.status.cpu().numpy(), s.info.cpu().numpy()
+    assert not np.any(bst & BAD), (bst, binfo)
+    grad = grad.cpu().numpy()
+    tans, arena = _tangent_arena(probs, 6)
+    jv = s.solve_jvp(arena.to(s.device))
+    torch.cuda.synchronize()
+    jst, jinfo = s.status.cpu().numpy(), s.info.cpu().numpy()
+    assert not np.any(jst & BAD), (jst, jinfo)
+    jv = jv.cpu().numpy()
+    clamped = 0
+    for k, p in enumerate(probs):
+        kkt, bound, sq, qpd = oracle_kkt_of_gpu_qp(p, s, k)
+        assert kkt <= bound, (k, kkt, bound)
+        # the projection itself: max(raw, floor) in float32
+        assert np.array_equal(sq["Qd"], np.maximum(p["Qd"], np.float32(PD_FLOOR)).astype(np.float32))
+        assert np.array_equal(sq["Rd"], np.maximum(p["Rd"], np.float32(PD_FLOOR)).astype(np.float32))
+        clamped += int(np.count_nonzero(p["Qd"] < PD_FLOOR) + np.count_nonzero(p["Rd"] < PD_FLOOR))
+        # the last QP's solution
+        sol = oracle.qp.solve_qp(qpd, p["x0"])
+        for name, a, b in zip(("x", "u", "lam"), (sq["xp"], sq["up"], sq["lam"]),
+                              (sol["x"], sol["u"], sol["lam"])):
+            assert rel_err(a, b) <= REL_TOL, (k, name, rel_err(a, b))
+        # VJP, including the clamped entries' gradients
+        g_o, _ = oracle.backward.vjp(p, sq["xlin"], sq["ulin"], qpd, sol, cots[k]["gx"],
+                                     cots[k]["gu"])
+        g = batch.split_grad(s.packed, grad, k)
+        for key in ("Qd", "q", "Rd", "r", "A", "B", "c", "x0"):
+            assert rel_err(g[key], g_o[key]) <= REL_TOL, (k, key, rel_err(g[key], g_o[key]))
+        mq = p["Qd"] < PD_FLOOR
+        assert rel_err(np.asarray(g["Qd"])[mq], g_o["Qd"][mq]) <= REL_TOL, k
+        mr = p["Rd"] < PD_FLOOR
+        assert rel_err(np.asarray(g["Rd"])[mr], g_o["Rd"][mr]) <= REL_TOL, k
+        # JVP
+        ref = oracle.backward.jvp(p, sq["xlin"], sq["ulin"], qpd, sol, tans[k])
+        got = batch.split_sol(s.packed, jv, k)
+        for name, a, b in zip(("dx", "du", "dlam"), got, ref):
+            assert rel_err(a, b) <= REL_TOL, (k, name, rel_err(a, b))
+    assert clamped >= 4 * 3
+
+
+def test_clamped_middle_stage_weight_is_flagged():
+    # A state weight clamped at a stage with a successor puts Q_t^-1 = 1e6
+    # into an off-diagonal Schur block (E_{t+1,t} = -A_t Q_t^-1): the
+    # preconditioned system is then beyond float32, and the refinement stops
+    # above the KKT target.  The solver says so in the status word instead of
+    # returning the answer as converged.
+    probs = clamped_batch(5, middle=True)
+    s, res, status, info = gpu_solve(probs, sqp_iters=3, pcg_tol=1e-6, pcg_max_iter=4000)
+    assert not np.any(status & (_lib.PROB_NONPD | _lib.PROB_NONFINITE)), status
+    for k, p in enumerate(probs):
+        kkt, bound, _, _ = oracle_kkt_of_gpu_qp(p, s, k)
+        if kkt > bound:
+            assert status[k] & _lib.PROB_KKT_UNMET, (k, kkt, status[k])

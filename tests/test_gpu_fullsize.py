@@ -42,23 +42,58 @@ def test_cartpole_full_batch_sampled():
 
 
 def test_uneven_ltv_full_batch_sampled():
-    # 4096 LTV OCPs of uneven horizon and size in one call, 8 SQP iterations
+    # 4096 LTV OCPs of uneven horizon and size in one call, 8 SQP iterations,
+    # forward and backward, in the launch configuration bench.py times; four
+    # problems of every (T, nx, nu) class are checked one by one: the KKT
+    # residual of the last QP, x, u, lambda of the returned solution against
+    # the oracle's SQP run, and the VJP of every input
     probs = W.ltv_uneven_batch(0, batch=4096)
-    s, res, status, info = gpu_solve(probs, sqp_iters=8, pcg_tol=1e-6)
+    cots = W.loss_cotangents(probs, seed=0)
+    s, res, status, info = gpu_solve(probs, sqp_iters=8, pcg_tol=1e-6, bwd_pcg_tol=1e-6)
     assert not np.any(status & BAD)
-    # one problem of every (T, nx) class
-    seen = {}
+    adj, grad = s.solve_backward(_dl(s, cots))
+    torch.cuda.synchronize()
+    assert not np.any(s.status.cpu().numpy() & (BAD | _lib.PROB_BWD_PCG_MAXITER))
+    grad = grad.cpu().numpy()
+    cls = {}
     for k, p in enumerate(probs):
-        seen.setdefault((p["T"], p["nx"]), k)
-    for (T, nx), k in sorted(seen.items()):
-        p = probs[k]
-        kkt, bound, sq, qpd = oracle_kkt_of_gpu_qp(p, s, k)
-        assert kkt <= bound, (T, nx, k, kkt, bound)
+        cls.setdefault((p["T"], p["nx"], p["nu"]), []).append(k)
+    assert len(cls) == 32
+    checked = 0
+    for key, ks in sorted(cls.items()):
+        for k in ks[:4]:
+            p = probs[k]
+            kkt, bound, sq, qpd = oracle_kkt_of_gpu_qp(p, s, k)
+            assert kkt <= bound, (key, k, kkt, bound)
+            # linear dynamics, quadratic costs: the QP does not depend on the
+            # linearisation point, and from the rollout start the first full
+            # step reaches its solution
+            sol = oracle.qp.solve_qp(qpd, p["x0"])
+            x, u, lam = res[k]
+            assert rel_err(x, sol["x"]) <= REL_TOL, (key, k, "x", rel_err(x, sol["x"]))
+            assert rel_err(u, sol["u"]) <= REL_TOL, (key, k, "u", rel_err(u, sol["u"]))
+            assert rel_err(lam, sol["lam"]) <= REL_TOL, (key, k, "lam", rel_err(lam, sol["lam"]))
+            g_o, _ = oracle.backward.vjp(p, sq["xlin"], sq["ulin"], qpd, sol, cots[k]["gx"],
+                                         cots[k]["gu"])
+            g = batch.split_grad(s.packed, grad, k)
+            for name in ("A", "B", "c", "Qd", "q", "Rd", "r", "x0"):
+                assert rel_err(g[name], g_o[name]) <= REL_TOL, (key, k, name,
+                                                                rel_err(g[name], g_o[name]))
+            checked += 1
+    assert checked == 4 * 32
+
+
+# The bicycle batch with its nominal weights (unit scales, 1e-2 on the two
+# actuator states): its preconditioned Schur complement has a condition
+# number of about 4e5, so each float32 refinement pass gains less than on the
+# other workloads; it runs with up to eight passes, each to 1e-2 of the
+# residual it corrects (the same KKT target).
+BICYCLE_OPTS = dict(pcg_tol=1e-6, refine_steps=8, refine_tol=1e-2)
 
 
 def test_bicycle_per_iteration_parity():
     probs = W.bicycle_batch(0, batch=8)
-    s, res, status, info = gpu_solve(probs, sqp_iters=1, pcg_tol=1e-6)
+    s, res, status, info = gpu_solve(probs, sqp_iters=1, **BICYCLE_OPTS)
     cur = [dict(p) for p in probs]
     for it in range(3):
         assert not np.any(status & BAD)
@@ -79,7 +114,7 @@ def test_bicycle_per_iteration_parity():
             q = dict(q)
             q["xbar"], q["ubar"], q["lam"], q["init"] = x, u, lam, "given"
             cur[k] = q
-        s, res, status, info = gpu_solve(cur, sqp_iters=1, pcg_tol=1e-6, init="given")
+        s, res, status, info = gpu_solve(cur, sqp_iters=1, init="given", **BICYCLE_OPTS)
 
 
 def test_bicycle_theta_gradients():
@@ -87,7 +122,7 @@ def test_bicycle_theta_gradients():
     # iterations, adjoint to dtheta, dxref, dx0
     probs = W.bicycle_batch(1, batch=16)
     cots = W.loss_cotangents(probs, seed=1)
-    s, res, status, info = gpu_solve(probs, sqp_iters=10, pcg_tol=1e-6, bwd_pcg_tol=1e-6)
+    s, res, status, info = gpu_solve(probs, sqp_iters=10, bwd_pcg_tol=1e-6, **BICYCLE_OPTS)
     assert not np.any(status & BAD)
     adj, grad = s.solve_backward(_dl(s, cots))
     torch.cuda.synchronize()
@@ -103,3 +138,25 @@ def test_bicycle_theta_gradients():
         for key in ("theta", "xref", "x0"):
             assert rel_err(g[key], g_o[key]) <= REL_TOL, (k, key, rel_err(g[key], g_o[key]))
         assert np.all(g["wscale"] == 0) and np.all(g["wfix"] == 0)
+
+
+def test_bicycle_conditioned_variant_theta_gradients():
+    # the better-conditioned weighting (per-state scales, unit actuator
+    # weights) with the default refinement
+    probs = W.bicycle_batch(2, batch=8, variant="conditioned")
+    cots = W.loss_cotangents(probs, seed=2)
+    s, res, status, info = gpu_solve(probs, sqp_iters=10, pcg_tol=1e-6, bwd_pcg_tol=1e-6)
+    assert not np.any(status & BAD)
+    adj, grad = s.solve_backward(_dl(s, cots))
+    torch.cuda.synchronize()
+    grad = grad.cpu().numpy()
+    for k in range(0, 8, 2):
+        p = probs[k]
+        kkt, bound, sq, qpd = oracle_kkt_of_gpu_qp(p, s, k)
+        assert kkt <= bound, (k, kkt, bound)
+        sol = oracle.qp.solve_qp(qpd, p["x0"])
+        g_o, _ = oracle.backward.vjp(p, sq["xlin"], sq["ulin"], qpd, sol, cots[k]["gx"],
+                                     cots[k]["gu"])
+        g = batch.split_grad(s.packed, grad, k)
+        for key in ("theta", "xref", "x0"):
+            assert rel_err(g[key], g_o[key]) <= REL_TOL, (k, key, rel_err(g[key], g_o[key]))

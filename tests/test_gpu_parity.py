@@ -9,6 +9,7 @@ import oracle
 from paper_2510_06179_amd import _lib, batch
 from paper_2510_06179_amd import workloads as W
 from _parity import REL_TOL, gpu_only, gpu_solve, oracle_kkt_of_gpu_qp, rel_err
+from paper_2510_06179_amd.solver import BatchSolver
 
 pytestmark = [pytest.mark.gpu, gpu_only]
 
@@ -123,7 +124,8 @@ def test_cartpole_ten_iterations_end_to_end():
         compared += 1
         assert rel_err(x, xo) <= REL_TOL, k
         assert rel_err(u, uo) <= REL_TOL, k
-        assert rel_err(lam, lo) <= 10 * REL_TOL, k
+        assert rel_err(lam, lo) <= REL_TOL, k
+    print(f"end-to-end comparison on {compared} of {len(probs)} problems")
     assert compared >= len(probs) // 2, compared
 
 
@@ -152,9 +154,46 @@ def test_pcg_cap_flag_forced_from_host():
     s, res, status, info = gpu_solve(probs, sqp_iters=1, alphas=(1.0,), pcg_max_iter=1,
                                      refine_steps=0)
     assert np.all(status & _lib.PROB_PCG_MAXITER)
+    # one iteration leaves the last QP's residual far above the KKT target
+    assert np.all(status & _lib.PROB_KKT_UNMET)
     assert np.all(info[:, 0] == 1)
 
 
 def test_empty_batch_is_a_noop():
     s, res, status, info = gpu_solve([], sqp_iters=1)
     assert res == []
+
+
+def test_graph_replay_matches_direct_launches():
+    # A batched call replays a HIP graph of the plan's launch groups; the same
+    # plan options with graph = 0 launch the groups on forked side streams.
+    # Replays several times in a row, with eager work and synchronisations in
+    # between and with the buffers changed (the nodes' arguments updated),
+    # each checked bit for bit against the direct launches.
+    probs = W.ltv_uneven_batch(6, batch=48)
+    cots = W.loss_cotangents(probs, seed=6)
+    sg = BatchSolver(probs, sqp_iters=3, pcg_tol=1e-6, graph=True)
+    sd = BatchSolver(probs, sqp_iters=3, pcg_tol=1e-6, graph=False)
+    assert len(sg.describe()) > 1
+    dl = torch.from_numpy(batch.sol_like(sg.packed, [(c["gx"], c["gu"], c["glam"])
+                                                     for c in cots])).to(sg.device)
+    ref = sd.solve().clone()
+    adj_r, grad_r = sd.solve_backward(dl)
+    adj_r, grad_r = adj_r.clone(), grad_r.clone()
+    bufs = [sg.sol0.clone(), sg.sol0.clone()]
+    for rep in range(4):
+        sol = bufs[rep % 2]
+        sol.copy_(sg.sol0)
+        out = sg.solve(sol=sol)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), rep
+        adj = torch.zeros_like(sol)
+        grad = torch.zeros_like(sg.data)
+        sg.solve_backward(dl, adj=adj, grad=grad)
+        torch.cuda.synchronize()
+        assert torch.equal(adj, adj_r) and torch.equal(grad, grad_r), rep
+        # eager work between the replays
+        sd.solve()
+        torch.cuda.synchronize()
+    sg.close()
+    sd.close()
