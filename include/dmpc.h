@@ -20,7 +20,9 @@
  *   - All floating point data is float32, row-major, stage-major.
  *   - The caller owns every buffer (arenas, workspace, status arrays).  The
  *     library allocates device memory only in dmpc_plan_create (the plan's
- *     descriptor table) and dmpc_server_create, never in a solve call.
+ *     descriptor table) and dmpc_server_create, never in a solve call; the
+ *     static workspace of dmpc_solve_static is a device array that exists
+ *     from the library's load on.
  *   - Calls return a dmpc_status; they never throw.  Numeric trouble of a
  *     single problem is reported in its per-problem status word, not as a call
  *     failure.  Solve calls are asynchronous on the given stream.
@@ -181,6 +183,24 @@ dmpc_status dmpc_plan_destroy(dmpc_plan* plan);
  *   stream    a hipStream_t (NULL = default stream) */
 dmpc_status dmpc_solve(dmpc_plan* plan, const float* data, float* sol, void* workspace,
                        int32_t* status, int32_t* info, void* stream);
+
+/* dmpc_solve for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same forward pass with its workspace in the library's own static device
+ * buffer of DMPC_STATIC_WORKSPACE_BYTES (64 MiB) instead of a caller buffer.
+ * The buffer is a file-scope device array, one per device, kept until the
+ * process ends; the call itself allocates nothing (no hipMalloc, hipFree or
+ * allocating library routine).
+ *   data, sol, status, info, stream  as for dmpc_solve (caller-owned)
+ * Returns DMPC_ERR_NOMEM, with nothing launched, when the plan's workspace
+ * (dmpc_plan_workspace_size) exceeds DMPC_STATIC_WORKSPACE_BYTES.  Every call
+ * on a device shares that device's buffer and leaves its contents there:
+ * calls that overlap on one device (other streams, other threads, other
+ * plans) race and must be ordered by the caller.  The buffer is not a
+ * workspace for dmpc_solve_backward (which takes its own). */
+#define DMPC_STATIC_WORKSPACE_BYTES (64ull << 20)
+dmpc_status dmpc_solve_static(dmpc_plan* plan, const float* data, float* sol, int32_t* status,
+                              int32_t* info, void* stream);
 
 /* Backward pass (Alg. backward): VJP of the last QP's solution map with the
  * linearisation point held fixed.

@@ -29,6 +29,7 @@ INIT_KIND = {"given": INIT_GIVEN, "rollout": INIT_ROLLOUT}
 EXPORTED = (
     "dmpc_default_opts", "dmpc_create", "dmpc_destroy", "dmpc_validate", "dmpc_workspace_size",
     "dmpc_plan_create", "dmpc_plan_workspace_size", "dmpc_plan_destroy", "dmpc_solve",
+    "dmpc_solve_static",
     "dmpc_solve_backward", "dmpc_solve_one", "dmpc_solve_backward_one", "dmpc_status_string",
     "dmpc_version", "dmpc_workspace_offsets", "dmpc_plan_describe",
     "dmpc_server_create", "dmpc_server_destroy", "dmpc_server_add_session", "dmpc_server_submit",
@@ -130,6 +131,7 @@ def load():
         "dmpc_plan_workspace_size": (i32, [vp, P(ctypes.c_size_t)]),
         "dmpc_plan_destroy": (i32, [vp]),
         "dmpc_solve": (i32, [vp, vp, vp, vp, vp, vp, vp]),
+        "dmpc_solve_static": (i32, [vp, vp, vp, vp, vp, vp]),
         "dmpc_solve_backward": (i32, [vp, vp, vp, vp, vp, vp, vp, vp, vp]),
         "dmpc_solve_jvp": (i32, [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
         "dmpc_solve_one": (i32, [vp, i32, vp, vp, vp, vp, vp, vp]),

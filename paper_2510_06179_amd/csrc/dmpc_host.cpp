@@ -21,8 +21,39 @@ using namespace dmpc;
 
 struct dmpc_handle {
   int device;
+  void* static_ws;   // device address of this device's copy of `scratch`
 };
 
+// Workspace of dmpc_solve_static, for callers that cannot allocate: a
+// file-scope device array, one copy per device, held until the process ends.
+// Host code never passes `scratch` itself to a kernel (on the host it is a
+// stand-in, not a device address); it uses the address hipGetSymbolAddress
+// gives for the current device, kept per device below.
+constexpr size_t kStaticWsBytes = (size_t)64 << 20;
+static __device__ __align__(256) float scratch[kStaticWsBytes / sizeof(float)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void* g_static_ws[kMaxDevices] = {};
+
+// The device address of `scratch` on `device`, looked up once per device with
+// that device current.  nullptr on failure.
+void* static_ws_address(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  if (g_static_ws[device]) return g_static_ws[device];
+  int prev = 0;
+  if (hipGetDevice(&prev) != hipSuccess) return nullptr;
+  if (prev != device && hipSetDevice(device) != hipSuccess) return nullptr;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (prev != device) hipSetDevice(prev);
+  if (e != hipSuccess) return nullptr;
+  g_static_ws[device] = ptr;
+  return ptr;
+}
+}  // namespace
 
 struct Group {
   LaunchCfg cfg;
@@ -421,9 +452,12 @@ dmpc_status dmpc_create(dmpc_handle** h, int device) {
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess) return DMPC_ERR_HIP;
   if (device < 0 || device >= n) return DMPC_ERR_INVALID_ARG;
+  void* sws = static_ws_address(device);
+  if (!sws) return DMPC_ERR_HIP;
   dmpc_handle* p = new (std::nothrow) dmpc_handle;
   if (!p) return DMPC_ERR_NOMEM;
   p->device = device;
+  p->static_ws = sws;
   *h = p;
   return DMPC_OK;
 }
@@ -764,6 +798,14 @@ static dmpc_status run(dmpc_plan* pl, int index, bool fwd, const float* data, fl
 dmpc_status dmpc_solve(dmpc_plan* plan, const float* data, float* sol, void* workspace,
                        int32_t* status, int32_t* info, void* stream) {
   return run(plan, -1, true, data, sol, nullptr, nullptr, nullptr, workspace, status, info, stream);
+}
+
+dmpc_status dmpc_solve_static(dmpc_plan* plan, const float* data, float* sol, int32_t* status,
+                              int32_t* info, void* stream) {
+  if (!plan) return DMPC_ERR_INVALID_ARG;
+  if (plan->ws_bytes > kStaticWsBytes) return DMPC_ERR_NOMEM;
+  return run(plan, -1, true, data, sol, nullptr, nullptr, nullptr, plan->h->static_ws, status,
+             info, stream);
 }
 
 dmpc_status dmpc_solve_backward(dmpc_plan* plan, const float* data, const float* dl_dsol,

@@ -73,6 +73,17 @@ class BatchSolver:
                    "dmpc_solve")
         return sol
 
+    def solve_static(self, data=None, sol=None, status=None, info=None, stream=None):
+        """dmpc_solve_static: the forward pass with the workspace in the
+        library's static device buffer (no allocation in the call)."""
+        data = self.data if data is None else data
+        sol = self.sol if sol is None else sol
+        status = self.status if status is None else status
+        info = self.info if info is None else info
+        _lib.check(self.lib.dmpc_solve_static(self.plan, _ptr(data), _ptr(sol), _ptr(status),
+                                              _ptr(info), _stream(stream)), "dmpc_solve_static")
+        return sol
+
     def solve_one(self, index, data=None, sol=None, stream=None):
         data = self.data if data is None else data
         sol = self.sol if sol is None else sol
