@@ -382,6 +382,9 @@ dmpc_status dmpc_server_trace(dmpc_server* srv, char* buf, size_t len);
 /* A problem's rows (T+1)*nx are spread over the threads of one workgroup,
  * `slots` rows per thread, with the Schur and preconditioner rows held in
  * registers (register_rows = 1) or read from the workspace (0); variants
+ * with register_rows = 3 keep the Schur rows in registers and the inverted
+ * diagonal blocks in LDS and apply the preconditioner of Eq. S_Phiinv in
+ * factored form (half the registers); variants
  * with register_rows = 2 run one wave per problem with a lane per stage block
  * (rows (T+1)*nx <= 64 * slots) and exchange neighbouring blocks between lanes
  * without LDS.  Without a

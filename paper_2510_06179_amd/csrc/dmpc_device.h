@@ -370,7 +370,7 @@ __device__ __forceinline__ float block_sum(float v, float* red, int nwv) {
 // LDS carve
 // ===========================================================================
 struct Carve {
-  int xbar, ubar, xp, up, lam, w0, w1, w2, piv, red, ls, lin;
+  int xbar, ubar, xp, up, lam, w0, w1, w2, piv, red, dinv, ls, lin;
 };
 __device__ __forceinline__ int a4(int v) { return (v + 3) & ~3; }
 // Offsets: the bulk regions (iterate, QP solution, multipliers, line-search
@@ -395,6 +395,8 @@ __device__ __forceinline__ Carve carve(int R, int TM, int N, int nx, int bt, int
   C.w2 = o;    o += wl;               // low part of a double-float vector in w0
   C.piv = o;   o += 4 * bt;
   C.red = o;   o += 128;
+  C.dinv = o;                         // kRecDinvLds: rows of the inverted diagonal blocks
+  if (flags & kRecDinvLds) o += R * nx;
   C.lin = o;                          // kRecLinLds: the QP-data copy (lin_floats)
   return C;
 }
@@ -1076,6 +1078,7 @@ struct Lds {
   float* w2;   // low part of the vector in w0 (double-float multipliers)
   float* piv;  // Gauss-Jordan pivot rows, double buffered
   float* red;  // 2 x 64 floats for block reductions
+  float* dinv; // kRecDinvLds: row rho of D_t^-1 at dinv + rho NX
 };
 
 template <int NX>
@@ -1087,6 +1090,7 @@ __device__ __forceinline__ Lds lds_of(float* smem, const Prob& P) {
   sh.w2 = smem + C.w2;
   sh.piv = smem + C.piv;
   sh.red = smem + C.red;
+  sh.dinv = smem + C.dinv;
   return sh;
 }
 
@@ -1542,14 +1546,107 @@ __device__ __forceinline__ float pcg_sum(float part, const Lds& sh, int& redi, i
   return block_sum(part, sh.red + 64 * (redi++ & 1), nwv);
 }
 
+// Row product of the inverted diagonal block D_t^-1 (row rho, in LDS) with
+// the window values of block t.
+template <int NX>
+__device__ __forceinline__ float dinv_dot(const float* drow, const float* wblk) {
+  float a0 = 0.f, a1 = 0.f;
+  if constexpr (NX % 4 == 0) {
+    const float4* d4 = reinterpret_cast<const float4*>(drow);
+    const float4* w4 = reinterpret_cast<const float4*>(wblk);
+#pragma unroll
+    for (int j = 0; j < NX / 4; ++j) {
+      const float4 d = d4[j], w = w4[j];
+      a0 = fmaf(d.x, w.x, a0);
+      a1 = fmaf(d.y, w.y, a1);
+      a0 = fmaf(d.z, w.z, a0);
+      a1 = fmaf(d.w, w.w, a1);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < NX; ++j) a0 = fmaf(drow[j], wblk[j], a0);
+  }
+  return a0 + a1;
+}
+
+// The off-diagonal part of a Schur row, E_{t,t-1}[i,:] v_{t-1} +
+// E_{t,t+1}[i,:] v_{t+1}, with the window at block t-1.
+template <int NX>
+__device__ __forceinline__ float offdiag_dot(const float* coef, const float* win) {
+  float a0 = 0.f, a2 = 0.f;
+#pragma unroll
+  for (int j = 0; j < NX; ++j) {
+    a0 = fmaf(coef[j], win[j], a0);
+    a2 = fmaf(coef[2 * NX + j], win[2 * NX + j], a2);
+  }
+  return a0 + a2;
+}
+
+// z = Phi^-1 v with the preconditioner in factored form: the blocks of
+// Eq. S_Phiinv are D_t^-1 on the diagonal and -D_t^-1 E_{t,t+-1} D_{t+-1}^-1
+// off it, that is Phi^-1 = D^-1 - D^-1 E D^-1 with E the off-diagonal blocks
+// of S^.  So w = D^-1 v, u = v - E w, z = D^-1 u: the inverted diagonal
+// blocks from LDS, E from the Schur rows the thread holds, three exchanges
+// through two windows (wa, wb).  Rows past R (register rows are zero there)
+// give zeros.
+template <int NX, int SLOTS>
+__device__ __forceinline__ void apply_precond_factored(const Prob& P, const Lds& sh, float* wa,
+                                                       float* wb, RowRegs<NX, SLOTS, true>& S,
+                                                       const float (&v)[SLOTS],
+                                                       float (&z)[SLOTS]) {
+  const int tid = threadIdx.x, BT = blockDim.x, R = P.R;
+  float w[SLOTS];
+  publish<NX, SLOTS, true>(wa, v, R);
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < SLOTS; ++s) {
+    const int rho = row_of<NX, false>(s, tid, BT);
+    const int t = rho / NX;
+    w[s] = rho < R ? dinv_dot<NX>(sh.dinv + rho * NX, wa + NX + t * NX) : 0.f;
+  }
+  publish<NX, SLOTS, true>(wb, w, R);
+  __syncthreads();
+  float u[SLOTS];
+#pragma unroll
+  for (int s = 0; s < SLOTS; ++s) {
+    const int rho = row_of<NX, false>(s, tid, BT);
+    const int t = rho / NX;
+    u[s] = v[s] - offdiag_dot<NX>(S[s], wb + t * NX);
+  }
+  // (every read of wa happened before the barrier above)
+  publish<NX, SLOTS, true>(wa, u, R);
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < SLOTS; ++s) {
+    const int rho = row_of<NX, false>(s, tid, BT);
+    const int t = rho / NX;
+    z[s] = rho < R ? dinv_dot<NX>(sh.dinv + rho * NX, wa + NX + t * NX) : 0.f;
+  }
+}
+
+// z = Phi^-1 v: the explicit preconditioner rows, or (DINV) the factored form.
+template <int NX, int SLOTS, bool REG, bool WAVE, bool DINV>
+__device__ __forceinline__ void apply_precond(const Prob& P, const Lds& sh,
+                                              RowRegs<NX, SLOTS, REG>& S,
+                                              RowRegs<NX, SLOTS, REG && !DINV>& Ph,
+                                              const float (&v)[SLOTS], float (&z)[SLOTS]) {
+  if constexpr (DINV) {
+    static_assert(REG && !WAVE, "factored preconditioner: register rows, workgroup layout");
+    apply_precond_factored<NX, SLOTS>(P, sh, sh.w1, sh.w2, S, v, z);
+  } else {
+    apply_rows<NX, SLOTS, REG, WAVE, true>(P, sh.w1, Ph, v, z);
+  }
+}
+
 // v' Phi^-1 v for a vector held in this thread's rows.
-template <int NX, int SLOTS, bool REG, bool WAVE>
+template <int NX, int SLOTS, bool REG, bool WAVE, bool DINV>
 __device__ __forceinline__ float precond_norm(const Prob& P, const Lds& sh,
-                                              RowRegs<NX, SLOTS, REG>& Ph, const float (&v)[SLOTS],
-                                              int& redi) {
+                                              RowRegs<NX, SLOTS, REG>& S,
+                                              RowRegs<NX, SLOTS, REG && !DINV>& Ph,
+                                              const float (&v)[SLOTS], int& redi) {
   const int nwv = (blockDim.x + 63) >> 6;
   float z[SLOTS];
-  apply_rows<NX, SLOTS, REG, WAVE, true>(P, sh.w0, Ph, v, z);
+  apply_precond<NX, SLOTS, REG, WAVE, DINV>(P, sh, S, Ph, v, z);
   float part = 0.f;
 #pragma unroll
   for (int s = 0; s < SLOTS; ++s) part = fmaf(v[s], z[s], part);
@@ -1561,9 +1658,9 @@ __device__ __forceinline__ float precond_norm(const Prob& P, const Lds& sh,
 // max(rel_tol^2 * rhs'Phi^-1 rhs, abs_thresh), or at the iteration cap.
 // (The warm start of Alg. pcg enters through rhs = g - S^ lambda, which the
 // caller computes in double.)  Returns the iteration count; ORs status bits.
-template <int NX, int SLOTS, bool REG, bool WAVE>
+template <int NX, int SLOTS, bool REG, bool WAVE, bool DINV>
 __device__ __forceinline__ int pcg(const Prob& P, const Lds& sh, RowRegs<NX, SLOTS, REG>& S,
-                                   RowRegs<NX, SLOTS, REG>& Ph, const float (&rhs)[SLOTS],
+                                   RowRegs<NX, SLOTS, REG && !DINV>& Ph, const float (&rhs)[SLOTS],
                                    float (&d)[SLOTS], int maxit, float rel_tol, float abs_thresh,
                                    int& flags, int& redi, int maxit_flag) {
   const int nwv = (blockDim.x + 63) >> 6;
@@ -1574,7 +1671,7 @@ __device__ __forceinline__ int pcg(const Prob& P, const Lds& sh, RowRegs<NX, SLO
     r[s] = rhs[s];
     d[s] = 0.f;
   }
-  apply_rows<NX, SLOTS, REG, WAVE, true>(P, sh.w1, Ph, r, z);
+  apply_precond<NX, SLOTS, REG, WAVE, DINV>(P, sh, S, Ph, r, z);
   float part = 0.f;
 #pragma unroll
   for (int s = 0; s < SLOTS; ++s) {
@@ -1609,7 +1706,7 @@ __device__ __forceinline__ int pcg(const Prob& P, const Lds& sh, RowRegs<NX, SLO
       r[s] = fmaf(-alpha, y[s], r[s]);
     }
     // r~ = Phi^-1 r, eta' = r'r~
-    apply_rows<NX, SLOTS, REG, WAVE, true>(P, sh.w1, Ph, r, z);
+    apply_precond<NX, SLOTS, REG, WAVE, DINV>(P, sh, S, Ph, r, z);
     part = 0.f;
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) part = fmaf(r[s], z[s], part);
@@ -2732,12 +2829,20 @@ struct KEntry {
 };
 
 // Loads this thread's rows (Schur, preconditioner, right-hand side).
-template <int NX, int SLOTS, bool REG, bool WAVE>
-__device__ __forceinline__ void load_rows(const Prob& P, RowRegs<NX, SLOTS, REG>& S,
-                                          RowRegs<NX, SLOTS, REG>& Ph, float (&g)[SLOTS]) {
+template <int NX, int SLOTS, bool REG, bool WAVE, bool DINV>
+__device__ __forceinline__ void load_rows(const Prob& P, const Lds& sh, RowRegs<NX, SLOTS, REG>& S,
+                                          RowRegs<NX, SLOTS, REG && !DINV>& Ph,
+                                          float (&g)[SLOTS]) {
   const int tid = threadIdx.x, BT = blockDim.x;
   const float* blk = P.W + P.L.blk;
   const float* gv = P.W + P.L.g;
+  if constexpr (DINV) {
+    // the inverted diagonal blocks (row-major per stage: row rho at rho NX)
+    const float4* src = reinterpret_cast<const float4*>(P.W + P.L.Dinv);
+    float4* dst = reinterpret_cast<float4*>(sh.dinv);
+    for (int e = tid; e < P.R * NX / 4; e += BT) dst[e] = src[e];
+    __syncthreads();
+  }
 #pragma unroll
   for (int s = 0; s < SLOTS; ++s) {
     const int rho = row_of<NX, WAVE>(s, tid, BT);
@@ -2747,7 +2852,7 @@ __device__ __forceinline__ void load_rows(const Prob& P, RowRegs<NX, SLOTS, REG>
 #pragma unroll
       for (int j = 0; j < 3 * NX; ++j) {
         S[s][j] = ok ? blk[blk_at<NX>(rho, j)] : 0.f;
-        Ph[s][j] = ok ? blk[blk_at<NX>(rho, 3 * NX + j)] : 0.f;
+        if constexpr (!DINV) Ph[s][j] = ok ? blk[blk_at<NX>(rho, 3 * NX + j)] : 0.f;
       }
     }
   }
@@ -2762,14 +2867,15 @@ __device__ __forceinline__ void load_rows(const Prob& P, RowRegs<NX, SLOTS, REG>
 // relative tolerance ref_tol.  Passes stop once the residual meets the KKT
 // target (||r||_2 <= kkt_tol ||rhs||_2) -- before pass 0 too, when the warm
 // start already meets it (converged SQP iterates).
-template <int NX, int SLOTS, bool REG, bool WAVE, typename ResidualFn>
+template <int NX, int SLOTS, bool REG, bool WAVE, bool DINV, typename ResidualFn>
 __device__ __forceinline__ int qp_solve(const Prob& P, const Lds& sh, RowRegs<NX, SLOTS, REG>& S,
-                                        RowRegs<NX, SLOTS, REG>& Ph, const float (&g)[SLOTS],
+                                        RowRegs<NX, SLOTS, REG && !DINV>& Ph,
+                                        const float (&g)[SLOTS],
                                         float (&hi)[SLOTS], float (&lo)[SLOTS], int steps,
                                         int maxit, float tol, float abs_tol, float ref_tol,
                                         float kkt_tol, int& flags, int& redi, int maxit_flag,
                                         int unmet_flag, ResidualFn residual) {
-  const float etab = precond_norm<NX, SLOTS, REG, WAVE>(P, sh, Ph, g, redi);
+  const float etab = precond_norm<NX, SLOTS, REG, WAVE, DINV>(P, sh, S, Ph, g, redi);
   int its = 0;
   float prev_r2 = 0.f;
   bool met = false;
@@ -2785,10 +2891,10 @@ __device__ __forceinline__ int qp_solve(const Prob& P, const Lds& sh, RowRegs<NX
     if (k > 0 && nr.r2 > 0.25f * prev_r2) break;
     prev_r2 = nr.r2;
     if (k == 0)
-      its += pcg<NX, SLOTS, REG, WAVE>(P, sh, S, Ph, rr, d, maxit, 0.f,
+      its += pcg<NX, SLOTS, REG, WAVE, DINV>(P, sh, S, Ph, rr, d, maxit, 0.f,
                                        fmaxf(tol * tol * etab, abs_tol), flags, redi, maxit_flag);
     else
-      its += pcg<NX, SLOTS, REG, WAVE>(P, sh, S, Ph, rr, d, maxit, ref_tol, 0.f, flags, redi,
+      its += pcg<NX, SLOTS, REG, WAVE, DINV>(P, sh, S, Ph, rr, d, maxit, ref_tol, 0.f, flags, redi,
                                        maxit_flag);
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
@@ -2900,10 +3006,12 @@ __device__ __forceinline__ ResNorms residual_rows(const ProbRec* rec, const KArg
 
 // MODE: 0 = rows of S^ and Phi^-1 read from the workspace, 1 = rows in
 // registers, 2 = rows in registers in the wave-block layout (one wave per
-// problem, a lane per stage block, neighbour values by DPP wave shifts).
+// problem, a lane per stage block, neighbour values by DPP wave shifts),
+// 3 = rows of S^ in registers and the preconditioner in factored form with
+// the inverted diagonal blocks in LDS (half the registers of mode 1).
 template <int NX, int SLOTS, int MAXBT, int MODE>
 __global__ __launch_bounds__(MAXBT) void forward_kernel(KArgs a) {
-  constexpr bool REG = MODE != 0, WAVE = MODE == 2;
+  constexpr bool REG = MODE != 0, WAVE = MODE == 2, DINV = MODE == 3;
   static_assert(!WAVE || (MAXBT == 64 && SLOTS % NX == 0), "wave-block kernels are one wave");
   extern __shared__ float smem[];
   const int tid = threadIdx.x, BT = blockDim.x;
@@ -2930,16 +3038,17 @@ __global__ __launch_bounds__(MAXBT) void forward_kernel(KArgs a) {
     const int maxit = a.pcg_max_iter > 0 ? a.pcg_max_iter : P.R + 10;
     const float rtol = a.refine_tol > 0.f ? a.refine_tol : a.pcg_tol;
     for (int k = 0; k < a.sqp_iters; ++k) {
-      RowRegs<NX, SLOTS, REG> S, Ph;
+      RowRegs<NX, SLOTS, REG> S;
+      RowRegs<NX, SLOTS, REG && !DINV> Ph;
       float g[SLOTS];
       if constexpr (WAVE) {
         fwd_form<NX>(rec, a.data, a.ws, k == 0);
         if (wave_blocks<NX, SLOTS>(P, S, Ph, g, k == a.sqp_iters - 1)) flags |= DMPC_PROB_NONPD;
       } else {
         if (fwd_blocks<NX>(rec, a.data, a.ws, k == 0)) flags |= DMPC_PROB_NONPD;
-        load_rows<NX, SLOTS, REG, WAVE>(P, S, Ph, g);
+        load_rows<NX, SLOTS, REG, WAVE, DINV>(P, sh, S, Ph, g);
       }
-      pcg_total += qp_solve<NX, SLOTS, REG, WAVE>(
+      pcg_total += qp_solve<NX, SLOTS, REG, WAVE, DINV>(
           P, sh, S, Ph, g, lam, lo, a.refine_steps, maxit, a.pcg_tol, a.pcg_abs_tol, rtol,
           a.kkt_tol, flags, redi, DMPC_PROB_PCG_MAXITER,
           k == a.sqp_iters - 1 ? DMPC_PROB_KKT_UNMET : 0,
@@ -2981,7 +3090,7 @@ __global__ __launch_bounds__(MAXBT) void forward_kernel(KArgs a) {
 
 template <int NX, int SLOTS, int MAXBT, int MODE>
 __global__ __launch_bounds__(MAXBT) void backward_kernel(KArgs a) {
-  constexpr bool REG = MODE != 0, WAVE = MODE == 2;
+  constexpr bool REG = MODE != 0, WAVE = MODE == 2, DINV = MODE == 3;
   static_assert(!WAVE || (MAXBT == 64 && SLOTS % NX == 0), "wave-block kernels are one wave");
   extern __shared__ float smem[];
   const int tid = threadIdx.x, BT = blockDim.x;
@@ -2990,9 +3099,10 @@ __global__ __launch_bounds__(MAXBT) void backward_kernel(KArgs a) {
     const Prob P = make_prob<NX>(*rec, a.data, a.ws);
     const Lds sh = lds_of<NX>(smem, P);
     bwd_begin<NX>(rec, a.data, a.ws, a.dl);
-    RowRegs<NX, SLOTS, REG> S, Ph;
+    RowRegs<NX, SLOTS, REG> S;
+    RowRegs<NX, SLOTS, REG && !DINV> Ph;
     float g[SLOTS], lt[SLOTS], lo[SLOTS];
-    load_rows<NX, SLOTS, REG, WAVE>(P, S, Ph, g);
+    load_rows<NX, SLOTS, REG, WAVE, DINV>(P, sh, S, Ph, g);
     const float* alv = a.adj + rec->sol_off + P.R + P.TM;
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
@@ -3004,7 +3114,7 @@ __global__ __launch_bounds__(MAXBT) void backward_kernel(KArgs a) {
     int flags = 0, redi = 0;
     const int maxit = a.bwd_max_iter > 0 ? a.bwd_max_iter : P.R + 10;
     const float rtol = a.refine_tol > 0.f ? a.refine_tol : a.bwd_tol;
-    const int its = qp_solve<NX, SLOTS, REG, WAVE>(
+    const int its = qp_solve<NX, SLOTS, REG, WAVE, DINV>(
         P, sh, S, Ph, g, lt, lo, a.refine_steps, maxit, a.bwd_tol, 0.f, rtol, a.kkt_tol, flags,
         redi, DMPC_PROB_BWD_PCG_MAXITER, DMPC_PROB_BWD_KKT_UNMET,
         [&](const float (&h)[SLOTS], const float (&l)[SLOTS], float (&rr)[SLOTS]) {

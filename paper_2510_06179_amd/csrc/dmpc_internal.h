@@ -31,6 +31,8 @@ constexpr int kRecRegRows = 1;   // the kernel keeps the Schur rows in registers
 constexpr int kRecBulkWs = 2;    // iterate, QP solution, multipliers and the line-search
                                  // region live in the workspace (too large for LDS)
 constexpr int kRecLinLds = 4;    // the QP data (see lin_floats) is read from an LDS copy
+constexpr int kRecDinvLds = 8;   // the inverted diagonal Schur blocks live in LDS (the kernel
+                                 // applies the preconditioner in factored form)
 constexpr int kComputeUnits = 256;   // CUs of an MI355X
 
 // Device record of one problem (96 bytes).
@@ -170,6 +172,7 @@ DMPC_HD inline int64_t lds_floats(int T, int nx, int nu, int bt, int slots, int 
          + 3 * win_floats(R, nx, bt, slots, flags)   // three padded windows
          + 4 * (int64_t)bt               // Gauss-Jordan pivot rows, double buffered
          + 128                           // reductions
+         + ((flags & kRecDinvLds) ? R * nx : 0)   // inverted diagonal blocks
          + ((flags & kRecLinLds) ? lin : 0);
 }
 // Record flags of a problem run by a kernel variant: register rows as the
@@ -178,7 +181,7 @@ DMPC_HD inline int64_t lds_floats(int T, int nx, int nu, int bt, int slots, int 
 // stays within lin_budget bytes (0: never).
 DMPC_HD inline int rec_flags(int T, int nx, int nu, int bt, int slots, int reg, int64_t lin,
                              int64_t lin_budget) {
-  const int f = reg ? kRecRegRows : 0;
+  const int f = (reg ? kRecRegRows : 0) | (reg == 3 ? kRecDinvLds : 0);
   if (lds_floats(T, nx, nu, bt, slots, f, 0) * 4 > kLdsBytes) return f | kRecBulkWs;
   if (lds_floats(T, nx, nu, bt, slots, f | kRecLinLds, lin) * 4 <= lin_budget) return f | kRecLinLds;
   return f;

@@ -164,7 +164,7 @@ def test_variants_cover_every_state_size():
     v = _lib.variants()
     assert {r[0] for r in v} == {2, 3, 4, 8, 12, 16, 32}
     for nx, slots, maxbt, reg in v:
-        assert slots >= 1 and maxbt in (64, 128, 256, 512, 1024) and reg in (0, 1, 2)
+        assert slots >= 1 and maxbt % 64 == 0 and 64 <= maxbt <= 1024 and reg in (0, 1, 2, 3)
         assert reg != 2 or (maxbt == 64 and slots % nx == 0)
 
 
