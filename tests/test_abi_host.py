@@ -212,7 +212,7 @@ def test_tuning_table_overrides_the_cost_model():
         _lib.install_tuning([(4, 40, 60, 1, 256, 1, 256)])
         assert _mapping(p, block_threads=64)[1][3] == 64
         # malformed rows are refused and leave the table as it was
-        for bad in [(5, 1, 9, 1, 64, 1, 64), (4, 9, 1, 1, 64, 1, 64), (4, 1, 9, 1, 64, 3, 64), (4, 1, 9, 2, 64, 2, 64),
+        for bad in [(5, 1, 9, 1, 64, 1, 64), (4, 9, 1, 1, 64, 1, 64), (4, 1, 9, 1, 64, 4, 64), (4, 1, 9, 2, 64, 2, 64),
                     (4, 1, 9, 1, 64, 1, 96), (4, 1, 9, 1, 64, 1, 128)]:
             with pytest.raises(_lib.DmpcError):
                 _lib.install_tuning([bad])
