@@ -393,10 +393,12 @@ __device__ __forceinline__ Carve carve(int R, int TM, int N, int nx, int bt, int
   C.w0 = o;    o += wl;
   C.w1 = o;    o += wl;
   C.w2 = o;    o += wl;               // low part of a double-float vector in w0
-  C.piv = o;   o += 4 * bt;
+  // Gauss-Jordan pivot rows (assembly only); kRecDinvLds: the rows of the
+  // inverted diagonal blocks share the region (staged after the assembly)
+  C.piv = o;
+  C.dinv = o;
+  o += (flags & kRecDinvLds) ? (4 * bt > R * nx ? 4 * bt : R * nx) : 4 * bt;
   C.red = o;   o += 128;
-  C.dinv = o;                         // kRecDinvLds: rows of the inverted diagonal blocks
-  if (flags & kRecDinvLds) o += R * nx;
   C.lin = o;                          // kRecLinLds: the QP-data copy (lin_floats)
   return C;
 }

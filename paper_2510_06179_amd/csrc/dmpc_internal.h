@@ -170,9 +170,11 @@ DMPC_HD inline int64_t lds_floats(int T, int nx, int nu, int bt, int slots, int 
   const int64_t N = T + 1, R = N * nx, TM = (int64_t)T * nu;
   return ((flags & kRecBulkWs) ? 0 : bulk_floats(N, R, TM))
          + 3 * win_floats(R, nx, bt, slots, flags)   // three padded windows
-         + 4 * (int64_t)bt               // Gauss-Jordan pivot rows, double buffered
+         // Gauss-Jordan pivot rows, double buffered (kRecDinvLds: the rows of
+         // the inverted diagonal blocks share the region)
+         + ((flags & kRecDinvLds) ? (4 * (int64_t)bt > R * nx ? 4 * (int64_t)bt : R * nx)
+                                  : 4 * (int64_t)bt)
          + 128                           // reductions
-         + ((flags & kRecDinvLds) ? R * nx : 0)   // inverted diagonal blocks
          + ((flags & kRecLinLds) ? lin : 0);
 }
 // Record flags of a problem run by a kernel variant: register rows as the
