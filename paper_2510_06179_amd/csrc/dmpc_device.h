@@ -2830,13 +2830,33 @@ struct KEntry {
   KernelFn fwd, bwd;
 };
 
+// Loads this thread's register rows (Schur and, without the factored
+// preconditioner, preconditioner) from the workspace copy of the assembly.
+template <int NX, int SLOTS, bool REG, bool WAVE, bool DINV>
+__device__ __forceinline__ void load_reg_rows(const Prob& P, RowRegs<NX, SLOTS, REG>& S,
+                                              RowRegs<NX, SLOTS, REG && !DINV>& Ph) {
+  if constexpr (REG) {
+    const int tid = threadIdx.x, BT = blockDim.x;
+    const float* blk = P.W + P.L.blk;
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+      const int rho = row_of<NX, WAVE>(s, tid, BT);
+      const bool ok = rho < P.R;
+#pragma unroll
+      for (int j = 0; j < 3 * NX; ++j) {
+        S[s][j] = ok ? blk[blk_at<NX>(rho, j)] : 0.f;
+        if constexpr (!DINV) Ph[s][j] = ok ? blk[blk_at<NX>(rho, 3 * NX + j)] : 0.f;
+      }
+    }
+  }
+}
+
 // Loads this thread's rows (Schur, preconditioner, right-hand side).
 template <int NX, int SLOTS, bool REG, bool WAVE, bool DINV>
 __device__ __forceinline__ void load_rows(const Prob& P, const Lds& sh, RowRegs<NX, SLOTS, REG>& S,
                                           RowRegs<NX, SLOTS, REG && !DINV>& Ph,
                                           float (&g)[SLOTS]) {
   const int tid = threadIdx.x, BT = blockDim.x;
-  const float* blk = P.W + P.L.blk;
   const float* gv = P.W + P.L.g;
   if constexpr (DINV) {
     // the inverted diagonal blocks (row-major per stage: row rho at rho NX)
@@ -2848,16 +2868,9 @@ __device__ __forceinline__ void load_rows(const Prob& P, const Lds& sh, RowRegs<
 #pragma unroll
   for (int s = 0; s < SLOTS; ++s) {
     const int rho = row_of<NX, WAVE>(s, tid, BT);
-    const bool ok = rho < P.R;
-    g[s] = ok ? gv[rho] : 0.f;
-    if constexpr (REG) {
-#pragma unroll
-      for (int j = 0; j < 3 * NX; ++j) {
-        S[s][j] = ok ? blk[blk_at<NX>(rho, j)] : 0.f;
-        if constexpr (!DINV) Ph[s][j] = ok ? blk[blk_at<NX>(rho, 3 * NX + j)] : 0.f;
-      }
-    }
+    g[s] = rho < P.R ? gv[rho] : 0.f;
   }
+  load_reg_rows<NX, SLOTS, REG, WAVE, DINV>(P, S, Ph);
 }
 
 // One QP solve of the Schur system, mixed precision.  lambda = hi + lo is a
@@ -2892,6 +2905,10 @@ __device__ __forceinline__ int qp_solve(const Prob& P, const Lds& sh, RowRegs<NX
     // of this system: further passes would not gain either
     if (k > 0 && nr.r2 > 0.25f * prev_r2) break;
     prev_r2 = nr.r2;
+    // register rows are read again after the residual, which is a call at
+    // nx > 4: held across it they would be saved through scratch and
+    // reloaded from there at every use inside the PCG loop
+    if constexpr (REG && !WAVE) load_reg_rows<NX, SLOTS, REG, WAVE, DINV>(P, S, Ph);
     if (k == 0)
       its += pcg<NX, SLOTS, REG, WAVE, DINV>(P, sh, S, Ph, rr, d, maxit, 0.f,
                                        fmaxf(tol * tol * etab, abs_tol), flags, redi, maxit_flag);
