@@ -384,8 +384,9 @@ dmpc_status dmpc_server_trace(dmpc_server* srv, char* buf, size_t len);
  * registers (register_rows = 1) or read from the workspace (0); variants
  * with register_rows = 3 keep the Schur rows in registers and the inverted
  * diagonal blocks in LDS and apply the preconditioner of Eq. S_Phiinv in
- * factored form (half the registers); variants
- * with register_rows = 2 run one wave per problem with a lane per stage block
+ * factored form (half the registers); register_rows = 4 is the same with the
+ * Schur rows of the last slot (those past (slots - 1) * block_threads) in
+ * LDS; variants with register_rows = 2 run one wave per problem with a lane per stage block
  * (rows (T+1)*nx <= 64 * slots) and exchange neighbouring blocks between lanes
  * without LDS.  Without a
  * tuning-table entry the library picks the instantiated variant with the
@@ -400,11 +401,13 @@ int32_t dmpc_list_variants(int32_t* out, int32_t max_rows);
  * (nx, T_min, T_max, slots, launch_bound, register_rows, block_threads).  A
  * problem with that nx and T_min <= T <= T_max uses the first matching row
  * whose variant is instantiated and holds its rows (slots * block_threads >=
- * (T+1)*nx, block_threads a multiple of 64 not above launch_bound); otherwise
+ * (T+1)*nx, block_threads a multiple of 64 not above launch_bound, the
+ * problem's LDS regions within a workgroup's LDS); otherwise
  * the cost model decides.  Replaces the previous table; n_rows = 0 clears it.
  * Affects plans and sessions created afterwards.  INVALID_ARG on a malformed
  * row (nothing is installed then); a row with register_rows = 2 must have
- * launch_bound 64 and slots a multiple of nx.  Host only; thread safe. */
+ * launch_bound 64 and slots a multiple of nx; one with register_rows = 4
+ * launch_bound and block_threads 512 and slots >= 2.  Host only; thread safe. */
 dmpc_status dmpc_set_tuning(const int32_t* rows, int32_t n_rows);
 
 /* Copies up to max_rows rows of the installed table into the HOST array rows

@@ -370,7 +370,7 @@ __device__ __forceinline__ float block_sum(float v, float* red, int nwv) {
 // LDS carve
 // ===========================================================================
 struct Carve {
-  int xbar, ubar, xp, up, lam, w0, w1, w2, piv, red, dinv, ls, lin;
+  int xbar, ubar, xp, up, lam, w0, w1, w2, piv, red, dinv, tail, ls, lin;
 };
 __device__ __forceinline__ int a4(int v) { return (v + 3) & ~3; }
 // Offsets: the bulk regions (iterate, QP solution, multipliers, line-search
@@ -399,6 +399,8 @@ __device__ __forceinline__ Carve carve(int R, int TM, int N, int nx, int bt, int
   C.dinv = o;
   o += (flags & kRecDinvLds) ? (4 * bt > R * nx ? 4 * bt : R * nx) : 4 * bt;
   C.red = o;   o += 128;
+  C.tail = o;                         // kRecTailLds: Schur rows past the register slots
+  o += (int)tail_rows(R, bt, slots, flags) * tail_stride(nx);
   C.lin = o;                          // kRecLinLds: the QP-data copy (lin_floats)
   return C;
 }
@@ -1081,6 +1083,7 @@ struct Lds {
   float* piv;  // Gauss-Jordan pivot rows, double buffered
   float* red;  // 2 x 64 floats for block reductions
   float* dinv; // kRecDinvLds: row rho of D_t^-1 at dinv + rho NX
+  float* tail; // kRecTailLds: Schur row (s - 1) BT + k of the last slot s at tail + k stride
 };
 
 template <int NX>
@@ -1093,6 +1096,7 @@ __device__ __forceinline__ Lds lds_of(float* smem, const Prob& P) {
   sh.piv = smem + C.piv;
   sh.red = smem + C.red;
   sh.dinv = smem + C.dinv;
+  sh.tail = smem + C.tail;
   return sh;
 }
 
@@ -1114,13 +1118,33 @@ __device__ __forceinline__ int row_of(int s, int tid, int BT) {
   return tid + s * BT;
 }
 
-template <int NX, int SLOTS, bool FULL = false, bool WAVE = false>
+// Threads of the workgroup: LDS-row kernels (TAIL) run with kTailThreads, a
+// compile-time constant there, so that per-slot row offsets are immediates.
+template <bool TAIL>
+__device__ __forceinline__ int block_threads() {
+  if constexpr (TAIL) return kTailThreads;
+  return blockDim.x;
+}
+// Thread index for the row products of the PCG loop.  TAIL: read through an
+// empty asm, so that the LDS addresses derived from it are formed where they
+// are used instead of being hoisted out of the loop and held (the rows need
+// those registers).
+template <bool TAIL>
+__device__ __forceinline__ int loop_tid() {
+  int tid = threadIdx.x;
+  if constexpr (TAIL) asm volatile("" : "+v"(tid));
+  return tid;
+}
+
+// (TAIL: the last slot's rows are in LDS and guarded, the others as FULL says)
+template <int NX, int SLOTS, bool FULL = false, bool WAVE = false, bool TAIL = false>
 __device__ __forceinline__ void publish(float* w, const float (&v)[SLOTS], int R) {
-  const int tid = threadIdx.x, BT = blockDim.x;
+  const int tid = loop_tid<TAIL>(), BT = block_threads<TAIL>();
 #pragma unroll
   for (int s = 0; s < SLOTS; ++s) {
     const int rho = row_of<NX, WAVE>(s, tid, BT);
-    if (row_live<FULL>(s, rho, R, BT)) w[NX + rho] = v[s];
+    const bool full = FULL && !(TAIL && s == SLOTS - 1);
+    if (full || rho < R) w[NX + rho] = v[s];
   }
 }
 
@@ -1444,9 +1468,91 @@ __device__ __forceinline__ void mfma_precond_blocks(const Prob& P, float* blk, c
 // PCG (Alg. pcg) and its row products
 // ===========================================================================
 // Register copy of a thread's Schur / preconditioner rows; a placeholder of
-// one float when the rows are read from the workspace.
+// one float when the rows are read from the workspace.  With the last value
+// slot's rows in LDS (TAIL) a thread holds SLOTS - 1 register rows.
 template <int NX, int SLOTS, bool REG>
 using RowRegs = float[REG ? SLOTS : 1][REG ? 3 * NX : 1];
+
+// Schur row k of the LDS rows (kRecTailLds).
+template <int NX>
+__device__ __forceinline__ const float* tail_row(const float* tail, int k) {
+  return tail + k * tail_stride(NX);
+}
+// Row product and off-diagonal part of an LDS row (16-byte aligned rows).
+template <int NX>
+__device__ __forceinline__ float tail_dot(const float* coef, const float* win) {
+  static_assert(NX % 4 == 0, "LDS rows: nx a multiple of 4");
+  const float4* c4 = reinterpret_cast<const float4*>(coef);
+  const float4* w4 = reinterpret_cast<const float4*>(win);
+  float acc[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int b = 0; b < 3; ++b)
+#pragma unroll
+    for (int j = 0; j < NX / 4; ++j) {
+      const float4 c = c4[b * (NX / 4) + j], v = w4[b * (NX / 4) + j];
+      acc[b] = fmaf(c.x, v.x, acc[b]);
+      acc[b] = fmaf(c.y, v.y, acc[b]);
+      acc[b] = fmaf(c.z, v.z, acc[b]);
+      acc[b] = fmaf(c.w, v.w, acc[b]);
+    }
+  return (acc[0] + acc[1]) + acc[2];
+}
+template <int NX>
+__device__ __forceinline__ float tail_offdiag(const float* coef, const float* win) {
+  const float4* c4 = reinterpret_cast<const float4*>(coef);
+  const float4* w4 = reinterpret_cast<const float4*>(win);
+  float a0 = 0.f, a2 = 0.f;
+#pragma unroll
+  for (int j = 0; j < NX / 4; ++j) {
+    const float4 c = c4[j], v = w4[j];
+    const float4 e = c4[NX / 2 + j], u = w4[NX / 2 + j];
+    a0 = fmaf(c.x, v.x, a0);
+    a2 = fmaf(e.x, u.x, a2);
+    a0 = fmaf(c.y, v.y, a0);
+    a2 = fmaf(e.y, u.y, a2);
+    a0 = fmaf(c.z, v.z, a0);
+    a2 = fmaf(e.z, u.z, a2);
+    a0 = fmaf(c.w, v.w, a0);
+    a2 = fmaf(e.w, u.w, a2);
+  }
+  return a0 + a2;
+}
+
+// Ordering fence on a computed value: the value is complete before the fence
+// and no memory access moves across it.  The LDS-row kernels hold four
+// register rows per thread in a 256-register budget; fences after each slot's
+// row product (and after each of the three blocks of a row) keep the
+// compiler from issuing every slot's window reads at once, which would leave
+// no room for the rows.
+template <bool ON>
+__device__ __forceinline__ void slot_fence(float& x) {
+  if constexpr (ON) asm volatile("" : "+v"(x) : : "memory");
+}
+// Row product with the window read block by block (three blocks of nx).
+template <int NX>
+__device__ __forceinline__ float row_dot_blocks(const float* coef, const float* win) {
+  static_assert(NX % 4 == 0, "block-wise row product: nx a multiple of 4");
+  const float4* w4 = reinterpret_cast<const float4*>(win);
+  float acc[3];
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    float wv[NX];
+#pragma unroll
+    for (int j = 0; j < NX / 4; ++j) {
+      const float4 v = w4[b * (NX / 4) + j];
+      wv[4 * j] = v.x;
+      wv[4 * j + 1] = v.y;
+      wv[4 * j + 2] = v.z;
+      wv[4 * j + 3] = v.w;
+    }
+    float a = 0.f;
+#pragma unroll
+    for (int j = 0; j < NX; ++j) a = fmaf(coef[b * NX + j], wv[j], a);
+    slot_fence<true>(a);
+    acc[b] = a;
+  }
+  return (acc[0] + acc[1]) + acc[2];
+}
 
 template <int NX, int SLOTS, bool REG>
 __device__ __forceinline__ const float* coefS(const Prob& P, RowRegs<NX, SLOTS, REG>& S, int s,
@@ -1505,10 +1611,13 @@ __device__ __forceinline__ void wave_neighbours(const float (&v)[SLOTS], float (
 // rows of S^ (PH = false) or Phi^-1 (PH = true): through an LDS window
 // (publish, barrier, row products) or, in the wave-block layout, with the
 // neighbour values in registers (same products in the same order).
-template <int NX, int SLOTS, bool REG, bool WAVE, bool PH>
-__device__ __forceinline__ void apply_rows(const Prob& P, float* win, RowRegs<NX, SLOTS, REG>& M,
-                                           const float (&v)[SLOTS], float (&out)[SLOTS]) {
-  const int tid = threadIdx.x, BT = blockDim.x, R = P.R;
+// (TAIL: the last slot's rows are the LDS rows at `tail`.)
+template <int NX, int SLOTS, bool REG, bool WAVE, bool PH, bool TAIL = false>
+__device__ __forceinline__ void apply_rows(const Prob& P, float* win,
+                                           RowRegs<NX, SLOTS - TAIL, REG>& M,
+                                           const float (&v)[SLOTS], float (&out)[SLOTS],
+                                           const float* tail = nullptr) {
+  const int tid = loop_tid<TAIL>(), BT = block_threads<TAIL>(), R = P.R;
   if constexpr (WAVE) {
     float pv[SLOTS], nv[SLOTS];
     wave_neighbours<NX, SLOTS>(v, pv, nv);
@@ -1526,17 +1635,28 @@ __device__ __forceinline__ void apply_rows(const Prob& P, float* win, RowRegs<NX
       out[s] = acc;
     }
   } else {
-    publish<NX, SLOTS, REG>(win, v, R);
+    publish<NX, SLOTS, REG, false, TAIL>(win, v, R);
     __syncthreads();
+    constexpr int RS = SLOTS - TAIL;
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
       const int rho = row_of<NX, false>(s, tid, BT);
       out[s] = 0.f;
-      if (row_live<REG>(s, rho, R, BT)) {
-        const int t = rho / NX;
-        const float* coef = PH ? coefP<NX, SLOTS, REG>(P, M, s, rho) : coefS<NX, SLOTS, REG>(P, M, s, rho);
-        out[s] = rdot<NX, SLOTS, REG>(coef, win + t * NX);
+      bool lds_row = false;
+      if constexpr (TAIL) {
+        if (s == SLOTS - 1) {
+          lds_row = true;
+          if (rho < R) out[s] = tail_dot<NX>(tail_row<NX>(tail, rho - RS * BT), win + (rho / NX) * NX);
+        }
       }
+      if (!lds_row && row_live<REG>(s, rho, R, BT)) {
+        const int t = rho / NX;
+        const int sr = s < RS ? s : 0;   // (s < RS here)
+        const float* coef = PH ? coefP<NX, RS, REG>(P, M, sr, rho) : coefS<NX, RS, REG>(P, M, sr, rho);
+        if constexpr (TAIL) out[s] = row_dot_blocks<NX>(coef, win + t * NX);
+        else out[s] = rdot<NX, RS, REG>(coef, win + t * NX);
+      }
+      slot_fence<TAIL>(out[s]);
     }
   }
 }
@@ -1591,64 +1711,78 @@ __device__ __forceinline__ float offdiag_dot(const float* coef, const float* win
 // blocks from LDS, E from the Schur rows the thread holds, three exchanges
 // through two windows (wa, wb).  Rows past R (register rows are zero there)
 // give zeros.
-template <int NX, int SLOTS>
+template <int NX, int SLOTS, bool TAIL>
 __device__ __forceinline__ void apply_precond_factored(const Prob& P, const Lds& sh, float* wa,
-                                                       float* wb, RowRegs<NX, SLOTS, true>& S,
+                                                       float* wb,
+                                                       RowRegs<NX, SLOTS - TAIL, true>& S,
                                                        const float (&v)[SLOTS],
                                                        float (&z)[SLOTS]) {
-  const int tid = threadIdx.x, BT = blockDim.x, R = P.R;
+  const int tid = loop_tid<TAIL>(), BT = block_threads<TAIL>(), R = P.R;
+  constexpr int RS = SLOTS - TAIL;
   float w[SLOTS];
-  publish<NX, SLOTS, true>(wa, v, R);
+  publish<NX, SLOTS, true, false, TAIL>(wa, v, R);
   __syncthreads();
 #pragma unroll
   for (int s = 0; s < SLOTS; ++s) {
     const int rho = row_of<NX, false>(s, tid, BT);
     const int t = rho / NX;
     w[s] = rho < R ? dinv_dot<NX>(sh.dinv + rho * NX, wa + NX + t * NX) : 0.f;
+    slot_fence<TAIL>(w[s]);
   }
-  publish<NX, SLOTS, true>(wb, w, R);
+  publish<NX, SLOTS, true, false, TAIL>(wb, w, R);
   __syncthreads();
   float u[SLOTS];
 #pragma unroll
   for (int s = 0; s < SLOTS; ++s) {
     const int rho = row_of<NX, false>(s, tid, BT);
     const int t = rho / NX;
-    u[s] = v[s] - offdiag_dot<NX>(S[s], wb + t * NX);
+    if constexpr (TAIL) {
+      if (s == SLOTS - 1)
+        u[s] = rho < R ? v[s] - tail_offdiag<NX>(tail_row<NX>(sh.tail, rho - RS * BT), wb + t * NX)
+                       : 0.f;
+      else
+        u[s] = v[s] - offdiag_dot<NX>(S[s < RS ? s : 0], wb + t * NX);
+    } else {
+      u[s] = v[s] - offdiag_dot<NX>(S[s], wb + t * NX);
+    }
+    slot_fence<TAIL>(u[s]);
   }
   // (every read of wa happened before the barrier above)
-  publish<NX, SLOTS, true>(wa, u, R);
+  publish<NX, SLOTS, true, false, TAIL>(wa, u, R);
   __syncthreads();
 #pragma unroll
   for (int s = 0; s < SLOTS; ++s) {
     const int rho = row_of<NX, false>(s, tid, BT);
     const int t = rho / NX;
     z[s] = rho < R ? dinv_dot<NX>(sh.dinv + rho * NX, wa + NX + t * NX) : 0.f;
+    slot_fence<TAIL>(z[s]);
   }
 }
 
 // z = Phi^-1 v: the explicit preconditioner rows, or (DINV) the factored form.
-template <int NX, int SLOTS, bool REG, bool WAVE, bool DINV>
+template <int NX, int SLOTS, bool REG, bool WAVE, bool DINV, bool TAIL>
 __device__ __forceinline__ void apply_precond(const Prob& P, const Lds& sh,
-                                              RowRegs<NX, SLOTS, REG>& S,
-                                              RowRegs<NX, SLOTS, REG && !DINV>& Ph,
+                                              RowRegs<NX, SLOTS - TAIL, REG>& S,
+                                              RowRegs<NX, SLOTS - TAIL, REG && !DINV>& Ph,
                                               const float (&v)[SLOTS], float (&z)[SLOTS]) {
   if constexpr (DINV) {
     static_assert(REG && !WAVE, "factored preconditioner: register rows, workgroup layout");
-    apply_precond_factored<NX, SLOTS>(P, sh, sh.w1, sh.w2, S, v, z);
+    apply_precond_factored<NX, SLOTS, TAIL>(P, sh, sh.w1, sh.w2, S, v, z);
   } else {
+    static_assert(!TAIL, "LDS rows: factored preconditioner only");
     apply_rows<NX, SLOTS, REG, WAVE, true>(P, sh.w1, Ph, v, z);
   }
 }
 
 // v' Phi^-1 v for a vector held in this thread's rows.
-template <int NX, int SLOTS, bool REG, bool WAVE, bool DINV>
+template <int NX, int SLOTS, bool REG, bool WAVE, bool DINV, bool TAIL>
 __device__ __forceinline__ float precond_norm(const Prob& P, const Lds& sh,
-                                              RowRegs<NX, SLOTS, REG>& S,
-                                              RowRegs<NX, SLOTS, REG && !DINV>& Ph,
+                                              RowRegs<NX, SLOTS - TAIL, REG>& S,
+                                              RowRegs<NX, SLOTS - TAIL, REG && !DINV>& Ph,
                                               const float (&v)[SLOTS], int& redi) {
-  const int nwv = (blockDim.x + 63) >> 6;
+  const int nwv = (block_threads<TAIL>() + 63) >> 6;
   float z[SLOTS];
-  apply_precond<NX, SLOTS, REG, WAVE, DINV>(P, sh, S, Ph, v, z);
+  apply_precond<NX, SLOTS, REG, WAVE, DINV, TAIL>(P, sh, S, Ph, v, z);
   float part = 0.f;
 #pragma unroll
   for (int s = 0; s < SLOTS; ++s) part = fmaf(v[s], z[s], part);
@@ -1660,12 +1794,14 @@ __device__ __forceinline__ float precond_norm(const Prob& P, const Lds& sh,
 // max(rel_tol^2 * rhs'Phi^-1 rhs, abs_thresh), or at the iteration cap.
 // (The warm start of Alg. pcg enters through rhs = g - S^ lambda, which the
 // caller computes in double.)  Returns the iteration count; ORs status bits.
-template <int NX, int SLOTS, bool REG, bool WAVE, bool DINV>
-__device__ __forceinline__ int pcg(const Prob& P, const Lds& sh, RowRegs<NX, SLOTS, REG>& S,
-                                   RowRegs<NX, SLOTS, REG && !DINV>& Ph, const float (&rhs)[SLOTS],
+template <int NX, int SLOTS, bool REG, bool WAVE, bool DINV, bool TAIL>
+__device__ __forceinline__ int pcg(const Prob& P, const Lds& sh,
+                                   RowRegs<NX, SLOTS - TAIL, REG>& S,
+                                   RowRegs<NX, SLOTS - TAIL, REG && !DINV>& Ph,
+                                   const float (&rhs)[SLOTS],
                                    float (&d)[SLOTS], int maxit, float rel_tol, float abs_thresh,
                                    int& flags, int& redi, int maxit_flag) {
-  const int nwv = (blockDim.x + 63) >> 6;
+  const int nwv = (block_threads<TAIL>() + 63) >> 6;
   float r[SLOTS], p[SLOTS], z[SLOTS], y[SLOTS];
   // initial residual r = rhs (d = 0), r~ = Phi^-1 r, p = r~, eta = r'r~
 #pragma unroll
@@ -1673,7 +1809,7 @@ __device__ __forceinline__ int pcg(const Prob& P, const Lds& sh, RowRegs<NX, SLO
     r[s] = rhs[s];
     d[s] = 0.f;
   }
-  apply_precond<NX, SLOTS, REG, WAVE, DINV>(P, sh, S, Ph, r, z);
+  apply_precond<NX, SLOTS, REG, WAVE, DINV, TAIL>(P, sh, S, Ph, r, z);
   float part = 0.f;
 #pragma unroll
   for (int s = 0; s < SLOTS; ++s) {
@@ -1689,7 +1825,7 @@ __device__ __forceinline__ int pcg(const Prob& P, const Lds& sh, RowRegs<NX, SLO
   }
   while (it < maxit && eta > thresh) {
     // y = S^ p, v = p'y, alpha = eta / v
-    apply_rows<NX, SLOTS, REG, WAVE, false>(P, sh.w0, S, p, y);
+    apply_rows<NX, SLOTS, REG, WAVE, false, TAIL>(P, sh.w0, S, p, y, sh.tail);
     part = 0.f;
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) part = fmaf(p[s], y[s], part);
@@ -1708,7 +1844,7 @@ __device__ __forceinline__ int pcg(const Prob& P, const Lds& sh, RowRegs<NX, SLO
       r[s] = fmaf(-alpha, y[s], r[s]);
     }
     // r~ = Phi^-1 r, eta' = r'r~
-    apply_precond<NX, SLOTS, REG, WAVE, DINV>(P, sh, S, Ph, r, z);
+    apply_precond<NX, SLOTS, REG, WAVE, DINV, TAIL>(P, sh, S, Ph, r, z);
     part = 0.f;
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) part = fmaf(r[s], z[s], part);
@@ -2832,14 +2968,14 @@ struct KEntry {
 
 // Loads this thread's register rows (Schur and, without the factored
 // preconditioner, preconditioner) from the workspace copy of the assembly.
-template <int NX, int SLOTS, bool REG, bool WAVE, bool DINV>
-__device__ __forceinline__ void load_reg_rows(const Prob& P, RowRegs<NX, SLOTS, REG>& S,
-                                              RowRegs<NX, SLOTS, REG && !DINV>& Ph) {
+template <int NX, int SLOTS, bool REG, bool WAVE, bool DINV, bool TAIL>
+__device__ __forceinline__ void load_reg_rows(const Prob& P, RowRegs<NX, SLOTS - TAIL, REG>& S,
+                                              RowRegs<NX, SLOTS - TAIL, REG && !DINV>& Ph) {
   if constexpr (REG) {
-    const int tid = threadIdx.x, BT = blockDim.x;
+    const int tid = threadIdx.x, BT = block_threads<TAIL>();
     const float* blk = P.W + P.L.blk;
 #pragma unroll
-    for (int s = 0; s < SLOTS; ++s) {
+    for (int s = 0; s < SLOTS - TAIL; ++s) {
       const int rho = row_of<NX, WAVE>(s, tid, BT);
       const bool ok = rho < P.R;
 #pragma unroll
@@ -2851,13 +2987,23 @@ __device__ __forceinline__ void load_reg_rows(const Prob& P, RowRegs<NX, SLOTS, 
   }
 }
 
-// Loads this thread's rows (Schur, preconditioner, right-hand side).
-template <int NX, int SLOTS, bool REG, bool WAVE, bool DINV>
-__device__ __forceinline__ void load_rows(const Prob& P, const Lds& sh, RowRegs<NX, SLOTS, REG>& S,
-                                          RowRegs<NX, SLOTS, REG && !DINV>& Ph,
+// Loads this thread's rows (Schur, preconditioner, right-hand side); TAIL:
+// the Schur rows past the register slots into LDS.
+template <int NX, int SLOTS, bool REG, bool WAVE, bool DINV, bool TAIL>
+__device__ __forceinline__ void load_rows(const Prob& P, const Lds& sh,
+                                          RowRegs<NX, SLOTS - TAIL, REG>& S,
+                                          RowRegs<NX, SLOTS - TAIL, REG && !DINV>& Ph,
                                           float (&g)[SLOTS]) {
-  const int tid = threadIdx.x, BT = blockDim.x;
+  const int tid = threadIdx.x, BT = block_threads<TAIL>();
   const float* gv = P.W + P.L.g;
+  if constexpr (TAIL) {
+    const float* blk = P.W + P.L.blk;
+    const int base = (SLOTS - 1) * BT, nt = P.R - base;
+    for (int e = tid; e < nt * 3 * NX; e += BT) {
+      const int k = e / (3 * NX), j = e - k * (3 * NX);
+      sh.tail[k * tail_stride(NX) + j] = blk[blk_at<NX>(base + k, j)];
+    }
+  }
   if constexpr (DINV) {
     // the inverted diagonal blocks (row-major per stage: row rho at rho NX)
     const float4* src = reinterpret_cast<const float4*>(P.W + P.L.Dinv);
@@ -2870,7 +3016,7 @@ __device__ __forceinline__ void load_rows(const Prob& P, const Lds& sh, RowRegs<
     const int rho = row_of<NX, WAVE>(s, tid, BT);
     g[s] = rho < P.R ? gv[rho] : 0.f;
   }
-  load_reg_rows<NX, SLOTS, REG, WAVE, DINV>(P, S, Ph);
+  load_reg_rows<NX, SLOTS, REG, WAVE, DINV, TAIL>(P, S, Ph);
 }
 
 // One QP solve of the Schur system, mixed precision.  lambda = hi + lo is a
@@ -2882,15 +3028,16 @@ __device__ __forceinline__ void load_rows(const Prob& P, const Lds& sh, RowRegs<
 // relative tolerance ref_tol.  Passes stop once the residual meets the KKT
 // target (||r||_2 <= kkt_tol ||rhs||_2) -- before pass 0 too, when the warm
 // start already meets it (converged SQP iterates).
-template <int NX, int SLOTS, bool REG, bool WAVE, bool DINV, typename ResidualFn>
-__device__ __forceinline__ int qp_solve(const Prob& P, const Lds& sh, RowRegs<NX, SLOTS, REG>& S,
-                                        RowRegs<NX, SLOTS, REG && !DINV>& Ph,
+template <int NX, int SLOTS, bool REG, bool WAVE, bool DINV, bool TAIL, typename ResidualFn>
+__device__ __forceinline__ int qp_solve(const Prob& P, const Lds& sh,
+                                        RowRegs<NX, SLOTS - TAIL, REG>& S,
+                                        RowRegs<NX, SLOTS - TAIL, REG && !DINV>& Ph,
                                         const float (&g)[SLOTS],
                                         float (&hi)[SLOTS], float (&lo)[SLOTS], int steps,
                                         int maxit, float tol, float abs_tol, float ref_tol,
                                         float kkt_tol, int& flags, int& redi, int maxit_flag,
                                         int unmet_flag, ResidualFn residual) {
-  const float etab = precond_norm<NX, SLOTS, REG, WAVE, DINV>(P, sh, S, Ph, g, redi);
+  const float etab = precond_norm<NX, SLOTS, REG, WAVE, DINV, TAIL>(P, sh, S, Ph, g, redi);
   int its = 0;
   float prev_r2 = 0.f;
   bool met = false;
@@ -2908,13 +3055,38 @@ __device__ __forceinline__ int qp_solve(const Prob& P, const Lds& sh, RowRegs<NX
     // register rows are read again after the residual, which is a call at
     // nx > 4: held across it they would be saved through scratch and
     // reloaded from there at every use inside the PCG loop
-    if constexpr (REG && !WAVE) load_reg_rows<NX, SLOTS, REG, WAVE, DINV>(P, S, Ph);
+    if constexpr (REG && !WAVE) load_reg_rows<NX, SLOTS, REG, WAVE, DINV, TAIL>(P, S, Ph);
+    if constexpr (TAIL) {
+      // the multipliers wait in the workspace while the PCG runs: in
+      // registers they would crowd out the rows (the PCG loop's fences keep
+      // the compiler from carrying them across it)
+      const int tid = threadIdx.x, BT = block_threads<TAIL>();
+      float* st = P.W + P.L.stash;
+#pragma unroll
+      for (int s = 0; s < SLOTS; ++s) {
+        const int rho = row_of<NX, false>(s, tid, BT);
+        if (rho < P.R) {
+          st[rho] = hi[s];
+          st[P.R + rho] = lo[s];
+        }
+      }
+    }
     if (k == 0)
-      its += pcg<NX, SLOTS, REG, WAVE, DINV>(P, sh, S, Ph, rr, d, maxit, 0.f,
+      its += pcg<NX, SLOTS, REG, WAVE, DINV, TAIL>(P, sh, S, Ph, rr, d, maxit, 0.f,
                                        fmaxf(tol * tol * etab, abs_tol), flags, redi, maxit_flag);
     else
-      its += pcg<NX, SLOTS, REG, WAVE, DINV>(P, sh, S, Ph, rr, d, maxit, ref_tol, 0.f, flags, redi,
+      its += pcg<NX, SLOTS, REG, WAVE, DINV, TAIL>(P, sh, S, Ph, rr, d, maxit, ref_tol, 0.f, flags, redi,
                                        maxit_flag);
+    if constexpr (TAIL) {
+      const int tid = threadIdx.x, BT = block_threads<TAIL>();
+      const float* st = P.W + P.L.stash;
+#pragma unroll
+      for (int s = 0; s < SLOTS; ++s) {
+        const int rho = row_of<NX, false>(s, tid, BT);
+        hi[s] = rho < P.R ? st[rho] : 0.f;
+        lo[s] = rho < P.R ? st[P.R + rho] : 0.f;
+      }
+    }
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
       const double v = ((double)hi[s] + (double)lo[s]) + (double)d[s];
@@ -3027,13 +3199,16 @@ __device__ __forceinline__ ResNorms residual_rows(const ProbRec* rec, const KArg
 // registers, 2 = rows in registers in the wave-block layout (one wave per
 // problem, a lane per stage block, neighbour values by DPP wave shifts),
 // 3 = rows of S^ in registers and the preconditioner in factored form with
-// the inverted diagonal blocks in LDS (half the registers of mode 1).
+// the inverted diagonal blocks in LDS (half the registers of mode 1), 4 = as
+// 3 with the rows of the last value slot in LDS (for problems a few rows
+// past what the register slots of the largest register-resident launch hold).
 template <int NX, int SLOTS, int MAXBT, int MODE>
 __global__ __launch_bounds__(MAXBT) void forward_kernel(KArgs a) {
-  constexpr bool REG = MODE != 0, WAVE = MODE == 2, DINV = MODE == 3;
+  constexpr bool REG = MODE != 0, WAVE = MODE == 2, DINV = MODE >= 3, TAIL = MODE == 4;
   static_assert(!WAVE || (MAXBT == 64 && SLOTS % NX == 0), "wave-block kernels are one wave");
+  static_assert(!TAIL || MAXBT == kTailThreads, "LDS-row kernels: kTailThreads threads");
   extern __shared__ float smem[];
-  const int tid = threadIdx.x, BT = blockDim.x;
+  const int tid = threadIdx.x, BT = block_threads<TAIL>();
   LsParams lp;
 #pragma unroll
   for (int i = 0; i < kMaxAlphas; ++i) lp.alphas[i] = a.alphas[i];
@@ -3057,17 +3232,17 @@ __global__ __launch_bounds__(MAXBT) void forward_kernel(KArgs a) {
     const int maxit = a.pcg_max_iter > 0 ? a.pcg_max_iter : P.R + 10;
     const float rtol = a.refine_tol > 0.f ? a.refine_tol : a.pcg_tol;
     for (int k = 0; k < a.sqp_iters; ++k) {
-      RowRegs<NX, SLOTS, REG> S;
-      RowRegs<NX, SLOTS, REG && !DINV> Ph;
+      RowRegs<NX, SLOTS - TAIL, REG> S;
+      RowRegs<NX, SLOTS - TAIL, REG && !DINV> Ph;
       float g[SLOTS];
       if constexpr (WAVE) {
         fwd_form<NX>(rec, a.data, a.ws, k == 0);
         if (wave_blocks<NX, SLOTS>(P, S, Ph, g, k == a.sqp_iters - 1)) flags |= DMPC_PROB_NONPD;
       } else {
         if (fwd_blocks<NX>(rec, a.data, a.ws, k == 0)) flags |= DMPC_PROB_NONPD;
-        load_rows<NX, SLOTS, REG, WAVE, DINV>(P, sh, S, Ph, g);
+        load_rows<NX, SLOTS, REG, WAVE, DINV, TAIL>(P, sh, S, Ph, g);
       }
-      pcg_total += qp_solve<NX, SLOTS, REG, WAVE, DINV>(
+      pcg_total += qp_solve<NX, SLOTS, REG, WAVE, DINV, TAIL>(
           P, sh, S, Ph, g, lam, lo, a.refine_steps, maxit, a.pcg_tol, a.pcg_abs_tol, rtol,
           a.kkt_tol, flags, redi, DMPC_PROB_PCG_MAXITER,
           k == a.sqp_iters - 1 ? DMPC_PROB_KKT_UNMET : 0,
@@ -3109,19 +3284,20 @@ __global__ __launch_bounds__(MAXBT) void forward_kernel(KArgs a) {
 
 template <int NX, int SLOTS, int MAXBT, int MODE>
 __global__ __launch_bounds__(MAXBT) void backward_kernel(KArgs a) {
-  constexpr bool REG = MODE != 0, WAVE = MODE == 2, DINV = MODE == 3;
+  constexpr bool REG = MODE != 0, WAVE = MODE == 2, DINV = MODE >= 3, TAIL = MODE == 4;
   static_assert(!WAVE || (MAXBT == 64 && SLOTS % NX == 0), "wave-block kernels are one wave");
+  static_assert(!TAIL || MAXBT == kTailThreads, "LDS-row kernels: kTailThreads threads");
   extern __shared__ float smem[];
-  const int tid = threadIdx.x, BT = blockDim.x;
+  const int tid = threadIdx.x, BT = block_threads<TAIL>();
   for (int pi = a.first + blockIdx.x; pi < a.first + a.count; pi += gridDim.x) {
     const ProbRec* rec = a.recs + pi;
     const Prob P = make_prob<NX>(*rec, a.data, a.ws);
     const Lds sh = lds_of<NX>(smem, P);
     bwd_begin<NX>(rec, a.data, a.ws, a.dl);
-    RowRegs<NX, SLOTS, REG> S;
-    RowRegs<NX, SLOTS, REG && !DINV> Ph;
+    RowRegs<NX, SLOTS - TAIL, REG> S;
+    RowRegs<NX, SLOTS - TAIL, REG && !DINV> Ph;
     float g[SLOTS], lt[SLOTS], lo[SLOTS];
-    load_rows<NX, SLOTS, REG, WAVE, DINV>(P, sh, S, Ph, g);
+    load_rows<NX, SLOTS, REG, WAVE, DINV, TAIL>(P, sh, S, Ph, g);
     const float* alv = a.adj + rec->sol_off + P.R + P.TM;
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
@@ -3133,7 +3309,7 @@ __global__ __launch_bounds__(MAXBT) void backward_kernel(KArgs a) {
     int flags = 0, redi = 0;
     const int maxit = a.bwd_max_iter > 0 ? a.bwd_max_iter : P.R + 10;
     const float rtol = a.refine_tol > 0.f ? a.refine_tol : a.bwd_tol;
-    const int its = qp_solve<NX, SLOTS, REG, WAVE, DINV>(
+    const int its = qp_solve<NX, SLOTS, REG, WAVE, DINV, TAIL>(
         P, sh, S, Ph, g, lt, lo, a.refine_steps, maxit, a.bwd_tol, 0.f, rtol, a.kkt_tol, flags,
         redi, DMPC_PROB_BWD_PCG_MAXITER, DMPC_PROB_BWD_KKT_UNMET,
         [&](const float (&h)[SLOTS], const float (&l)[SLOTS], float (&rr)[SLOTS]) {

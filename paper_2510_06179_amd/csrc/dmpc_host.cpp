@@ -205,10 +205,18 @@ struct Variant {
 const Variant kVariants[] = {
     {1, 64, 1},  {2, 64, 1},  {4, 64, 1},  {8, 64, 1},  {1, 128, 1}, {2, 128, 1}, {4, 128, 1},
     {8, 128, 1}, {1, 256, 1}, {2, 256, 1}, {4, 256, 1}, {1, 512, 1}, {2, 512, 1}, {1, 1024, 1},
-    {3, 512, 1}, {2, 1024, 1}, {2, 640, 3}, {2, 1024, 3},
+    {3, 512, 1}, {2, 1024, 1}, {2, 640, 3}, {2, 1024, 3}, {5, 512, 4},
     {4, 256, 0}, {8, 256, 0}, {8, 512, 0}, {2, 1024, 0}, {4, 1024, 0}, {8, 1024, 0}, {12, 1024, 0},
     {2, 64, 2},  {4, 64, 2},  {8, 64, 2},
 };
+
+// Whether a problem's LDS regions fit a workgroup under a mapping (the bulk
+// regions move to the workspace when they do not fit; the inverted diagonal
+// blocks and LDS rows of modes 3 and 4 cannot).
+bool lds_fits(const dmpc_problem& p, int slots, int bt, int reg) {
+  const int f = rec_flags(p.T, p.nx, p.nu, bt, slots, reg, lin_floats_of(p), 0);
+  return lds_floats(p.T, p.nx, p.nu, bt, slots, f, 0) * (int64_t)sizeof(float) <= kLdsBytes;
+}
 
 // Process-wide tuning table (rows of 7 int32, see dmpc_set_tuning).
 std::mutex g_tune_mu;
@@ -221,7 +229,8 @@ bool tuned_cfg(const dmpc_problem& p, LaunchCfg* c) {
     if (r[0] != p.nx || p.T < r[1] || p.T > r[2]) continue;
     const int slots = r[3], maxbt = r[4], reg = r[5], bt = r[6];
     if (!kernel_available(p.nx, slots, maxbt, reg)) continue;
-    if ((int64_t)slots * bt < R) continue;
+    if ((int64_t)slots * bt < R || !lds_fits(p, slots, bt, reg)) continue;
+    if (reg == 4 && bt != kTailThreads) continue;
     *c = LaunchCfg{p.nx, slots, maxbt, reg, bt, 0, 0};
     return true;
   }
@@ -244,9 +253,16 @@ bool choose_cfg(const dmpc_problem& p, int force_bt, LaunchCfg* c) {
       bt = (int)((R + 64LL * v.slots - 1) / (64LL * v.slots) * 64);
       if (bt > v.maxbt) continue;
     }
+    // LDS-row kernels run with exactly kTailThreads threads
+    if (v.reg == 4) {
+      if (force_bt > 0 && force_bt != kTailThreads) continue;
+      bt = kTailThreads;
+      if (R > (int64_t)v.slots * bt) continue;
+    }
+    if (!lds_fits(p, v.slots, bt, v.reg)) continue;
     const int waves = bt / 64;
     // wave-block variants (reg = 2) need no LDS round trip per row product
-    const double row_w = v.reg == 2 ? 0.7 : (v.reg == 3 ? 1.4 : (v.reg ? 1.0 : 3.0));
+    const double row_w = v.reg == 2 ? 0.7 : (v.reg >= 3 ? 1.4 : (v.reg ? 1.0 : 3.0));
     const double cost = waves * (per_wave + v.slots * per_row * row_w) + 1e-3 * v.maxbt;
     if (cost < best) {
       best = cost;
@@ -363,10 +379,13 @@ dmpc_status dmpc_set_tuning(const int32_t* rows, int32_t n_rows) {
     for (int j = 0; j < 7; ++j) t[i][j] = rows[7 * i + j];
     const auto& r = t[i];
     if (!nx_supported(r[0]) || r[1] < 1 || r[2] < r[1] || r[3] < 1 || r[4] < 64 ||
-        r[4] > 1024 || r[5] < 0 || r[5] > 3 || r[6] < 64 || r[6] > r[4] || r[6] % 64 != 0)
+        r[4] > 1024 || r[5] < 0 || r[5] > 4 || r[6] < 64 || r[6] > r[4] || r[6] % 64 != 0)
       return DMPC_ERR_INVALID_ARG;
     // a wave-block row is one wave holding whole stage blocks per lane
     if (r[5] == 2 && (r[4] != 64 || r[3] % r[0] != 0)) return DMPC_ERR_INVALID_ARG;
+    // an LDS-row row runs kTailThreads threads and has a register slot
+    if (r[5] == 4 && (r[4] != kTailThreads || r[6] != kTailThreads || r[3] < 2))
+      return DMPC_ERR_INVALID_ARG;
   }
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune.swap(t);

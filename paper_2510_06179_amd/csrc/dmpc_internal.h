@@ -33,6 +33,9 @@ constexpr int kRecBulkWs = 2;    // iterate, QP solution, multipliers and the li
 constexpr int kRecLinLds = 4;    // the QP data (see lin_floats) is read from an LDS copy
 constexpr int kRecDinvLds = 8;   // the inverted diagonal Schur blocks live in LDS (the kernel
                                  // applies the preconditioner in factored form)
+constexpr int kRecTailLds = 16;  // with kRecDinvLds: the Schur rows of a thread's last value
+                                 // slot live in LDS (rows past the register slots)
+constexpr int kTailThreads = 512; // workgroup size of the kRecTailLds kernels
 constexpr int kComputeUnits = 256;   // CUs of an MI355X
 
 // Device record of one problem (96 bytes).
@@ -57,6 +60,7 @@ struct WsLayout {
   int64_t xlin, ulin;             // last linearisation point
   int64_t g;                      // right-hand side of the Schur system [N*nx]
   int64_t bulk;                   // kRecBulkWs: the regions that do not fit LDS (-1 if unused)
+  int64_t stash;                  // kRecTailLds: the multipliers (hi, lo) during a PCG [2][N*nx]
   int64_t total;
 };
 
@@ -105,6 +109,12 @@ DMPC_HD inline WsLayout ws_layout(int T, int nx, int nu, int dyn, int flags) {
   } else {
     L.bulk = -1;
   }
+  if (flags & kRecTailLds) {
+    o = align_up(o, 4);
+    L.stash = o; o += 2 * R;
+  } else {
+    L.stash = -1;
+  }
   L.total = align_up(o, kAlignFloats);
   return L;
 }
@@ -144,7 +154,23 @@ DMPC_HD inline int64_t bulk_floats(int64_t N, int64_t R, int64_t TM) {
 // every slot when the rows are in registers: those PCG loops have no row
 // guard), and 2 nx of zero pad.
 DMPC_HD inline int64_t win_floats(int64_t R, int nx, int bt, int slots, int flags) {
+  if (flags & kRecTailLds) {   // register slots unguarded, the LDS slot up to R
+    const int64_t reg = (int64_t)(slots - 1) * bt;
+    return a4h((R > reg ? R : reg) + 3 * nx);
+  }
   return a4h(((flags & kRecRegRows) ? (int64_t)slots * bt : R) + 3 * nx);
+}
+// Rows held in LDS under kRecTailLds (those past the register slots) and the
+// LDS stride of one such row: its 3 nx Schur coefficients padded to a
+// multiple of four floats with an odd number of 16-byte words, so that the
+// 16-byte reads of consecutive lanes fall on distinct banks.
+DMPC_HD inline int64_t tail_rows(int64_t R, int bt, int slots, int flags) {
+  if (!(flags & kRecTailLds)) return 0;
+  const int64_t t = R - (int64_t)(slots - 1) * bt;
+  return t > 0 ? t : 0;
+}
+DMPC_HD constexpr int tail_stride(int nx) {
+  return ((3 * nx + 3) / 4) % 2 == 1 ? (3 * nx + 3) / 4 * 4 : (3 * nx + 3) / 4 * 4 + 4;
 }
 // QP data read by every phase of an SQP iteration, copied to LDS under
 // kRecLinLds (one region after the reductions): an image of the workspace
@@ -175,6 +201,7 @@ DMPC_HD inline int64_t lds_floats(int T, int nx, int nu, int bt, int slots, int 
          + ((flags & kRecDinvLds) ? (4 * (int64_t)bt > R * nx ? 4 * (int64_t)bt : R * nx)
                                   : 4 * (int64_t)bt)
          + 128                           // reductions
+         + tail_rows(R, bt, slots, flags) * tail_stride(nx)   // kRecTailLds rows
          + ((flags & kRecLinLds) ? lin : 0);
 }
 // Record flags of a problem run by a kernel variant: register rows as the
@@ -183,7 +210,8 @@ DMPC_HD inline int64_t lds_floats(int T, int nx, int nu, int bt, int slots, int 
 // stays within lin_budget bytes (0: never).
 DMPC_HD inline int rec_flags(int T, int nx, int nu, int bt, int slots, int reg, int64_t lin,
                              int64_t lin_budget) {
-  const int f = (reg ? kRecRegRows : 0) | (reg == 3 ? kRecDinvLds : 0);
+  const int f = (reg ? kRecRegRows : 0) | (reg >= 3 ? kRecDinvLds : 0) |
+                (reg == 4 ? kRecTailLds : 0);
   if (lds_floats(T, nx, nu, bt, slots, f, 0) * 4 > kLdsBytes) return f | kRecBulkWs;
   if (lds_floats(T, nx, nu, bt, slots, f | kRecLinLds, lin) * 4 <= lin_budget) return f | kRecLinLds;
   return f;

@@ -164,8 +164,9 @@ def test_variants_cover_every_state_size():
     v = _lib.variants()
     assert {r[0] for r in v} == {2, 3, 4, 8, 12, 16, 32}
     for nx, slots, maxbt, reg in v:
-        assert slots >= 1 and maxbt % 64 == 0 and 64 <= maxbt <= 1024 and reg in (0, 1, 2, 3)
+        assert slots >= 1 and maxbt % 64 == 0 and 64 <= maxbt <= 1024 and reg in (0, 1, 2, 3, 4)
         assert reg != 2 or (maxbt == 64 and slots % nx == 0)
+        assert reg != 4 or (maxbt == 512 and slots >= 2)
 
 
 def test_mapping_holds_the_rows_and_respects_forced_threads():
@@ -213,9 +214,27 @@ def test_tuning_table_overrides_the_cost_model():
         assert _mapping(p, block_threads=64)[1][3] == 64
         # malformed rows are refused and leave the table as it was
         for bad in [(5, 1, 9, 1, 64, 1, 64), (4, 9, 1, 1, 64, 1, 64), (4, 1, 9, 1, 64, 4, 64), (4, 1, 9, 2, 64, 2, 64),
-                    (4, 1, 9, 1, 64, 1, 96), (4, 1, 9, 1, 64, 1, 128)]:
+                    (4, 1, 9, 1, 64, 1, 96), (4, 1, 9, 1, 64, 1, 128), (16, 1, 9, 5, 512, 4, 448),
+                    (16, 1, 9, 1, 512, 4, 512), (16, 1, 9, 5, 512, 5, 512)]:
             with pytest.raises(_lib.DmpcError):
                 _lib.install_tuning([bad])
         assert _saved_tuning() == [(4, 40, 60, 1, 256, 1, 256)]
+    finally:
+        _lib.install_tuning(saved)
+
+
+def test_lds_row_mapping_only_where_its_lds_fits():
+    """Kernels with the last slot's Schur rows in LDS (register_rows = 4) hold
+    T = 128, nx = 16 (2064 rows: four register slots of 512 threads and 16 LDS
+    rows); one more stage no longer fits the LDS, and the table row is
+    skipped."""
+    saved = _saved_tuning()
+    try:
+        rng = np.random.default_rng(3)
+        _lib.install_tuning([(16, 1, 1000, 5, 512, 4, 512)])
+        assert _mapping(W.ltv_problem(rng, 128, 16, 4)) == (_lib.DMPC_OK, (5, 512, 4, 512))
+        assert _mapping(W.ltv_problem(rng, 100, 16, 2)) == (_lib.DMPC_OK, (5, 512, 4, 512))
+        rc, m = _mapping(W.ltv_problem(rng, 129, 16, 4))
+        assert rc == _lib.DMPC_OK and m[2] != 4 and m[0] * m[3] >= 130 * 16
     finally:
         _lib.install_tuning(saved)

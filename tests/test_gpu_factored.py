@@ -3,7 +3,9 @@ the preconditioner of Eq. S_Phiinv in factored form (Phi^-1 = D^-1 - D^-1 E
 D^-1 with the inverted diagonal blocks in LDS), forced through the tuning
 table: forward (several SQP iterations) and backward against the FP64 oracle
 on ragged shapes (rows not a multiple of the workgroup, one or two rows per
-thread), and JVP."""
+thread), and JVP.  The same for the variant whose last value slot keeps its
+Schur rows in LDS (T = 128, nx = 16: 16 rows past four register slots of 512
+threads; T = 127: none; shorter horizons: register slots partly empty)."""
 import numpy as np
 import pytest
 import torch
@@ -51,10 +53,32 @@ def _shapes(seed):
     return probs
 
 
+@pytest.fixture
+def lds_row_table():
+    saved = _saved_table()
+    _lib.install_tuning([(16, 1, 128, 5, 512, 4, 512)])
+    yield
+    _lib.install_tuning(saved)
+
+
 def test_factored_forward_backward_jvp(factored_table):
-    probs = _shapes(11)
+    _check(_shapes(11), 3)
+
+
+def test_lds_row_slot_forward_backward_jvp(lds_row_table):
+    rng = np.random.default_rng(21)
+    probs = []
+    for T, nu in [(128, 4), (128, 2), (127, 3), (100, 2), (9, 4)]:
+        p = W.ltv_problem(rng, T, 16, nu)
+        p["c"] = W.f32(rng.normal(0, 0.1, size=(T, 16)))
+        p["init"] = "rollout"
+        probs.append(p)
+    _check(probs, 4)
+
+
+def _check(probs, mode):
     s, res, status, info = gpu_solve(probs, sqp_iters=3, pcg_tol=1e-6, bwd_pcg_tol=1e-6)
-    assert all(d["register_rows"] == 3 for d in s.describe()), s.describe()
+    assert all(d["register_rows"] == mode for d in s.describe()), s.describe()
     assert not np.any(status & BAD), (status, info)
     cots = W.loss_cotangents(probs, seed=11, with_lambda=True)
     dl = torch.from_numpy(batch.sol_like(s.packed, [(c["gx"], c["gu"], c["glam"]) for c in cots]))
