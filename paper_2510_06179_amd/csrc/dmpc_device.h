@@ -643,6 +643,27 @@ __device__ __forceinline__ double dcost_u1(const Prob& P, int t, int l, float ub
   return (double)sp_weight(P, t, P.nw + l) * ub * ((double)uq - (double)ub);
 }
 
+// State cost of one row (t, i) and its directional derivative: the stage
+// costs above are sums of these over i.
+template <int NX>
+__device__ __forceinline__ double cost_x1(const Prob& P, int t, int i, double x, int cost_kind) {
+  if (cost_kind == DMPC_COST_DIAG) {
+    const double qd = P.costp[t * NX + i], q = P.costp[P.N * NX + t * NX + i];
+    return 0.5 * qd * x * x + q * x;
+  }
+  const double d = x - (double)sp_xref<NX>(P)[i];
+  return 0.5 * (double)sp_wx<NX>(P, t, i) * d * d;
+}
+template <int NX>
+__device__ __forceinline__ double dcost_x1(const Prob& P, int t, int i, double xb, double dx,
+                                           int cost_kind) {
+  if (cost_kind == DMPC_COST_DIAG) {
+    const double qd = P.costp[t * NX + i], q = P.costp[P.N * NX + t * NX + i];
+    return (qd * xb + q) * dx;
+  }
+  return (double)sp_wx<NX>(P, t, i) * (xb - (double)sp_xref<NX>(P)[i]) * dx;
+}
+
 // Parameters of a nonlinear model, loaded once per phase into registers
 // (through the scalar unit: the block is the same for the whole workgroup).
 struct ModelPar {
@@ -2203,6 +2224,67 @@ __device__ __forceinline__ void ls_tasks(const Prob& P, const ModelPar& mp, cons
   }
 }
 
+// Line-search sums for linear dynamics (App. A.3, Alg. linesearch): the
+// stage costs and dynamics defects are sums over state rows (t, i) and input
+// rows (t, l), so threads take rows instead of stages.  Along a candidate
+// step the next state is affine in alpha, (A_t x + B_t u + c_t)(alpha) = a0 +
+// alpha a1, with a0 and a1 formed once per row in double.  cs[a], ds[a]: this
+// thread's share of the cost and of the l1 defect at candidate a (a = 0: the
+// current point); dn: its share of the cost's directional derivative.
+template <int NX, int COST>
+__device__ __forceinline__ void ls_rows_ltv(const Prob& P, const LsParams& lp, const float* xbar,
+                                            const float* xp, const float* ubar, const float* up,
+                                            double (&cs)[kMaxAlphas + 1],
+                                            double (&ds)[kMaxAlphas + 1], double& dn) {
+  const int tid = threadIdx.x, BT = blockDim.x;
+  const int T = P.T, m = P.m, R = P.R, TM = P.TM;
+  double al[kMaxAlphas + 1];
+#pragma unroll
+  for (int a = 0; a <= kMaxAlphas; ++a) {
+    al[a] = a <= lp.n ? (double)pick_alpha(lp, a) : 0.0;
+    cs[a] = ds[a] = 0.0;
+  }
+  dn = 0.0;
+  for (int rho = tid; rho < R; rho += BT) {
+    const int t = rho / NX, i = rho - t * NX;
+    const double xb = xbar[rho], dx = (double)xp[rho] - xb;
+#pragma unroll
+    for (int a = 0; a <= kMaxAlphas; ++a)
+      cs[a] += a <= lp.n ? cost_x1<NX>(P, t, i, xb + al[a] * dx, COST) : 0.0;
+    dn += dcost_x1<NX>(P, t, i, xb, dx, COST);
+    if (t < T) {
+      const float* Ai = P.A + (t * NX + i) * NX;
+      const float* Bi = P.B + (t * NX + i) * m;
+      const float* xs = xbar + t * NX;
+      const float* qs = xp + t * NX;
+      double a0 = P.c[rho], a1 = 0.0;
+#pragma unroll
+      for (int j = 0; j < NX; ++j) {
+        const double xj = xs[j];
+        a0 += (double)Ai[j] * xj;
+        a1 += (double)Ai[j] * ((double)qs[j] - xj);
+      }
+      for (int l = 0; l < m; ++l) {
+        const double ul = ubar[t * m + l];
+        a0 += (double)Bi[l] * ul;
+        a1 += (double)Bi[l] * ((double)up[t * m + l] - ul);
+      }
+      const double xn = xbar[rho + NX];
+      const double e0 = xn - a0, e1 = ((double)xp[rho + NX] - xn) - a1;
+#pragma unroll
+      for (int a = 0; a <= kMaxAlphas; ++a) ds[a] += a <= lp.n ? fabs(e0 + al[a] * e1) : 0.0;
+    }
+  }
+  for (int idx = tid; idx < TM; idx += BT) {
+    const int t = idx / m, l = idx - t * m;
+    const double ub = ubar[idx], du = (double)up[idx] - ub;
+#pragma unroll
+    for (int a = 0; a <= kMaxAlphas; ++a)
+      cs[a] += a <= lp.n ? cost_u1<NX>(P, t, l, ub + al[a] * du, COST) : 0.0;
+    dn += dcost_u1<NX>(P, t, l, ubar[idx], up[idx], COST);
+  }
+}
+
 // QP primal solution (Eq. schur:xu, user signs; accumulated in double):
 //   x_t = -Q_t^-1 (q_t + lambda_t - A_t' lambda_{t+1}),  u_t = -R_t^-1 (r_t - B_t' lambda_{t+1})
 // lambda from the LDS window w0; then the line search (App. A.3, Alg.
@@ -2263,61 +2345,106 @@ __device__ __forceinline__ LsResult fwd_recover_ls_body(const ProbRec* rec, cons
   double* tc = (double*)(bulk_base(smem, P) + C.ls);
   double* td = tc + (kMaxAlphas + 1) * N;
   double* res = td + (kMaxAlphas + 1) * N;
-  const ModelPar mp = load_par(P);
   double dn = 0.0;   // directional derivative of the cost at the current point (row 0 tasks)
-  const LsTaskArgs ta{xbar, xp, ubar, up, tc, td, &dn, ntask, na};
-  // (the cart-pole has nx = 4 and the bicycle nx = 8: other pairs are refused
-  // when the problem is validated)
-  if (P.dyn == DMPC_DYN_LTV) {
-    if (P.cost == DMPC_COST_DIAG) ls_tasks<NX, DMPC_DYN_LTV, DMPC_COST_DIAG>(P, mp, lp, ta);
-    else ls_tasks<NX, DMPC_DYN_LTV, DMPC_COST_SOFTPLUS>(P, mp, lp, ta);
-  } else {
-    constexpr int D = NX == 4 ? DMPC_DYN_CARTPOLE : DMPC_DYN_BICYCLE;
-    if constexpr (NX == 4 || NX == 8) {
-      if (P.cost == DMPC_COST_DIAG) ls_tasks<NX, D, DMPC_COST_DIAG>(P, mp, lp, ta);
-      else ls_tasks<NX, D, DMPC_COST_SOFTPLUS>(P, mp, lp, ta);
-    }
-  }
-  __syncthreads();
   // per-candidate sums in a fixed order, held in registers by every thread
   double csum[kMaxAlphas + 1], dsum[kMaxAlphas + 1];
-  if (nwv == 1) {
-    // one wave: every row's partial sums first (rows past the last read the
-    // last row and count zero), then all the wave sums in one branch-free
-    // block, side by side
-#pragma unroll
-    for (int r = 0; r <= kMaxAlphas; ++r) csum[r] = dsum[r] = 0.0;
-    for (int tt = tid; tt < N; tt += 64) {
-#pragma unroll
-      for (int r = 0; r <= kMaxAlphas; ++r) {
-        const int rr = r < nrow ? r : nrow - 1;
-        const double cv = tc[rr * N + tt], dv = td[rr * N + tt];
-        csum[r] += r < nrow ? cv : 0.0;
-        dsum[r] += r < nrow ? dv : 0.0;
-      }
-    }
+  if (P.dyn == DMPC_DYN_LTV) {
+    // rows in parallel; wave sums, then the waves' partial sums in order
+    if (P.cost == DMPC_COST_DIAG)
+      ls_rows_ltv<NX, DMPC_COST_DIAG>(P, lp, xbar, xp, ubar, up, csum, dsum, dn);
+    else
+      ls_rows_ltv<NX, DMPC_COST_SOFTPLUS>(P, lp, xbar, xp, ubar, up, csum, dsum, dn);
     wave_sum_d_multi<kMaxAlphas + 1>(csum);
     wave_sum_d_multi<kMaxAlphas + 1>(dsum);
-  } else {
-    const int lane = tid & 63;
-    for (int r = tid >> 6; r < nrow; r += nwv) {
-      double c0 = 0.0, d0 = 0.0;
-      for (int tt = lane; tt < N; tt += 64) {
-        c0 += tc[r * N + tt];
-        d0 += td[r * N + tt];
+    constexpr int K = kMaxAlphas + 1;
+    if (nwv > 1 && 2 * K * nwv <= 2 * K * (N + 1)) {   // (the region holds 2 K (N + 1) doubles)
+      if ((tid & 63) == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          tc[(tid >> 6) * 2 * K + k] = csum[k];
+          tc[(tid >> 6) * 2 * K + K + k] = dsum[k];
+        }
       }
-      c0 = wave_sum_d(c0);
-      d0 = wave_sum_d(d0);
-      if (lane == 0) {
-        res[r] = c0;
-        res[kMaxAlphas + 1 + r] = d0;
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        double c0 = 0.0, d0 = 0.0;
+        for (int w = 0; w < nwv; ++w) {
+          c0 += tc[w * 2 * K + k];
+          d0 += tc[w * 2 * K + K + k];
+        }
+        csum[k] = c0;
+        dsum[k] = d0;
+      }
+      __syncthreads();
+    } else if (nwv > 1) {
+      double* rd = (double*)(smem + C.red);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if ((tid & 63) == 0) rd[tid >> 6] = csum[k];
+        if ((tid & 63) == 0) rd[16 + (tid >> 6)] = dsum[k];
+        __syncthreads();
+        double c0 = 0.0, d0 = 0.0;
+        for (int w = 0; w < nwv; ++w) {
+          c0 += rd[w];
+          d0 += rd[16 + w];
+        }
+        csum[k] = c0;
+        dsum[k] = d0;
+        __syncthreads();
+      }
+    }
+  } else {
+    const ModelPar mp = load_par(P);
+    const LsTaskArgs ta{xbar, xp, ubar, up, tc, td, &dn, ntask, na};
+    // (the cart-pole has nx = 4 and the bicycle nx = 8: other pairs are refused
+    // when the problem is validated)
+    {
+      constexpr int D = NX == 4 ? DMPC_DYN_CARTPOLE : DMPC_DYN_BICYCLE;
+      if constexpr (NX == 4 || NX == 8) {
+        if (P.cost == DMPC_COST_DIAG) ls_tasks<NX, D, DMPC_COST_DIAG>(P, mp, lp, ta);
+        else ls_tasks<NX, D, DMPC_COST_SOFTPLUS>(P, mp, lp, ta);
       }
     }
     __syncthreads();
+    if (nwv == 1) {
+      // one wave: every row's partial sums first (rows past the last read the
+      // last row and count zero), then all the wave sums in one branch-free
+      // block, side by side
 #pragma unroll
-    for (int r = 0; r <= kMaxAlphas; ++r) {
-      csum[r] = r < nrow ? res[r] : 0.0;
-      dsum[r] = r < nrow ? res[kMaxAlphas + 1 + r] : 0.0;
+      for (int r = 0; r <= kMaxAlphas; ++r) csum[r] = dsum[r] = 0.0;
+      for (int tt = tid; tt < N; tt += 64) {
+#pragma unroll
+        for (int r = 0; r <= kMaxAlphas; ++r) {
+          const int rr = r < nrow ? r : nrow - 1;
+          const double cv = tc[rr * N + tt], dv = td[rr * N + tt];
+          csum[r] += r < nrow ? cv : 0.0;
+          dsum[r] += r < nrow ? dv : 0.0;
+        }
+      }
+      wave_sum_d_multi<kMaxAlphas + 1>(csum);
+      wave_sum_d_multi<kMaxAlphas + 1>(dsum);
+    } else {
+      const int lane = tid & 63;
+      for (int r = tid >> 6; r < nrow; r += nwv) {
+        double c0 = 0.0, d0 = 0.0;
+        for (int tt = lane; tt < N; tt += 64) {
+          c0 += tc[r * N + tt];
+          d0 += td[r * N + tt];
+        }
+        c0 = wave_sum_d(c0);
+        d0 = wave_sum_d(d0);
+        if (lane == 0) {
+          res[r] = c0;
+          res[kMaxAlphas + 1 + r] = d0;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r <= kMaxAlphas; ++r) {
+        csum[r] = r < nrow ? res[r] : 0.0;
+        dsum[r] = r < nrow ? res[kMaxAlphas + 1 + r] : 0.0;
+      }
     }
   }
   const double num = block_sum_d(dn, (double*)(smem + C.red), nwv);
@@ -2989,27 +3116,30 @@ __device__ __forceinline__ void load_reg_rows(const Prob& P, RowRegs<NX, SLOTS -
 
 // Loads this thread's rows (Schur, preconditioner, right-hand side); TAIL:
 // the Schur rows past the register slots into LDS.
+// (lds_kept: the LDS copies of an earlier SQP iteration still hold, as for
+// linear dynamics with diagonal costs, whose blocks do not change)
 template <int NX, int SLOTS, bool REG, bool WAVE, bool DINV, bool TAIL>
 __device__ __forceinline__ void load_rows(const Prob& P, const Lds& sh,
                                           RowRegs<NX, SLOTS - TAIL, REG>& S,
                                           RowRegs<NX, SLOTS - TAIL, REG && !DINV>& Ph,
-                                          float (&g)[SLOTS]) {
+                                          float (&g)[SLOTS], bool lds_kept = false) {
   const int tid = threadIdx.x, BT = block_threads<TAIL>();
   const float* gv = P.W + P.L.g;
-  if constexpr (TAIL) {
-    const float* blk = P.W + P.L.blk;
-    const int base = (SLOTS - 1) * BT, nt = P.R - base;
-    for (int e = tid; e < nt * 3 * NX; e += BT) {
-      const int k = e / (3 * NX), j = e - k * (3 * NX);
-      sh.tail[k * tail_stride(NX) + j] = blk[blk_at<NX>(base + k, j)];
+  if (!lds_kept) {   // (uniform over the workgroup)
+    if constexpr (TAIL) {
+      const float* blk = P.W + P.L.blk;
+      const int base = (SLOTS - 1) * BT, nt = P.R - base;
+      for (int e = tid; e < nt * 3 * NX; e += BT) {
+        const int k = e / (3 * NX), j = e - k * (3 * NX);
+        sh.tail[k * tail_stride(NX) + j] = blk[blk_at<NX>(base + k, j)];
+      }
     }
-  }
-  if constexpr (DINV) {
-    // the inverted diagonal blocks (row-major per stage: row rho at rho NX)
-    const float4* src = reinterpret_cast<const float4*>(P.W + P.L.Dinv);
-    float4* dst = reinterpret_cast<float4*>(sh.dinv);
-    for (int e = tid; e < P.R * NX / 4; e += BT) dst[e] = src[e];
-    __syncthreads();
+    if constexpr (DINV) {
+      // the inverted diagonal blocks (row-major per stage: row rho at rho NX)
+      static_assert(NX % 4 == 0, "factored preconditioner: nx a multiple of 4");
+      copy_block<true>(sh.dinv, P.W + P.L.Dinv, P.R * NX);
+      __syncthreads();
+    }
   }
 #pragma unroll
   for (int s = 0; s < SLOTS; ++s) {
@@ -3240,7 +3370,10 @@ __global__ __launch_bounds__(MAXBT) void forward_kernel(KArgs a) {
         if (wave_blocks<NX, SLOTS>(P, S, Ph, g, k == a.sqp_iters - 1)) flags |= DMPC_PROB_NONPD;
       } else {
         if (fwd_blocks<NX>(rec, a.data, a.ws, k == 0)) flags |= DMPC_PROB_NONPD;
-        load_rows<NX, SLOTS, REG, WAVE, DINV, TAIL>(P, sh, S, Ph, g);
+        // linear dynamics, diagonal costs: the assembly of the first
+        // iteration stays (see fwd_blocks_body), and so do its LDS copies
+        const bool kept = k > 0 && P.dyn == DMPC_DYN_LTV && P.cost == DMPC_COST_DIAG;
+        load_rows<NX, SLOTS, REG, WAVE, DINV, TAIL>(P, sh, S, Ph, g, kept);
       }
       pcg_total += qp_solve<NX, SLOTS, REG, WAVE, DINV, TAIL>(
           P, sh, S, Ph, g, lam, lo, a.refine_steps, maxit, a.pcg_tol, a.pcg_abs_tol, rtol,
