@@ -1725,13 +1725,25 @@ __device__ __forceinline__ float offdiag_dot(const float* coef, const float* win
   return a0 + a2;
 }
 
+// Orders a wave's LDS stores before its later LDS loads of other lanes' data
+// (a wave executes its LDS instructions in order; this keeps the compiler
+// from moving them).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // z = Phi^-1 v with the preconditioner in factored form: the blocks of
 // Eq. S_Phiinv are D_t^-1 on the diagonal and -D_t^-1 E_{t,t+-1} D_{t+-1}^-1
 // off it, that is Phi^-1 = D^-1 - D^-1 E D^-1 with E the off-diagonal blocks
 // of S^.  So w = D^-1 v, u = v - E w, z = D^-1 u: the inverted diagonal
 // blocks from LDS, E from the Schur rows the thread holds, three exchanges
 // through two windows (wa, wb).  Rows past R (register rows are zero there)
-// give zeros.
+// give zeros.  When nx divides the wave size, the rows of a stage are
+// consecutive lanes of one wave, so the two D^-1 products read only their own
+// wave's values and need no workgroup barrier before them (wa is read only by
+// the wave that wrote those entries).
 template <int NX, int SLOTS, bool TAIL>
 __device__ __forceinline__ void apply_precond_factored(const Prob& P, const Lds& sh, float* wa,
                                                        float* wb,
@@ -1741,8 +1753,10 @@ __device__ __forceinline__ void apply_precond_factored(const Prob& P, const Lds&
   const int tid = loop_tid<TAIL>(), BT = block_threads<TAIL>(), R = P.R;
   constexpr int RS = SLOTS - TAIL;
   float w[SLOTS];
+  constexpr bool STAGE_IN_WAVE = 64 % NX == 0;
   publish<NX, SLOTS, true, false, TAIL>(wa, v, R);
-  __syncthreads();
+  if constexpr (STAGE_IN_WAVE) wave_sync();
+  else __syncthreads();
 #pragma unroll
   for (int s = 0; s < SLOTS; ++s) {
     const int rho = row_of<NX, false>(s, tid, BT);
@@ -1770,7 +1784,8 @@ __device__ __forceinline__ void apply_precond_factored(const Prob& P, const Lds&
   }
   // (every read of wa happened before the barrier above)
   publish<NX, SLOTS, true, false, TAIL>(wa, u, R);
-  __syncthreads();
+  if constexpr (STAGE_IN_WAVE) wave_sync();
+  else __syncthreads();
 #pragma unroll
   for (int s = 0; s < SLOTS; ++s) {
     const int rho = row_of<NX, false>(s, tid, BT);
