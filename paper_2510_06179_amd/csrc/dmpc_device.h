@@ -1689,17 +1689,29 @@ __device__ __forceinline__ float pcg_sum(float part, const Lds& sh, int& redi, i
   return block_sum(part, sh.red + 64 * (redi++ & 1), nwv);
 }
 
-// Row product of the inverted diagonal block D_t^-1 (row rho, in LDS) with
-// the window values of block t.
+// LDS layout of the inverted diagonal blocks: row rho of D_t^-1 at rho NX,
+// its 16-byte chunks permuted by dinv_swz(rho) (chunk j at j ^ swz).  With an
+// even number of chunks per row the 16-byte reads of consecutive rows (lanes)
+// would fall on the same banks every few lanes; the permutation spreads the
+// 16 lanes of a read over all banks.
 template <int NX>
-__device__ __forceinline__ float dinv_dot(const float* drow, const float* wblk) {
+__device__ __forceinline__ int dinv_swz(int rho) {
+  constexpr int C = NX / 4;
+  if constexpr (NX % 4 != 0 || C % 2 == 1 || C > 16) return 0;
+  else return (rho / (16 / C)) & (C - 1);
+}
+
+// Row product of the inverted diagonal block D_t^-1 (row rho, in LDS, chunks
+// permuted by swz) with the window values of block t.
+template <int NX>
+__device__ __forceinline__ float dinv_dot(const float* drow, const float* wblk, int swz) {
   float a0 = 0.f, a1 = 0.f;
   if constexpr (NX % 4 == 0) {
     const float4* d4 = reinterpret_cast<const float4*>(drow);
     const float4* w4 = reinterpret_cast<const float4*>(wblk);
 #pragma unroll
     for (int j = 0; j < NX / 4; ++j) {
-      const float4 d = d4[j], w = w4[j];
+      const float4 d = d4[j ^ swz], w = w4[j];
       a0 = fmaf(d.x, w.x, a0);
       a1 = fmaf(d.y, w.y, a1);
       a0 = fmaf(d.z, w.z, a0);
@@ -1761,7 +1773,7 @@ __device__ __forceinline__ void apply_precond_factored(const Prob& P, const Lds&
   for (int s = 0; s < SLOTS; ++s) {
     const int rho = row_of<NX, false>(s, tid, BT);
     const int t = rho / NX;
-    w[s] = rho < R ? dinv_dot<NX>(sh.dinv + rho * NX, wa + NX + t * NX) : 0.f;
+    w[s] = rho < R ? dinv_dot<NX>(sh.dinv + rho * NX, wa + NX + t * NX, dinv_swz<NX>(rho)) : 0.f;
     slot_fence<TAIL>(w[s]);
   }
   publish<NX, SLOTS, true, false, TAIL>(wb, w, R);
@@ -1790,7 +1802,7 @@ __device__ __forceinline__ void apply_precond_factored(const Prob& P, const Lds&
   for (int s = 0; s < SLOTS; ++s) {
     const int rho = row_of<NX, false>(s, tid, BT);
     const int t = rho / NX;
-    z[s] = rho < R ? dinv_dot<NX>(sh.dinv + rho * NX, wa + NX + t * NX) : 0.f;
+    z[s] = rho < R ? dinv_dot<NX>(sh.dinv + rho * NX, wa + NX + t * NX, dinv_swz<NX>(rho)) : 0.f;
     slot_fence<TAIL>(z[s]);
   }
 }
@@ -3150,9 +3162,28 @@ __device__ __forceinline__ void load_rows(const Prob& P, const Lds& sh,
       }
     }
     if constexpr (DINV) {
-      // the inverted diagonal blocks (row-major per stage: row rho at rho NX)
+      // the inverted diagonal blocks (row-major per stage: row rho at rho NX,
+      // chunks permuted as dinv_swz says), four 16-byte loads in flight
       static_assert(NX % 4 == 0, "factored preconditioner: nx a multiple of 4");
-      copy_block<true>(sh.dinv, P.W + P.L.Dinv, P.R * NX);
+      constexpr int CH = NX / 4;
+      const float4* s4 = reinterpret_cast<const float4*>(P.W + P.L.Dinv);
+      float4* d4 = reinterpret_cast<float4*>(sh.dinv);
+      const int n4 = P.R * CH;
+      int e = tid;
+      for (; e + 3 * BT < n4; e += 4 * BT) {
+        float4 v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = s4[e + q * BT];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int f = e + q * BT, rho = f / CH, j = f - rho * CH;
+          d4[rho * CH + (j ^ dinv_swz<NX>(rho))] = v[q];
+        }
+      }
+      for (; e < n4; e += BT) {
+        const int rho = e / CH, j = e - rho * CH;
+        d4[rho * CH + (j ^ dinv_swz<NX>(rho))] = s4[e];
+      }
       __syncthreads();
     }
   }
