@@ -8,13 +8,14 @@ namespace dmpc {
 
 // (values per thread, launch bound, mode: 0 rows read from the workspace,
 // 1 rows in registers, 2 rows in registers in the wave-block layout, 3 Schur
-// rows in registers and the inverted diagonal blocks in LDS)
+// rows in registers and the inverted diagonal blocks in LDS, 4 as 3 with the
+// last slot's rows in LDS)
 static const KEntry kEntries[] = {
     DMPC_K(12, 1, 64, 1), DMPC_K(12, 2, 64, 1), DMPC_K(12, 1, 128, 1), DMPC_K(12, 2, 128, 1),
     DMPC_K(12, 1, 256, 1), DMPC_K(12, 2, 256, 1), DMPC_K(12, 1, 512, 1), DMPC_K(12, 2, 512, 1),
     DMPC_K(12, 1, 1024, 1),
     DMPC_K(12, 4, 256, 0), DMPC_K(12, 8, 256, 0), DMPC_K(12, 8, 512, 0),
-    DMPC_K(12, 2, 1024, 3),
+    DMPC_K(12, 2, 1024, 3), DMPC_K(12, 4, 512, 4),
 };
 
 const KEntry* kernel_entries_nx12(int* n) {

@@ -15,7 +15,7 @@ static const KEntry kEntries[] = {
     DMPC_K(16, 1, 256, 1), DMPC_K(16, 2, 256, 1), DMPC_K(16, 1, 512, 1), DMPC_K(16, 2, 512, 1),
     DMPC_K(16, 1, 1024, 1),
     DMPC_K(16, 4, 256, 0), DMPC_K(16, 8, 256, 0), DMPC_K(16, 8, 512, 0), DMPC_K(16, 4, 1024, 0),
-    DMPC_K(16, 2, 640, 3), DMPC_K(16, 2, 1024, 3), DMPC_K(16, 5, 512, 4),
+    DMPC_K(16, 2, 640, 3), DMPC_K(16, 2, 1024, 3), DMPC_K(16, 5, 512, 4), DMPC_K(16, 3, 512, 4), DMPC_K(16, 2, 512, 4),
 };
 
 const KEntry* kernel_entries_nx16(int* n) {

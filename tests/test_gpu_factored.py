@@ -61,6 +61,16 @@ def lds_row_table():
     _lib.install_tuning(saved)
 
 
+@pytest.fixture
+def lds_row_mixed_table():
+    # nx = 12 with three register slots; nx = 16 with one and two
+    saved = _saved_table()
+    _lib.install_tuning([(12, 1, 132, 4, 512, 4, 512), (16, 1, 35, 2, 512, 4, 512),
+                         (16, 36, 67, 3, 512, 4, 512)])
+    yield
+    _lib.install_tuning(saved)
+
+
 def test_factored_forward_backward_jvp(factored_table):
     _check(_shapes(11), 3)
 
@@ -71,6 +81,20 @@ def test_lds_row_slot_forward_backward_jvp(lds_row_table):
     for T, nu in [(128, 4), (128, 2), (127, 3), (100, 2), (9, 4)]:
         p = W.ltv_problem(rng, T, 16, nu)
         p["c"] = W.f32(rng.normal(0, 0.1, size=(T, 16)))
+        p["init"] = "rollout"
+        probs.append(p)
+    _check(probs, 4)
+
+
+def test_lds_row_slot_other_widths(lds_row_mixed_table):
+    # nx = 12: T = 128 (12 LDS rows), 100 (register slots partly empty), 5;
+    # nx = 16: T = 32 and 64 (16 LDS rows each), 20, 50
+    rng = np.random.default_rng(23)
+    probs = []
+    for T, nx, nu in [(128, 12, 4), (100, 12, 2), (5, 12, 3), (32, 16, 2), (20, 16, 4),
+                      (64, 16, 3), (50, 16, 2)]:
+        p = W.ltv_problem(rng, T, nx, nu)
+        p["c"] = W.f32(rng.normal(0, 0.1, size=(T, nx)))
         p["init"] = "rollout"
         probs.append(p)
     _check(probs, 4)
