@@ -190,8 +190,9 @@ def ltv_bytes(T, n, m):
     return 4 * (T * (n * n + n * m + n) + 2 * N * n + 2 * T * m + n) + 4 * (2 * N * n + T * m)
 
 
-KERNEL_SOURCES = ("dmpc_device.h", "dmpc_internal.h", "dmpc_launch.hip", "dmpc_k4.hip",
-                  "dmpc_k8.hip", "dmpc_k12.hip", "dmpc_k16.hip")
+KERNEL_SOURCES = ("csrc/dmpc_device.h", "csrc/dmpc_internal.h", "csrc/dmpc_launch.hip",
+                  "csrc/dmpc_k4.hip", "csrc/dmpc_k8.hip", "csrc/dmpc_k12.hip", "csrc/dmpc_k16.hip",
+                  "csrc/dmpc_host.cpp", "tuning_gfx950.json")   # (the mapping decides the kernels)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "forward_pass_uneven_ltv_traffic.json")
 
 
@@ -199,7 +200,7 @@ def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2510_06179_amd", "csrc", name), "rb") as f:
+        with open(os.path.join(ROOT, "paper_2510_06179_amd", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
