@@ -397,7 +397,7 @@ __device__ __forceinline__ Carve carve(int R, int TM, int N, int nx, int bt, int
   // inverted diagonal blocks share the region (staged after the assembly)
   C.piv = o;
   C.dinv = o;
-  o += (flags & kRecDinvLds) ? (4 * bt > R * nx ? 4 * bt : R * nx) : 4 * bt;
+  o += (int)piv_floats(R, nx, bt, flags);
   C.red = o;   o += 128;
   C.tail = o;                         // kRecTailLds: Schur rows past the register slots
   o += (int)tail_rows(R, bt, slots, flags) * tail_stride(nx);
@@ -1169,6 +1169,148 @@ __device__ __forceinline__ void publish(float* w, const float (&v)[SLOTS], int R
   }
 }
 
+// Orders a wave's LDS stores before its later LDS loads of other lanes' data
+// (a wave executes its LDS instructions in order; this keeps the compiler
+// from moving them).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ===========================================================================
+// Scaled Schur system (kRecScaled).  With D_t = L_t L_t' (Cholesky, in double
+// from the float blocks) and L = blkdiag(L_t), the PCG of Alg. pcg on S^
+// with the stair preconditioner Phi^-1 = D^-1 - D^-1 E D^-1 (Eq. S_Phiinv)
+// is the same iteration, in the variables x~ = L' x, as the PCG on
+// L^-1 S^ L^-T = I + E~ with the preconditioner L' Phi^-1 L = I - E~, where
+// E~_{t,t-1} = L_t^-1 S_{t,t-1} L_{t-1}^-T (and E~_{t-1,t} its transpose):
+// the same step lengths and the same stopping test (r'Phi^-1 r is unchanged).
+// A row then needs only its two scaled off-diagonal blocks.  Writes L_t^-1
+// (float, row-major per stage) to the Dinv region and row rho of E~ (the
+// blocks at t-1 and t+1) to coefficients 3 nx .. 5 nx of the saved row.
+// xch: LDS exchange of BT doubles.  Returns true (in every thread) on a
+// non-positive pivot.
+// ===========================================================================
+template <int NX>
+__device__ __forceinline__ bool scaled_blocks(const Prob& P, double* xch) {
+  static_assert(64 % NX == 0, "scaled system: the rows of a stage in one wave");
+  const int tid = threadIdx.x, BT = blockDim.x, R = P.R;
+  const int N = P.N;
+  float* blk = P.W + P.L.blk;
+  double* Lid = (double*)(P.W + P.L.Lid);
+  double* Pd = (double*)(P.W + P.L.Pd);
+  float* Li = P.W + P.L.Dinv;
+  double* xg = xch + (tid / NX) * NX;   // exchange row of this thread's stage group
+  int bad = 0;
+  // (1), (2) per group of BT rows: a stage's NX rows are consecutive lanes of
+  // one wave (NX divides the wave size, BT is a multiple of it), so the
+  // factorisation exchanges values through LDS under wave-level ordering
+  // only; rows past R factor identity blocks and store nothing
+  for (int base = 0; base < R; base += BT) {
+    const int rho = base + tid;
+    const bool live = rho < R;
+    const int t = rho / NX, i = rho - t * NX;
+    double a[NX];
+#pragma unroll
+    for (int j = 0; j < NX; ++j)
+      a[j] = live ? (double)blk[blk_at<NX>(rho, NX + j)] : (j == i ? 1.0 : 0.0);
+    // Cholesky, one column per step: lane i ends with row i of L_t in a[0..i]
+#pragma unroll
+    for (int k = 0; k < NX; ++k) {
+      if (i == k) {
+        if (!(a[k] > 0.0)) bad = 1;
+        xg[k] = sqrt(a[k] > 0.0 ? a[k] : 1.0);
+      }
+      wave_sync();
+      const double lkk = xg[k];
+      if (i == k) a[k] = lkk;
+      if (i > k) {
+        a[k] /= lkk;
+        xg[i] = a[k];
+      }
+      wave_sync();
+#pragma unroll
+      for (int j = k + 1; j < NX; ++j)
+        if (j <= i) a[j] -= a[k] * xg[j];
+      wave_sync();
+    }
+    // L_t^-1 by columns: lane i gets column i (x[m], zero for m < i); row m
+    // of L_t comes from lane m through the exchange row
+    double x[NX];
+#pragma unroll
+    for (int m = 0; m < NX; ++m) {
+      if (i == m) {
+#pragma unroll
+        for (int q = 0; q <= m; ++q) xg[q] = a[q];
+      }
+      wave_sync();
+      double acc = m == i ? 1.0 : 0.0;
+#pragma unroll
+      for (int q = 0; q < m; ++q) acc -= xg[q] * x[q];
+      x[m] = m < i ? 0.0 : acc / xg[m];
+      wave_sync();
+    }
+    if (live) {
+#pragma unroll
+      for (int m = 0; m < NX; ++m) {
+        Lid[((int64_t)t * NX + m) * NX + i] = x[m];
+        Li[((int64_t)t * NX + m) * NX + i] = (float)x[m];
+      }
+    }
+  }
+  __syncthreads();
+  // (3) P_t = S_{t,t-1} L_{t-1}^-T and P'_t = S_{t,t+1} L_{t+1}^-T, row k by
+  // thread (t, k) from the first and third blocks of its Schur row
+  double* Pn = Pd + (int64_t)N * NX * NX;
+  for (int rho = tid; rho < R; rho += BT) {
+    const int t = rho / NX;
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const int tn = side == 0 ? t - 1 : t + 1;
+      if (tn < 0 || tn >= N) continue;
+      const double* Xn = Lid + (int64_t)tn * NX * NX;
+      double o[NX];
+#pragma unroll
+      for (int m = 0; m < NX; ++m) o[m] = blk[blk_at<NX>(rho, 2 * side * NX + m)];
+      double* out = (side == 0 ? Pd : Pn) + (int64_t)rho * NX;
+#pragma unroll
+      for (int j = 0; j < NX; ++j) {
+        double acc = 0.0;
+#pragma unroll
+        for (int m = 0; m <= j; ++m) acc += o[m] * Xn[j * NX + m];
+        out[j] = acc;
+      }
+    }
+  }
+  __syncthreads();
+  // (4) E~_{t,t-1} = L_t^-1 P_t and E~_{t,t+1} = L_t^-1 P'_t, row i by thread
+  // (t, i); blocks past either end are zero
+  for (int rho = tid; rho < R; rho += BT) {
+    const int t = rho / NX;
+    const double* Xi = Lid + (int64_t)rho * NX;
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const int tn = side == 0 ? t - 1 : t + 1;
+      double acc[NX];
+#pragma unroll
+      for (int j = 0; j < NX; ++j) acc[j] = 0.0;
+      if (tn >= 0 && tn < N) {
+        const double* Pt = (side == 0 ? Pd : Pn) + (int64_t)t * NX * NX;
+#pragma unroll
+        for (int k = 0; k < NX; ++k) {   // (X_t is lower triangular: Xi[k] = 0 for k > i)
+          const double xk = Xi[k];
+#pragma unroll
+          for (int j = 0; j < NX; ++j) acc[j] += xk * Pt[k * NX + j];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < NX; ++j) blk[blk_at<NX>(rho, (3 + side) * NX + j)] = (float)acc[j];
+    }
+  }
+  return __syncthreads_or(bad) != 0;
+}
+
 // ===========================================================================
 // Symmetric stair preconditioner (Eq. S_Phiinv): Gauss-Jordan inversion of
 // every D_t (rows of a block are handled by consecutive threads; the rows are
@@ -1539,6 +1681,19 @@ __device__ __forceinline__ float tail_offdiag(const float* coef, const float* wi
   return a0 + a2;
 }
 
+// Scaled off-diagonal row product (kRecScaled rows: E~_{t,t-1}[i,:] at
+// coef[0, nx), E~_{t,t+1}[i,:] at coef[nx, 2 nx)), window at block t-1.
+template <int NX>
+__device__ __forceinline__ float scaled_dot(const float* coef, const float* win) {
+  float a0 = 0.f, a2 = 0.f;
+#pragma unroll
+  for (int j = 0; j < NX; ++j) {
+    a0 = fmaf(coef[j], win[j], a0);
+    a2 = fmaf(coef[NX + j], win[2 * NX + j], a2);
+  }
+  return a0 + a2;
+}
+
 // Ordering fence on a computed value: the value is complete before the fence
 // and no memory access moves across it.  The LDS-row kernels hold four
 // register rows per thread in a 256-register budget; fences after each slot's
@@ -1632,8 +1787,10 @@ __device__ __forceinline__ void wave_neighbours(const float (&v)[SLOTS], float (
 // rows of S^ (PH = false) or Phi^-1 (PH = true): through an LDS window
 // (publish, barrier, row products) or, in the wave-block layout, with the
 // neighbour values in registers (same products in the same order).
-// (TAIL: the last slot's rows are the LDS rows at `tail`.)
-template <int NX, int SLOTS, bool REG, bool WAVE, bool PH, bool TAIL = false>
+// (TAIL: the last slot's rows are the LDS rows at `tail`.  SC: the scaled
+// system, out = v + E~ v for the Schur product and v - E~ v for the
+// preconditioner.)
+template <int NX, int SLOTS, bool REG, bool WAVE, bool PH, bool TAIL = false, bool SC = false>
 __device__ __forceinline__ void apply_rows(const Prob& P, float* win,
                                            RowRegs<NX, SLOTS - TAIL, REG>& M,
                                            const float (&v)[SLOTS], float (&out)[SLOTS],
@@ -1670,7 +1827,12 @@ __device__ __forceinline__ void apply_rows(const Prob& P, float* win,
           if (rho < R) out[s] = tail_dot<NX>(tail_row<NX>(tail, rho - RS * BT), win + (rho / NX) * NX);
         }
       }
-      if (!lds_row && row_live<REG>(s, rho, R, BT)) {
+      if constexpr (SC) {
+        if (row_live<REG>(s, rho, R, BT)) {
+          const float e = scaled_dot<NX>(M[s], win + (rho / NX) * NX);
+          out[s] = PH ? v[s] - e : v[s] + e;
+        }
+      } else if (!lds_row && row_live<REG>(s, rho, R, BT)) {
         const int t = rho / NX;
         const int sr = s < RS ? s : 0;   // (s < RS here)
         const float* coef = PH ? coefP<NX, RS, REG>(P, M, sr, rho) : coefS<NX, RS, REG>(P, M, sr, rho);
@@ -1737,15 +1899,6 @@ __device__ __forceinline__ float offdiag_dot(const float* coef, const float* win
   return a0 + a2;
 }
 
-// Orders a wave's LDS stores before its later LDS loads of other lanes' data
-// (a wave executes its LDS instructions in order; this keeps the compiler
-// from moving them).
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // z = Phi^-1 v with the preconditioner in factored form: the blocks of
 // Eq. S_Phiinv are D_t^-1 on the diagonal and -D_t^-1 E_{t,t+-1} D_{t+-1}^-1
 // off it, that is Phi^-1 = D^-1 - D^-1 E D^-1 with E the off-diagonal blocks
@@ -1808,12 +1961,15 @@ __device__ __forceinline__ void apply_precond_factored(const Prob& P, const Lds&
 }
 
 // z = Phi^-1 v: the explicit preconditioner rows, or (DINV) the factored form.
-template <int NX, int SLOTS, bool REG, bool WAVE, bool DINV, bool TAIL>
+template <int NX, int SLOTS, bool REG, bool WAVE, bool DINV, bool TAIL, bool SC = false>
 __device__ __forceinline__ void apply_precond(const Prob& P, const Lds& sh,
                                               RowRegs<NX, SLOTS - TAIL, REG>& S,
                                               RowRegs<NX, SLOTS - TAIL, REG && !DINV>& Ph,
                                               const float (&v)[SLOTS], float (&z)[SLOTS]) {
-  if constexpr (DINV) {
+  if constexpr (SC) {
+    static_assert(REG && !WAVE && !DINV && !TAIL, "scaled system: register rows");
+    apply_rows<NX, SLOTS, REG, WAVE, true, false, true>(P, sh.w1, S, v, z);
+  } else if constexpr (DINV) {
     static_assert(REG && !WAVE, "factored preconditioner: register rows, workgroup layout");
     apply_precond_factored<NX, SLOTS, TAIL>(P, sh, sh.w1, sh.w2, S, v, z);
   } else {
@@ -1823,14 +1979,14 @@ __device__ __forceinline__ void apply_precond(const Prob& P, const Lds& sh,
 }
 
 // v' Phi^-1 v for a vector held in this thread's rows.
-template <int NX, int SLOTS, bool REG, bool WAVE, bool DINV, bool TAIL>
+template <int NX, int SLOTS, bool REG, bool WAVE, bool DINV, bool TAIL, bool SC = false>
 __device__ __forceinline__ float precond_norm(const Prob& P, const Lds& sh,
                                               RowRegs<NX, SLOTS - TAIL, REG>& S,
                                               RowRegs<NX, SLOTS - TAIL, REG && !DINV>& Ph,
                                               const float (&v)[SLOTS], int& redi) {
   const int nwv = (block_threads<TAIL>() + 63) >> 6;
   float z[SLOTS];
-  apply_precond<NX, SLOTS, REG, WAVE, DINV, TAIL>(P, sh, S, Ph, v, z);
+  apply_precond<NX, SLOTS, REG, WAVE, DINV, TAIL, SC>(P, sh, S, Ph, v, z);
   float part = 0.f;
 #pragma unroll
   for (int s = 0; s < SLOTS; ++s) part = fmaf(v[s], z[s], part);
@@ -1842,7 +1998,7 @@ __device__ __forceinline__ float precond_norm(const Prob& P, const Lds& sh,
 // max(rel_tol^2 * rhs'Phi^-1 rhs, abs_thresh), or at the iteration cap.
 // (The warm start of Alg. pcg enters through rhs = g - S^ lambda, which the
 // caller computes in double.)  Returns the iteration count; ORs status bits.
-template <int NX, int SLOTS, bool REG, bool WAVE, bool DINV, bool TAIL>
+template <int NX, int SLOTS, bool REG, bool WAVE, bool DINV, bool TAIL, bool SC = false>
 __device__ __forceinline__ int pcg(const Prob& P, const Lds& sh,
                                    RowRegs<NX, SLOTS - TAIL, REG>& S,
                                    RowRegs<NX, SLOTS - TAIL, REG && !DINV>& Ph,
@@ -1857,7 +2013,7 @@ __device__ __forceinline__ int pcg(const Prob& P, const Lds& sh,
     r[s] = rhs[s];
     d[s] = 0.f;
   }
-  apply_precond<NX, SLOTS, REG, WAVE, DINV, TAIL>(P, sh, S, Ph, r, z);
+  apply_precond<NX, SLOTS, REG, WAVE, DINV, TAIL, SC>(P, sh, S, Ph, r, z);
   float part = 0.f;
 #pragma unroll
   for (int s = 0; s < SLOTS; ++s) {
@@ -1873,7 +2029,7 @@ __device__ __forceinline__ int pcg(const Prob& P, const Lds& sh,
   }
   while (it < maxit && eta > thresh) {
     // y = S^ p, v = p'y, alpha = eta / v
-    apply_rows<NX, SLOTS, REG, WAVE, false, TAIL>(P, sh.w0, S, p, y, sh.tail);
+    apply_rows<NX, SLOTS, REG, WAVE, false, TAIL, SC>(P, sh.w0, S, p, y, sh.tail);
     part = 0.f;
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) part = fmaf(p[s], y[s], part);
@@ -1892,7 +2048,7 @@ __device__ __forceinline__ int pcg(const Prob& P, const Lds& sh,
       r[s] = fmaf(-alpha, y[s], r[s]);
     }
     // r~ = Phi^-1 r, eta' = r'r~
-    apply_precond<NX, SLOTS, REG, WAVE, DINV, TAIL>(P, sh, S, Ph, r, z);
+    apply_precond<NX, SLOTS, REG, WAVE, DINV, TAIL, SC>(P, sh, S, Ph, r, z);
     part = 0.f;
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) part = fmaf(r[s], z[s], part);
@@ -2029,6 +2185,9 @@ __device__ __forceinline__ int fwd_blocks_body(const ProbRec* rec, const float* 
   }
   if constexpr (MX) mfma_diag_blocks<NX>(P, blk);
   __syncthreads();
+  if constexpr (64 % NX == 0) {   // (scaled-system kernels exist for such nx only)
+    if (P.flags & kRecScaled) return scaled_blocks<NX>(P, (double*)(smem + C.piv)) ? 1 : 0;
+  }
   const bool bad = precond_rows<NX>(P, smem + C.piv);
   if constexpr (MX) mfma_precond_blocks<NX>(P, blk, P.W + P.L.Dinv, smem + C.piv);
   return __syncthreads_or(bad ? 1 : 0);
@@ -3122,10 +3281,21 @@ struct KEntry {
 
 // Loads this thread's register rows (Schur and, without the factored
 // preconditioner, preconditioner) from the workspace copy of the assembly.
-template <int NX, int SLOTS, bool REG, bool WAVE, bool DINV, bool TAIL>
+template <int NX, int SLOTS, bool REG, bool WAVE, bool DINV, bool TAIL, bool SC = false>
 __device__ __forceinline__ void load_reg_rows(const Prob& P, RowRegs<NX, SLOTS - TAIL, REG>& S,
                                               RowRegs<NX, SLOTS - TAIL, REG && !DINV>& Ph) {
-  if constexpr (REG) {
+  if constexpr (SC) {
+    // the scaled off-diagonal blocks (coefficients 3 nx .. 5 nx of the row)
+    const int tid = threadIdx.x, BT = blockDim.x;
+    const float* blk = P.W + P.L.blk;
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+      const int rho = row_of<NX, false>(s, tid, BT);
+      const bool ok = rho < P.R;
+#pragma unroll
+      for (int j = 0; j < 2 * NX; ++j) S[s][j] = ok ? blk[blk_at<NX>(rho, 3 * NX + j)] : 0.f;
+    }
+  } else if constexpr (REG) {
     const int tid = threadIdx.x, BT = block_threads<TAIL>();
     const float* blk = P.W + P.L.blk;
 #pragma unroll
@@ -3145,7 +3315,7 @@ __device__ __forceinline__ void load_reg_rows(const Prob& P, RowRegs<NX, SLOTS -
 // the Schur rows past the register slots into LDS.
 // (lds_kept: the LDS copies of an earlier SQP iteration still hold, as for
 // linear dynamics with diagonal costs, whose blocks do not change)
-template <int NX, int SLOTS, bool REG, bool WAVE, bool DINV, bool TAIL>
+template <int NX, int SLOTS, bool REG, bool WAVE, bool DINV, bool TAIL, bool SC = false>
 __device__ __forceinline__ void load_rows(const Prob& P, const Lds& sh,
                                           RowRegs<NX, SLOTS - TAIL, REG>& S,
                                           RowRegs<NX, SLOTS - TAIL, REG && !DINV>& Ph,
@@ -3192,7 +3362,40 @@ __device__ __forceinline__ void load_rows(const Prob& P, const Lds& sh,
     const int rho = row_of<NX, WAVE>(s, tid, BT);
     g[s] = rho < P.R ? gv[rho] : 0.f;
   }
-  load_reg_rows<NX, SLOTS, REG, WAVE, DINV, TAIL>(P, S, Ph);
+  load_reg_rows<NX, SLOTS, REG, WAVE, DINV, TAIL, SC>(P, S, Ph);
+}
+
+// Scaled system (kRecScaled): out = L^-1 v (TRANS = false) or L^-T v, stage by
+// stage (L_t^-1 in the Dinv region, float, zero above its diagonal), through
+// the window w.
+template <int NX, int SLOTS, bool TRANS>
+__device__ __forceinline__ void scale_vec(const Prob& P, float* w, const float (&v)[SLOTS],
+                                          float (&out)[SLOTS]) {
+  const int tid = threadIdx.x, BT = blockDim.x, R = P.R;
+  publish<NX, SLOTS, false, false>(w, v, R);
+  __syncthreads();
+  const float* Li = P.W + P.L.Dinv;
+#pragma unroll
+  for (int s = 0; s < SLOTS; ++s) {
+    const int rho = row_of<NX, false>(s, tid, BT);
+    out[s] = 0.f;
+    if (rho < R) {
+      const int t = rho / NX, i = rho - t * NX;
+      const float* wt = w + NX + t * NX;
+      float acc = 0.f;
+      if constexpr (!TRANS) {
+        const float* row = Li + (int64_t)rho * NX;
+#pragma unroll
+        for (int j = 0; j < NX; ++j) acc = fmaf(row[j], wt[j], acc);
+      } else {
+        const float* col = Li + (int64_t)t * NX * NX + i;
+#pragma unroll
+        for (int j = 0; j < NX; ++j) acc = fmaf(col[j * NX], wt[j], acc);
+      }
+      out[s] = acc;
+    }
+  }
+  __syncthreads();
 }
 
 // One QP solve of the Schur system, mixed precision.  lambda = hi + lo is a
@@ -3203,8 +3406,11 @@ __device__ __forceinline__ void load_rows(const Prob& P, const Lds& sh,
 // paper's relative tolerance); then up to `steps` refinement passes, each to
 // relative tolerance ref_tol.  Passes stop once the residual meets the KKT
 // target (||r||_2 <= kkt_tol ||rhs||_2) -- before pass 0 too, when the warm
-// start already meets it (converged SQP iterates).
-template <int NX, int SLOTS, bool REG, bool WAVE, bool DINV, bool TAIL, typename ResidualFn>
+// start already meets it (converged SQP iterates).  SC: the PCG runs on the
+// scaled system (scaled_blocks), its right-hand side L^-1 r and its solution
+// mapped back by L^-T.
+template <int NX, int SLOTS, bool REG, bool WAVE, bool DINV, bool TAIL, bool SC,
+          typename ResidualFn>
 __device__ __forceinline__ int qp_solve(const Prob& P, const Lds& sh,
                                         RowRegs<NX, SLOTS - TAIL, REG>& S,
                                         RowRegs<NX, SLOTS - TAIL, REG && !DINV>& Ph,
@@ -3213,7 +3419,7 @@ __device__ __forceinline__ int qp_solve(const Prob& P, const Lds& sh,
                                         int maxit, float tol, float abs_tol, float ref_tol,
                                         float kkt_tol, int& flags, int& redi, int maxit_flag,
                                         int unmet_flag, ResidualFn residual) {
-  const float etab = precond_norm<NX, SLOTS, REG, WAVE, DINV, TAIL>(P, sh, S, Ph, g, redi);
+  float etab = 0.f;   // g'Phi^-1 g, formed when pass 0 runs
   int its = 0;
   float prev_r2 = 0.f;
   bool met = false;
@@ -3231,7 +3437,22 @@ __device__ __forceinline__ int qp_solve(const Prob& P, const Lds& sh,
     // register rows are read again after the residual, which is a call at
     // nx > 4: held across it they would be saved through scratch and
     // reloaded from there at every use inside the PCG loop
-    if constexpr (REG && !WAVE) load_reg_rows<NX, SLOTS, REG, WAVE, DINV, TAIL>(P, S, Ph);
+    if constexpr (REG && !WAVE) load_reg_rows<NX, SLOTS, REG, WAVE, DINV, TAIL, SC>(P, S, Ph);
+    if (k == 0) {
+      if constexpr (SC) {
+        float gt[SLOTS];
+        scale_vec<NX, SLOTS, false>(P, sh.w2, g, gt);
+        etab = precond_norm<NX, SLOTS, REG, WAVE, DINV, TAIL, SC>(P, sh, S, Ph, gt, redi);
+      } else {
+        etab = precond_norm<NX, SLOTS, REG, WAVE, DINV, TAIL, SC>(P, sh, S, Ph, g, redi);
+      }
+    }
+    if constexpr (SC) {
+      float rt[SLOTS];
+      scale_vec<NX, SLOTS, false>(P, sh.w2, rr, rt);
+#pragma unroll
+      for (int s = 0; s < SLOTS; ++s) rr[s] = rt[s];
+    }
     if constexpr (TAIL) {
       // the multipliers wait in the workspace while the PCG runs: in
       // registers they would crowd out the rows (the PCG loop's fences keep
@@ -3248,11 +3469,17 @@ __device__ __forceinline__ int qp_solve(const Prob& P, const Lds& sh,
       }
     }
     if (k == 0)
-      its += pcg<NX, SLOTS, REG, WAVE, DINV, TAIL>(P, sh, S, Ph, rr, d, maxit, 0.f,
+      its += pcg<NX, SLOTS, REG, WAVE, DINV, TAIL, SC>(P, sh, S, Ph, rr, d, maxit, 0.f,
                                        fmaxf(tol * tol * etab, abs_tol), flags, redi, maxit_flag);
     else
-      its += pcg<NX, SLOTS, REG, WAVE, DINV, TAIL>(P, sh, S, Ph, rr, d, maxit, ref_tol, 0.f, flags, redi,
-                                       maxit_flag);
+      its += pcg<NX, SLOTS, REG, WAVE, DINV, TAIL, SC>(P, sh, S, Ph, rr, d, maxit, ref_tol, 0.f,
+                                       flags, redi, maxit_flag);
+    if constexpr (SC) {
+      float dd[SLOTS];
+      scale_vec<NX, SLOTS, true>(P, sh.w2, d, dd);
+#pragma unroll
+      for (int s = 0; s < SLOTS; ++s) d[s] = dd[s];
+    }
     if constexpr (TAIL) {
       const int tid = threadIdx.x, BT = block_threads<TAIL>();
       const float* st = P.W + P.L.stash;
@@ -3377,10 +3604,13 @@ __device__ __forceinline__ ResNorms residual_rows(const ProbRec* rec, const KArg
 // 3 = rows of S^ in registers and the preconditioner in factored form with
 // the inverted diagonal blocks in LDS (half the registers of mode 1), 4 = as
 // 3 with the rows of the last value slot in LDS (for problems a few rows
-// past what the register slots of the largest register-resident launch hold).
+// past what the register slots of the largest register-resident launch hold),
+// 5 = the scaled system (scaled_blocks): rows of the two scaled off-diagonal
+// blocks in registers, no preconditioner blocks.
 template <int NX, int SLOTS, int MAXBT, int MODE>
 __global__ __launch_bounds__(MAXBT) void forward_kernel(KArgs a) {
-  constexpr bool REG = MODE != 0, WAVE = MODE == 2, DINV = MODE >= 3, TAIL = MODE == 4;
+  constexpr bool REG = MODE != 0, WAVE = MODE == 2, DINV = MODE == 3 || MODE == 4,
+                 TAIL = MODE == 4, SC = MODE == 5;
   static_assert(!WAVE || (MAXBT == 64 && SLOTS % NX == 0), "wave-block kernels are one wave");
   static_assert(!TAIL || MAXBT == kTailThreads, "LDS-row kernels: kTailThreads threads");
   extern __shared__ float smem[];
@@ -3419,9 +3649,9 @@ __global__ __launch_bounds__(MAXBT) void forward_kernel(KArgs a) {
         // linear dynamics, diagonal costs: the assembly of the first
         // iteration stays (see fwd_blocks_body), and so do its LDS copies
         const bool kept = k > 0 && P.dyn == DMPC_DYN_LTV && P.cost == DMPC_COST_DIAG;
-        load_rows<NX, SLOTS, REG, WAVE, DINV, TAIL>(P, sh, S, Ph, g, kept);
+        load_rows<NX, SLOTS, REG, WAVE, DINV, TAIL, SC>(P, sh, S, Ph, g, kept);
       }
-      pcg_total += qp_solve<NX, SLOTS, REG, WAVE, DINV, TAIL>(
+      pcg_total += qp_solve<NX, SLOTS, REG, WAVE, DINV, TAIL, SC>(
           P, sh, S, Ph, g, lam, lo, a.refine_steps, maxit, a.pcg_tol, a.pcg_abs_tol, rtol,
           a.kkt_tol, flags, redi, DMPC_PROB_PCG_MAXITER,
           k == a.sqp_iters - 1 ? DMPC_PROB_KKT_UNMET : 0,
@@ -3463,7 +3693,8 @@ __global__ __launch_bounds__(MAXBT) void forward_kernel(KArgs a) {
 
 template <int NX, int SLOTS, int MAXBT, int MODE>
 __global__ __launch_bounds__(MAXBT) void backward_kernel(KArgs a) {
-  constexpr bool REG = MODE != 0, WAVE = MODE == 2, DINV = MODE >= 3, TAIL = MODE == 4;
+  constexpr bool REG = MODE != 0, WAVE = MODE == 2, DINV = MODE == 3 || MODE == 4,
+                 TAIL = MODE == 4, SC = MODE == 5;
   static_assert(!WAVE || (MAXBT == 64 && SLOTS % NX == 0), "wave-block kernels are one wave");
   static_assert(!TAIL || MAXBT == kTailThreads, "LDS-row kernels: kTailThreads threads");
   extern __shared__ float smem[];
@@ -3476,7 +3707,7 @@ __global__ __launch_bounds__(MAXBT) void backward_kernel(KArgs a) {
     RowRegs<NX, SLOTS - TAIL, REG> S;
     RowRegs<NX, SLOTS - TAIL, REG && !DINV> Ph;
     float g[SLOTS], lt[SLOTS], lo[SLOTS];
-    load_rows<NX, SLOTS, REG, WAVE, DINV, TAIL>(P, sh, S, Ph, g);
+    load_rows<NX, SLOTS, REG, WAVE, DINV, TAIL, SC>(P, sh, S, Ph, g);
     const float* alv = a.adj + rec->sol_off + P.R + P.TM;
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
@@ -3488,7 +3719,7 @@ __global__ __launch_bounds__(MAXBT) void backward_kernel(KArgs a) {
     int flags = 0, redi = 0;
     const int maxit = a.bwd_max_iter > 0 ? a.bwd_max_iter : P.R + 10;
     const float rtol = a.refine_tol > 0.f ? a.refine_tol : a.bwd_tol;
-    const int its = qp_solve<NX, SLOTS, REG, WAVE, DINV, TAIL>(
+    const int its = qp_solve<NX, SLOTS, REG, WAVE, DINV, TAIL, SC>(
         P, sh, S, Ph, g, lt, lo, a.refine_steps, maxit, a.bwd_tol, 0.f, rtol, a.kkt_tol, flags,
         redi, DMPC_PROB_BWD_PCG_MAXITER, DMPC_PROB_BWD_KKT_UNMET,
         [&](const float (&h)[SLOTS], const float (&l)[SLOTS], float (&rr)[SLOTS]) {

@@ -206,7 +206,7 @@ const Variant kVariants[] = {
     {1, 64, 1},  {2, 64, 1},  {4, 64, 1},  {8, 64, 1},  {1, 128, 1}, {2, 128, 1}, {4, 128, 1},
     {8, 128, 1}, {1, 256, 1}, {2, 256, 1}, {4, 256, 1}, {1, 512, 1}, {2, 512, 1}, {1, 1024, 1},
     {3, 512, 1}, {2, 1024, 1}, {2, 640, 3}, {2, 1024, 3}, {5, 512, 4}, {4, 512, 4},
-    {3, 512, 4}, {2, 512, 4},
+    {3, 512, 4}, {2, 512, 4}, {5, 512, 5}, {4, 512, 5}, {3, 512, 5}, {2, 512, 5},
     {4, 256, 0}, {8, 256, 0}, {8, 512, 0}, {2, 1024, 0}, {4, 1024, 0}, {8, 1024, 0}, {12, 1024, 0},
     {2, 64, 2},  {4, 64, 2},  {8, 64, 2},
 };
@@ -263,7 +263,7 @@ bool choose_cfg(const dmpc_problem& p, int force_bt, LaunchCfg* c) {
     if (!lds_fits(p, v.slots, bt, v.reg)) continue;
     const int waves = bt / 64;
     // wave-block variants (reg = 2) need no LDS round trip per row product
-    const double row_w = v.reg == 2 ? 0.7 : (v.reg >= 3 ? 1.4 : (v.reg ? 1.0 : 3.0));
+    const double row_w = v.reg == 2 ? 0.7 : ((v.reg == 3 || v.reg == 4) ? 1.4 : (v.reg ? 1.0 : 3.0));
     const double cost = waves * (per_wave + v.slots * per_row * row_w) + 1e-3 * v.maxbt;
     if (cost < best) {
       best = cost;
@@ -380,7 +380,7 @@ dmpc_status dmpc_set_tuning(const int32_t* rows, int32_t n_rows) {
     for (int j = 0; j < 7; ++j) t[i][j] = rows[7 * i + j];
     const auto& r = t[i];
     if (!nx_supported(r[0]) || r[1] < 1 || r[2] < r[1] || r[3] < 1 || r[4] < 64 ||
-        r[4] > 1024 || r[5] < 0 || r[5] > 4 || r[6] < 64 || r[6] > r[4] || r[6] % 64 != 0)
+        r[4] > 1024 || r[5] < 0 || r[5] > 5 || r[6] < 64 || r[6] > r[4] || r[6] % 64 != 0)
       return DMPC_ERR_INVALID_ARG;
     // a wave-block row is one wave holding whole stage blocks per lane
     if (r[5] == 2 && (r[4] != 64 || r[3] % r[0] != 0)) return DMPC_ERR_INVALID_ARG;

@@ -36,6 +36,9 @@ constexpr int kRecDinvLds = 8;   // the inverted diagonal Schur blocks live in L
 constexpr int kRecTailLds = 16;  // with kRecDinvLds: the Schur rows of a thread's last value
                                  // slot live in LDS (rows past the register slots)
 constexpr int kTailThreads = 512; // workgroup size of the kRecTailLds kernels
+constexpr int kRecScaled = 32;   // the kernel runs the PCG on the Schur system scaled by the
+                                 // Cholesky factors of its diagonal blocks (register rows of
+                                 // the scaled off-diagonal blocks only)
 constexpr int kComputeUnits = 256;   // CUs of an MI355X
 
 // Device record of one problem (96 bytes).
@@ -61,6 +64,10 @@ struct WsLayout {
   int64_t g;                      // right-hand side of the Schur system [N*nx]
   int64_t bulk;                   // kRecBulkWs: the regions that do not fit LDS (-1 if unused)
   int64_t stash;                  // kRecTailLds: the multipliers (hi, lo) during a PCG [2][N*nx]
+  int64_t Lid, Pd;                // kRecScaled: the inverses of the Cholesky factors L_t of
+                                  // the diagonal blocks [N][nx][nx] and the products
+                                  // S_{t,t-1} L_{t-1}^-T, S_{t,t+1} L_{t+1}^-T [2][N][nx][nx],
+                                  // in double (float offsets, 8-byte aligned)
   int64_t total;
 };
 
@@ -114,6 +121,13 @@ DMPC_HD inline WsLayout ws_layout(int T, int nx, int nu, int dyn, int flags) {
     L.stash = o; o += 2 * R;
   } else {
     L.stash = -1;
+  }
+  if (flags & kRecScaled) {
+    o = align_up(o, 4);
+    L.Lid = o; o += 2 * N * nx * nx;
+    L.Pd = o; o += 4 * N * nx * nx;
+  } else {
+    L.Lid = L.Pd = -1;
   }
   L.total = align_up(o, kAlignFloats);
   return L;
@@ -191,15 +205,21 @@ inline int64_t lin_floats_of(const dmpc_problem& p) {
   return lin_floats(p.T, p.nx, p.nu, p.dyn,
                     cost_block_len(p.T, p.nx, p.nu, p.cost, p.cost_phases, p.cost_nw));
 }
+DMPC_HD inline int64_t piv_floats(int64_t R, int nx, int bt, int flags) {
+  int64_t v = 4 * (int64_t)bt;
+  if ((flags & kRecDinvLds) && R * nx > v) v = R * nx;
+  if ((flags & kRecScaled) && 2 * R > v) v = 2 * R;
+  return v;
+}
 DMPC_HD inline int64_t lds_floats(int T, int nx, int nu, int bt, int slots, int flags,
                                   int64_t lin) {
   const int64_t N = T + 1, R = N * nx, TM = (int64_t)T * nu;
   return ((flags & kRecBulkWs) ? 0 : bulk_floats(N, R, TM))
          + 3 * win_floats(R, nx, bt, slots, flags)   // three padded windows
          // Gauss-Jordan pivot rows, double buffered (kRecDinvLds: the rows of
-         // the inverted diagonal blocks share the region)
-         + ((flags & kRecDinvLds) ? (4 * (int64_t)bt > R * nx ? 4 * (int64_t)bt : R * nx)
-                                  : 4 * (int64_t)bt)
+         // the inverted diagonal blocks share the region; kRecScaled: the
+         // Cholesky exchange, one double row per stage)
+         + piv_floats(R, nx, bt, flags)
          + 128                           // reductions
          + tail_rows(R, bt, slots, flags) * tail_stride(nx)   // kRecTailLds rows
          + ((flags & kRecLinLds) ? lin : 0);
@@ -210,8 +230,8 @@ DMPC_HD inline int64_t lds_floats(int T, int nx, int nu, int bt, int slots, int 
 // stays within lin_budget bytes (0: never).
 DMPC_HD inline int rec_flags(int T, int nx, int nu, int bt, int slots, int reg, int64_t lin,
                              int64_t lin_budget) {
-  const int f = (reg ? kRecRegRows : 0) | (reg >= 3 ? kRecDinvLds : 0) |
-                (reg == 4 ? kRecTailLds : 0);
+  const int f = (reg ? kRecRegRows : 0) | ((reg == 3 || reg == 4) ? kRecDinvLds : 0) |
+                (reg == 4 ? kRecTailLds : 0) | (reg == 5 ? kRecScaled : 0);
   if (lds_floats(T, nx, nu, bt, slots, f, 0) * 4 > kLdsBytes) return f | kRecBulkWs;
   if (lds_floats(T, nx, nu, bt, slots, f | kRecLinLds, lin) * 4 <= lin_budget) return f | kRecLinLds;
   return f;

@@ -164,7 +164,7 @@ def test_variants_cover_every_state_size():
     v = _lib.variants()
     assert {r[0] for r in v} == {2, 3, 4, 8, 12, 16, 32}
     for nx, slots, maxbt, reg in v:
-        assert slots >= 1 and maxbt % 64 == 0 and 64 <= maxbt <= 1024 and reg in (0, 1, 2, 3, 4)
+        assert slots >= 1 and maxbt % 64 == 0 and 64 <= maxbt <= 1024 and reg in (0, 1, 2, 3, 4, 5)
         assert reg != 2 or (maxbt == 64 and slots % nx == 0)
         assert reg != 4 or (maxbt == 512 and slots >= 2)
 
@@ -215,7 +215,7 @@ def test_tuning_table_overrides_the_cost_model():
         # malformed rows are refused and leave the table as it was
         for bad in [(5, 1, 9, 1, 64, 1, 64), (4, 9, 1, 1, 64, 1, 64), (4, 1, 9, 1, 64, 4, 64), (4, 1, 9, 2, 64, 2, 64),
                     (4, 1, 9, 1, 64, 1, 96), (4, 1, 9, 1, 64, 1, 128), (16, 1, 9, 5, 512, 4, 448),
-                    (16, 1, 9, 1, 512, 4, 512), (16, 1, 9, 5, 512, 5, 512)]:
+                    (16, 1, 9, 1, 512, 4, 512), (16, 1, 9, 5, 512, 6, 512)]:
             with pytest.raises(_lib.DmpcError):
                 _lib.install_tuning([bad])
         assert _saved_tuning() == [(4, 40, 60, 1, 256, 1, 256)]

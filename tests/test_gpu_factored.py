@@ -5,7 +5,9 @@ table: forward (several SQP iterations) and backward against the FP64 oracle
 on ragged shapes (rows not a multiple of the workgroup, one or two rows per
 thread), and JVP.  The same for the variant whose last value slot keeps its
 Schur rows in LDS (T = 128, nx = 16: 16 rows past four register slots of 512
-threads; T = 127: none; shorter horizons: register slots partly empty)."""
+threads; T = 127: none; shorter horizons: register slots partly empty), and
+for the PCG on the Schur system scaled by the Cholesky factors of its
+diagonal blocks."""
 import numpy as np
 import pytest
 import torch
@@ -84,6 +86,27 @@ def test_lds_row_slot_forward_backward_jvp(lds_row_table):
         p["init"] = "rollout"
         probs.append(p)
     _check(probs, 4)
+
+
+@pytest.fixture
+def scaled_table():
+    saved = _saved_table()
+    _lib.install_tuning([(16, 1, 159, 5, 512, 5, 512)])
+    yield
+    _lib.install_tuning(saved)
+
+
+def test_scaled_system_forward_backward_jvp(scaled_table):
+    # the Cholesky-scaled Schur system (register_rows 5): full and partly
+    # empty register slots
+    rng = np.random.default_rng(29)
+    probs = []
+    for T, nx, nu in [(128, 16, 4), (64, 16, 2), (31, 16, 3), (9, 16, 4), (159, 16, 2)]:
+        p = W.ltv_problem(rng, T, nx, nu)
+        p["c"] = W.f32(rng.normal(0, 0.1, size=(T, nx)))
+        p["init"] = "rollout"
+        probs.append(p)
+    _check(probs, 5)
 
 
 def test_lds_row_slot_other_widths(lds_row_mixed_table):
