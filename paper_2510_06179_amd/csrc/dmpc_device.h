@@ -1187,7 +1187,7 @@ __device__ __forceinline__ void wave_sync() {
 // E~_{t,t-1} = L_t^-1 S_{t,t-1} L_{t-1}^-T (and E~_{t-1,t} its transpose):
 // the same step lengths and the same stopping test (r'Phi^-1 r is unchanged).
 // A row then needs only its two scaled off-diagonal blocks.  Writes L_t^-1
-// (float, row-major per stage) to the Dinv region and row rho of E~ (the
+// (double, row-major per stage) to the Lid region and row rho of E~ (the
 // blocks at t-1 and t+1) to coefficients 3 nx .. 5 nx of the saved row.
 // xch: LDS exchange of BT doubles.  Returns true (in every thread) on a
 // non-positive pivot.
@@ -1200,7 +1200,6 @@ __device__ __forceinline__ bool scaled_blocks(const Prob& P, double* xch) {
   float* blk = P.W + P.L.blk;
   double* Lid = (double*)(P.W + P.L.Lid);
   double* Pd = (double*)(P.W + P.L.Pd);
-  float* Li = P.W + P.L.Dinv;
   double* xg = xch + (tid / NX) * NX;   // exchange row of this thread's stage group
   int bad = 0;
   // (1), (2) per group of BT rows: a stage's NX rows are consecutive lanes of
@@ -1253,10 +1252,7 @@ __device__ __forceinline__ bool scaled_blocks(const Prob& P, double* xch) {
     }
     if (live) {
 #pragma unroll
-      for (int m = 0; m < NX; ++m) {
-        Lid[((int64_t)t * NX + m) * NX + i] = x[m];
-        Li[((int64_t)t * NX + m) * NX + i] = (float)x[m];
-      }
+      for (int m = 0; m < NX; ++m) Lid[((int64_t)t * NX + m) * NX + i] = x[m];
     }
   }
   __syncthreads();
@@ -3366,15 +3362,16 @@ __device__ __forceinline__ void load_rows(const Prob& P, const Lds& sh,
 }
 
 // Scaled system (kRecScaled): out = L^-1 v (TRANS = false) or L^-T v, stage by
-// stage (L_t^-1 in the Dinv region, float, zero above its diagonal), through
-// the window w.
+// stage, through the window w, accumulated in double with the double L_t^-1
+// (zero above its diagonal): for ill-conditioned diagonal blocks a float
+// copy of L^-1 would limit what the refinement passes can reach.
 template <int NX, int SLOTS, bool TRANS>
 __device__ __forceinline__ void scale_vec(const Prob& P, float* w, const float (&v)[SLOTS],
                                           float (&out)[SLOTS]) {
   const int tid = threadIdx.x, BT = blockDim.x, R = P.R;
   publish<NX, SLOTS, false, false>(w, v, R);
   __syncthreads();
-  const float* Li = P.W + P.L.Dinv;
+  const double* Li = (const double*)(P.W + P.L.Lid);
 #pragma unroll
   for (int s = 0; s < SLOTS; ++s) {
     const int rho = row_of<NX, false>(s, tid, BT);
@@ -3382,17 +3379,17 @@ __device__ __forceinline__ void scale_vec(const Prob& P, float* w, const float (
     if (rho < R) {
       const int t = rho / NX, i = rho - t * NX;
       const float* wt = w + NX + t * NX;
-      float acc = 0.f;
+      double acc = 0.0;
       if constexpr (!TRANS) {
-        const float* row = Li + (int64_t)rho * NX;
+        const double* row = Li + (int64_t)rho * NX;
 #pragma unroll
-        for (int j = 0; j < NX; ++j) acc = fmaf(row[j], wt[j], acc);
+        for (int j = 0; j < NX; ++j) acc = fma(row[j], (double)wt[j], acc);
       } else {
-        const float* col = Li + (int64_t)t * NX * NX + i;
+        const double* col = Li + (int64_t)t * NX * NX + i;
 #pragma unroll
-        for (int j = 0; j < NX; ++j) acc = fmaf(col[j * NX], wt[j], acc);
+        for (int j = 0; j < NX; ++j) acc = fma(col[j * NX], (double)wt[j], acc);
       }
-      out[s] = acc;
+      out[s] = (float)acc;
     }
   }
   __syncthreads();

@@ -207,6 +207,8 @@ const Variant kVariants[] = {
     {8, 128, 1}, {1, 256, 1}, {2, 256, 1}, {4, 256, 1}, {1, 512, 1}, {2, 512, 1}, {1, 1024, 1},
     {3, 512, 1}, {2, 1024, 1}, {2, 640, 3}, {2, 1024, 3}, {5, 512, 4}, {4, 512, 4},
     {3, 512, 4}, {2, 512, 4}, {5, 512, 5}, {4, 512, 5}, {3, 512, 5}, {2, 512, 5},
+    {2, 320, 5}, {1, 320, 5}, {3, 384, 5}, {2, 128, 5}, {3, 192, 5}, {5, 256, 5}, {9, 256, 5},
+    {2, 192, 5}, {3, 128, 5},
     {4, 256, 0}, {8, 256, 0}, {8, 512, 0}, {2, 1024, 0}, {4, 1024, 0}, {8, 1024, 0}, {12, 1024, 0},
     {2, 64, 2},  {4, 64, 2},  {8, 64, 2},
 };

@@ -15,6 +15,8 @@ static const KEntry kEntries[] = {
     DMPC_K(8, 1, 1024, 1), DMPC_K(8, 3, 512, 1), DMPC_K(8, 2, 1024, 1),
     DMPC_K(8, 4, 256, 0), DMPC_K(8, 8, 256, 0), DMPC_K(8, 8, 512, 0),
     DMPC_K(8, 8, 64, 2),
+    DMPC_K(8, 3, 384, 5), DMPC_K(8, 2, 320, 5), DMPC_K(8, 2, 128, 5), DMPC_K(8, 3, 192, 5),
+    DMPC_K(8, 5, 256, 5), DMPC_K(8, 3, 128, 5),
 };
 
 const KEntry* kernel_entries_nx8(int* n) {

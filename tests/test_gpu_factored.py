@@ -109,6 +109,29 @@ def test_scaled_system_forward_backward_jvp(scaled_table):
     _check(probs, 5)
 
 
+@pytest.fixture
+def scaled_small_table():
+    saved = _saved_table()
+    _lib.install_tuning([(16, 1, 23, 2, 192, 5, 192), (16, 24, 35, 3, 192, 5, 192),
+                         (8, 1, 71, 3, 192, 5, 192), (8, 72, 143, 3, 384, 5, 384)])
+    yield
+    _lib.install_tuning(saved)
+
+
+def test_scaled_system_small_workgroups(scaled_small_table):
+    # register_rows 5 on 192 and 384 threads, nx = 16 and 8, full and partly
+    # empty slots
+    rng = np.random.default_rng(31)
+    probs = []
+    for T, nx, nu in [(20, 16, 2), (32, 16, 4), (35, 16, 3), (64, 8, 2), (71, 8, 4), (10, 8, 3),
+                      (128, 8, 4), (100, 8, 2)]:
+        p = W.ltv_problem(rng, T, nx, nu)
+        p["c"] = W.f32(rng.normal(0, 0.1, size=(T, nx)))
+        p["init"] = "rollout"
+        probs.append(p)
+    _check(probs, 5)
+
+
 def test_lds_row_slot_other_widths(lds_row_mixed_table):
     # nx = 12: T = 128 (12 LDS rows), 100 (register slots partly empty), 5;
     # nx = 16: T = 32 and 64 (16 LDS rows each), 20, 50
