@@ -1194,7 +1194,15 @@ __device__ __forceinline__ void wave_sync() {
 // ===========================================================================
 template <int NX>
 __device__ __forceinline__ bool scaled_blocks(const Prob& P, double* xch) {
-  static_assert(64 % NX == 0, "scaled system: the rows of a stage in one wave");
+  // a stage's NX rows are consecutive threads of one group of BT rows (the
+  // host launches these kernels with BT a multiple of nx); when nx divides
+  // the wave size they are lanes of one wave and exchange under wave-level
+  // ordering, otherwise through workgroup barriers
+  constexpr bool STAGE_IN_WAVE = 64 % NX == 0;
+  auto sync = [] {
+    if constexpr (STAGE_IN_WAVE) wave_sync();
+    else __syncthreads();
+  };
   const int tid = threadIdx.x, BT = blockDim.x, R = P.R;
   const int N = P.N;
   float* blk = P.W + P.L.blk;
@@ -1202,10 +1210,8 @@ __device__ __forceinline__ bool scaled_blocks(const Prob& P, double* xch) {
   double* Pd = (double*)(P.W + P.L.Pd);
   double* xg = xch + (tid / NX) * NX;   // exchange row of this thread's stage group
   int bad = 0;
-  // (1), (2) per group of BT rows: a stage's NX rows are consecutive lanes of
-  // one wave (NX divides the wave size, BT is a multiple of it), so the
-  // factorisation exchanges values through LDS under wave-level ordering
-  // only; rows past R factor identity blocks and store nothing
+  // (1), (2) per group of BT rows (whole stages); rows past R factor
+  // identity blocks and store nothing
   for (int base = 0; base < R; base += BT) {
     const int rho = base + tid;
     const bool live = rho < R;
@@ -1221,18 +1227,18 @@ __device__ __forceinline__ bool scaled_blocks(const Prob& P, double* xch) {
         if (!(a[k] > 0.0)) bad = 1;
         xg[k] = sqrt(a[k] > 0.0 ? a[k] : 1.0);
       }
-      wave_sync();
+      sync();
       const double lkk = xg[k];
       if (i == k) a[k] = lkk;
       if (i > k) {
         a[k] /= lkk;
         xg[i] = a[k];
       }
-      wave_sync();
+      sync();
 #pragma unroll
       for (int j = k + 1; j < NX; ++j)
         if (j <= i) a[j] -= a[k] * xg[j];
-      wave_sync();
+      sync();
     }
     // L_t^-1 by columns: lane i gets column i (x[m], zero for m < i); row m
     // of L_t comes from lane m through the exchange row
@@ -1243,12 +1249,12 @@ __device__ __forceinline__ bool scaled_blocks(const Prob& P, double* xch) {
 #pragma unroll
         for (int q = 0; q <= m; ++q) xg[q] = a[q];
       }
-      wave_sync();
+      sync();
       double acc = m == i ? 1.0 : 0.0;
 #pragma unroll
       for (int q = 0; q < m; ++q) acc -= xg[q] * x[q];
       x[m] = m < i ? 0.0 : acc / xg[m];
-      wave_sync();
+      sync();
     }
     if (live) {
 #pragma unroll
@@ -2181,7 +2187,7 @@ __device__ __forceinline__ int fwd_blocks_body(const ProbRec* rec, const float* 
   }
   if constexpr (MX) mfma_diag_blocks<NX>(P, blk);
   __syncthreads();
-  if constexpr (64 % NX == 0) {   // (scaled-system kernels exist for such nx only)
+  if constexpr (NX == 8 || NX == 12 || NX == 16) {   // (nx with scaled-system kernels)
     if (P.flags & kRecScaled) return scaled_blocks<NX>(P, (double*)(smem + C.piv)) ? 1 : 0;
   }
   const bool bad = precond_rows<NX>(P, smem + C.piv);

@@ -208,7 +208,7 @@ const Variant kVariants[] = {
     {3, 512, 1}, {2, 1024, 1}, {2, 640, 3}, {2, 1024, 3}, {5, 512, 4}, {4, 512, 4},
     {3, 512, 4}, {2, 512, 4}, {5, 512, 5}, {4, 512, 5}, {3, 512, 5}, {2, 512, 5},
     {2, 320, 5}, {1, 320, 5}, {3, 384, 5}, {2, 128, 5}, {3, 192, 5}, {5, 256, 5}, {9, 256, 5},
-    {2, 192, 5}, {3, 128, 5},
+    {2, 192, 5}, {3, 128, 5}, {3, 576, 5}, {5, 384, 5}, {5, 192, 5}, {3, 384, 5}, {3, 192, 5},
     {4, 256, 0}, {8, 256, 0}, {8, 512, 0}, {2, 1024, 0}, {4, 1024, 0}, {8, 1024, 0}, {12, 1024, 0},
     {2, 64, 2},  {4, 64, 2},  {8, 64, 2},
 };
@@ -234,6 +234,7 @@ bool tuned_cfg(const dmpc_problem& p, LaunchCfg* c) {
     if (!kernel_available(p.nx, slots, maxbt, reg)) continue;
     if ((int64_t)slots * bt < R || !lds_fits(p, slots, bt, reg)) continue;
     if (reg == 4 && bt != kTailThreads) continue;
+    if (reg == 5 && bt % p.nx != 0) continue;   // (whole stages per group of bt rows)
     *c = LaunchCfg{p.nx, slots, maxbt, reg, bt, 0, 0};
     return true;
   }
@@ -256,6 +257,7 @@ bool choose_cfg(const dmpc_problem& p, int force_bt, LaunchCfg* c) {
       bt = (int)((R + 64LL * v.slots - 1) / (64LL * v.slots) * 64);
       if (bt > v.maxbt) continue;
     }
+    if (v.reg == 5 && bt % p.nx != 0) continue;   // scaled system: whole stages per group
     // LDS-row kernels run with exactly kTailThreads threads
     if (v.reg == 4) {
       if (force_bt > 0 && force_bt != kTailThreads) continue;

@@ -132,6 +132,27 @@ def test_scaled_system_small_workgroups(scaled_small_table):
     _check(probs, 5)
 
 
+@pytest.fixture
+def scaled_nx12_table():
+    saved = _saved_table()
+    _lib.install_tuning([(12, 1, 47, 3, 192, 5, 192), (12, 48, 143, 3, 576, 5, 576)])
+    yield
+    _lib.install_tuning(saved)
+
+
+def test_scaled_system_nx12(scaled_nx12_table):
+    # nx = 12: a stage's rows can straddle two waves (workgroup barriers in
+    # the factorisation); 192 and 576 threads
+    rng = np.random.default_rng(37)
+    probs = []
+    for T, nu in [(128, 4), (143, 2), (100, 3), (32, 2), (16, 4), (5, 3)]:
+        p = W.ltv_problem(rng, T, 12, nu)
+        p["c"] = W.f32(rng.normal(0, 0.1, size=(T, 12)))
+        p["init"] = "rollout"
+        probs.append(p)
+    _check(probs, 5)
+
+
 def test_lds_row_slot_other_widths(lds_row_mixed_table):
     # nx = 12: T = 128 (12 LDS rows), 100 (register slots partly empty), 5;
     # nx = 16: T = 32 and 64 (16 LDS rows each), 20, 50
