@@ -26,6 +26,7 @@
 #include <math.h>
 #include <stdint.h>
 
+
 #include "dmpc_internal.h"
 
 namespace dmpc {
@@ -1696,6 +1697,47 @@ __device__ __forceinline__ float scaled_dot(const float* coef, const float* win)
   return a0 + a2;
 }
 
+// nx = 16 with a stage per 16-lane row of the wave (rows tid + s BT with BT a
+// multiple of 16): lane i of a row holds row i of stage t, so the products
+// with the neighbouring stages need, per lane, only its own entry of p_{t-1}
+// and of p_{t+1} from the window (two 4-byte reads); entry j then reaches
+// every lane of the row through the multiply-add's DPP operand (row_newbcast:j
+// reads lane j of the row), instead of every lane reading all 2 nx entries.
+// (The compiler does not fold a broadcast into the multiply-add, hence the
+// asm; s_nop 1 covers the wait states a DPP read needs after a vector ALU
+// write of its source.)
+__device__ __forceinline__ float bcast_dot16(const float* c, float x) {
+  float a = 0.f;
+  asm("s_nop 1\n\t"
+      "v_fmac_f32_dpp %0, %1, %2 row_newbcast:0 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %0, %1, %3 row_newbcast:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %0, %1, %4 row_newbcast:2 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %0, %1, %5 row_newbcast:3 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %0, %1, %6 row_newbcast:4 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %0, %1, %7 row_newbcast:5 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %0, %1, %8 row_newbcast:6 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %0, %1, %9 row_newbcast:7 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %0, %1, %10 row_newbcast:8 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %0, %1, %11 row_newbcast:9 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %0, %1, %12 row_newbcast:10 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %0, %1, %13 row_newbcast:11 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %0, %1, %14 row_newbcast:12 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %0, %1, %15 row_newbcast:13 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %0, %1, %16 row_newbcast:14 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %0, %1, %17 row_newbcast:15 row_mask:0xf bank_mask:0xf"
+      : "+v"(a)
+      : "v"(x), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]), "v"(c[4]), "v"(c[5]), "v"(c[6]),
+        "v"(c[7]), "v"(c[8]), "v"(c[9]), "v"(c[10]), "v"(c[11]), "v"(c[12]), "v"(c[13]),
+        "v"(c[14]), "v"(c[15]));
+  return a;
+}
+// Scaled off-diagonal row product of row rho (window entry w[nx + rho] is
+// row rho of the published vector).
+__device__ __forceinline__ float scaled_dot_rows16(const float* coef, const float* wrow) {
+  const float pv = wrow[-16], nv = wrow[16];
+  return bcast_dot16(coef, pv) + bcast_dot16(coef + 16, nv);
+}
+
 // Ordering fence on a computed value: the value is complete before the fence
 // and no memory access moves across it.  The LDS-row kernels hold four
 // register rows per thread in a 256-register budget; fences after each slot's
@@ -1831,7 +1873,9 @@ __device__ __forceinline__ void apply_rows(const Prob& P, float* win,
       }
       if constexpr (SC) {
         if (row_live<REG>(s, rho, R, BT)) {
-          const float e = scaled_dot<NX>(M[s], win + (rho / NX) * NX);
+          float e;
+          if constexpr (NX == 16) e = scaled_dot_rows16(M[s], win + NX + rho);
+          else e = scaled_dot<NX>(M[s], win + (rho / NX) * NX);
           out[s] = PH ? v[s] - e : v[s] + e;
         }
       } else if (!lds_row && row_live<REG>(s, rho, R, BT)) {
