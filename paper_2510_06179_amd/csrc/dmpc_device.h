@@ -1179,6 +1179,63 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Double-precision matrix-core product of 16 x 16 x 4 tiles: lane (q, c)
+// (q = lane / 16, c = lane % 16) supplies A[c][k_q] and B[k_q][c], where k_q
+// is the contraction index its lane group stands for in this step; item r of
+// the result is D[4 r + q][c] (rows interleaved across the lane groups,
+// unlike the single-precision 16 x 16 x 4 tile, whose item r is row 4 q + r).
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ mfma_d4 mfma16d(double a, double b, mfma_d4 acc) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+}
+
+// Scaled off-diagonal blocks E~_{t,t-1} = L_t^-1 S_{t,t-1} L_{t-1}^-T for
+// t = 1..T (nx <= 16, padded to 16 with zeros), one wave per stage:
+// Y = S_{t,t-1} L_{t-1}^-T, then L_t^-1 Y.  Step s of either product lets
+// lane group q stand for index 4 s + q, so that the B operand of the second
+// product, Y[4 s + q][c], is item s of the lane's own result of the first.
+// Writes E~_{t,t-1} to coefficients 3 nx .. 4 nx of the rows of stage t and
+// its transpose E~_{t-1,t} to coefficients 4 nx .. 5 nx of the rows of stage
+// t - 1.  Lid: L_t^-1, double, row-major per stage.
+template <int NX>
+__device__ __forceinline__ void mfma_scaled_offdiag(const Prob& P, float* blk, const double* Lid) {
+  static_assert(NX <= 16, "one 16 x 16 tile per block");
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, W = blockDim.x >> 6;
+  const int q = lane >> 4, c = lane & 15;
+  const bool cin = c < NX;
+  const int cc = cin ? c : 0;
+  for (int t = 1 + w; t < P.N; t += W) {
+    const float* St = blk + blk_at<NX>(t * NX + cc, 0);         // row c of S_{t,t-1}
+    const double* Lp = Lid + ((int64_t)(t - 1) * NX + cc) * NX;  // row c of L_{t-1}^-1
+    const double* Lt = Lid + ((int64_t)t * NX + cc) * NX;        // row c of L_t^-1
+    mfma_d4 y = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int k = 4 * s + q;
+      const bool ok = cin && k < NX;
+      y = mfma16d(ok ? (double)St[k] : 0.0, ok ? Lp[k] : 0.0, y);
+    }
+    mfma_d4 e = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int k = 4 * s + q;
+      const bool ok = cin && k < NX;
+      e = mfma16d(ok ? Lt[k] : 0.0, y[s], e);
+    }
+    if (cin) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 4 * r + q;
+        if (i < NX) {
+          const float v = (float)e[r];
+          blk[blk_at<NX>(t * NX + i, 3 * NX + c)] = v;
+          blk[blk_at<NX>((t - 1) * NX + c, 4 * NX + i)] = v;
+        }
+      }
+    }
+  }
+}
+
 // ===========================================================================
 // Scaled Schur system (kRecScaled).  With D_t = L_t L_t' (Cholesky, in double
 // from the float blocks) and L = blkdiag(L_t), the PCG of Alg. pcg on S^
@@ -1208,7 +1265,6 @@ __device__ __forceinline__ bool scaled_blocks(const Prob& P, double* xch) {
   const int N = P.N;
   float* blk = P.W + P.L.blk;
   double* Lid = (double*)(P.W + P.L.Lid);
-  double* Pd = (double*)(P.W + P.L.Pd);
   double* xg = xch + (tid / NX) * NX;   // exchange row of this thread's stage group
   int bad = 0;
   // (1), (2) per group of BT rows (whole stages); rows past R factor
@@ -1263,52 +1319,14 @@ __device__ __forceinline__ bool scaled_blocks(const Prob& P, double* xch) {
     }
   }
   __syncthreads();
-  // (3) P_t = S_{t,t-1} L_{t-1}^-T and P'_t = S_{t,t+1} L_{t+1}^-T, row k by
-  // thread (t, k) from the first and third blocks of its Schur row
-  double* Pn = Pd + (int64_t)N * NX * NX;
-  for (int rho = tid; rho < R; rho += BT) {
-    const int t = rho / NX;
+  // (3) E~_{t,t-1} = L_t^-1 S_{t,t-1} L_{t-1}^-T on the matrix cores, and
+  // E~_{t-1,t} as its transpose; the blocks past either end are zero
+  mfma_scaled_offdiag<NX>(P, blk, Lid);
+  for (int rho = tid; rho < NX; rho += BT) {
 #pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      const int tn = side == 0 ? t - 1 : t + 1;
-      if (tn < 0 || tn >= N) continue;
-      const double* Xn = Lid + (int64_t)tn * NX * NX;
-      double o[NX];
-#pragma unroll
-      for (int m = 0; m < NX; ++m) o[m] = blk[blk_at<NX>(rho, 2 * side * NX + m)];
-      double* out = (side == 0 ? Pd : Pn) + (int64_t)rho * NX;
-#pragma unroll
-      for (int j = 0; j < NX; ++j) {
-        double acc = 0.0;
-#pragma unroll
-        for (int m = 0; m <= j; ++m) acc += o[m] * Xn[j * NX + m];
-        out[j] = acc;
-      }
-    }
-  }
-  __syncthreads();
-  // (4) E~_{t,t-1} = L_t^-1 P_t and E~_{t,t+1} = L_t^-1 P'_t, row i by thread
-  // (t, i); blocks past either end are zero
-  for (int rho = tid; rho < R; rho += BT) {
-    const int t = rho / NX;
-    const double* Xi = Lid + (int64_t)rho * NX;
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      const int tn = side == 0 ? t - 1 : t + 1;
-      double acc[NX];
-#pragma unroll
-      for (int j = 0; j < NX; ++j) acc[j] = 0.0;
-      if (tn >= 0 && tn < N) {
-        const double* Pt = (side == 0 ? Pd : Pn) + (int64_t)t * NX * NX;
-#pragma unroll
-        for (int k = 0; k < NX; ++k) {   // (X_t is lower triangular: Xi[k] = 0 for k > i)
-          const double xk = Xi[k];
-#pragma unroll
-          for (int j = 0; j < NX; ++j) acc[j] += xk * Pt[k * NX + j];
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < NX; ++j) blk[blk_at<NX>(rho, (3 + side) * NX + j)] = (float)acc[j];
+    for (int j = 0; j < NX; ++j) {
+      blk[blk_at<NX>(rho, 3 * NX + j)] = 0.f;
+      blk[blk_at<NX>((N - 1) * NX + rho, 4 * NX + j)] = 0.f;
     }
   }
   return __syncthreads_or(bad) != 0;

@@ -64,10 +64,9 @@ struct WsLayout {
   int64_t g;                      // right-hand side of the Schur system [N*nx]
   int64_t bulk;                   // kRecBulkWs: the regions that do not fit LDS (-1 if unused)
   int64_t stash;                  // kRecTailLds: the multipliers (hi, lo) during a PCG [2][N*nx]
-  int64_t Lid, Pd;                // kRecScaled: the inverses of the Cholesky factors L_t of
-                                  // the diagonal blocks [N][nx][nx] and the products
-                                  // S_{t,t-1} L_{t-1}^-T, S_{t,t+1} L_{t+1}^-T [2][N][nx][nx],
-                                  // in double (float offsets, 8-byte aligned)
+  int64_t Lid;                    // kRecScaled: the inverses of the Cholesky factors L_t of
+                                  // the diagonal blocks [N][nx][nx], in double (float
+                                  // offset, 8-byte aligned)
   int64_t total;
 };
 
@@ -125,9 +124,8 @@ DMPC_HD inline WsLayout ws_layout(int T, int nx, int nu, int dyn, int flags) {
   if (flags & kRecScaled) {
     o = align_up(o, 4);
     L.Lid = o; o += 2 * N * nx * nx;
-    L.Pd = o; o += 4 * N * nx * nx;
   } else {
-    L.Lid = L.Pd = -1;
+    L.Lid = -1;
   }
   L.total = align_up(o, kAlignFloats);
   return L;
