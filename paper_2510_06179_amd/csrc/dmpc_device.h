@@ -552,6 +552,31 @@ __device__ __forceinline__ R ldc(const Prob& P, int idx) {
   return (R)P.c[idx];
 }
 
+// Row passes over the Schur rows: the entries of A a row needs, for U rows
+// rho = base + u BT of a thread at once, every load issued before any is
+// used (the passes are bound by the latency of these loads, and a row at a
+// time leaves one row's loads in flight).  Row index r = rho - off of the
+// stacked blocks A_t (row-major [T][NX][NX]): COL takes column i of block t
+// = r / NX (entries A_t[k][i]), else row r (entries A_t[i][k]); rows outside
+// [0, lim) read block 0 and the caller discards them.  Float data (LTV).
+template <int NX, int U, bool COL>
+__device__ __forceinline__ void gather_A(const float* A, int base, int BT, int off, int lim,
+                                         float (&a)[U][NX]) {
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int r = base + u * BT - off;
+    const bool ok = r >= 0 && r < lim;
+    const int t = r / NX, i = r - t * NX;
+    const float* s = A + (ok ? (COL ? t * NX * NX + i : r * NX) : 0);
+#pragma unroll
+    for (int k = 0; k < NX; ++k) a[u][k] = s[COL ? k * NX : k];
+  }
+}
+// rows gathered at once: 32 floats of A per thread (the passes are calls
+// with at most 128 registers)
+template <int NX>
+constexpr int gather_rows() { return NX >= 12 ? 2 : (NX >= 8 ? 4 : 8); }
+
 __device__ __forceinline__ float softplusf(float v) {
   return v > 20.f ? v : log1pf(expf(v));
 }
@@ -2323,17 +2348,39 @@ __device__ __forceinline__ ResNorms fwd_residual64_body(const ProbRec* rec, cons
   const float* rr = P.Wq + P.L.r;
   const double* iQd = (const double*)(P.Wq + P.L.iQd);
   const double* iRd = (const double*)(P.Wq + P.L.iRd);
-  for (int rho = tid; rho < R; rho += BT) {
-    const int t = rho / NX, i = rho - t * NX;
-    double acc = (double)q[rho] + ((double)w0[rho] + (double)w2[rho]);
-    if (t < T) {
-      const int a0 = t * NX * NX;
+  if (P.Ad == nullptr) {
+    constexpr int U = gather_rows<NX>();
+    for (int base = tid; base < R; base += U * BT) {
+      float a[U][NX];
+      gather_A<NX, U, true>(P.A, base, BT, 0, T * NX, a);
 #pragma unroll
-      for (int k = 0; k < NX; ++k)
-        acc -= ldA<double>(P, a0 + k * NX + i) *
-               ((double)w0[(t + 1) * NX + k] + (double)w2[(t + 1) * NX + k]);
+      for (int u = 0; u < U; ++u) {
+        const int rho = base + u * BT;
+        if (rho < R) {
+          const int t = rho / NX;
+          double acc = (double)q[rho] + ((double)w0[rho] + (double)w2[rho]);
+          if (t < T) {
+#pragma unroll
+            for (int k = 0; k < NX; ++k)
+              acc -= (double)a[u][k] * ((double)w0[(t + 1) * NX + k] + (double)w2[(t + 1) * NX + k]);
+          }
+          xz[rho] = -acc * iQd[rho];
+        }
+      }
     }
-    xz[rho] = -acc * iQd[rho];
+  } else {
+    for (int rho = tid; rho < R; rho += BT) {
+      const int t = rho / NX, i = rho - t * NX;
+      double acc = (double)q[rho] + ((double)w0[rho] + (double)w2[rho]);
+      if (t < T) {
+        const int a0 = t * NX * NX;
+#pragma unroll
+        for (int k = 0; k < NX; ++k)
+          acc -= ldA<double>(P, a0 + k * NX + i) *
+                 ((double)w0[(t + 1) * NX + k] + (double)w2[(t + 1) * NX + k]);
+      }
+      xz[rho] = -acc * iQd[rho];
+    }
   }
   for (int idx = tid; idx < TM; idx += BT) {
     const int t = idx / m, l = idx - t * m;
@@ -2347,7 +2394,7 @@ __device__ __forceinline__ ResNorms fwd_residual64_body(const ProbRec* rec, cons
   }
   __syncthreads();
   float r2 = 0.f, b2 = 0.f;
-  for (int rho = tid; rho < R; rho += BT) {
+  auto defect_row = [&](int rho, auto&& aent) {
     const int t = rho / NX, i = rho - t * NX;
     double res;
     float dv;
@@ -2359,14 +2406,28 @@ __device__ __forceinline__ ResNorms fwd_residual64_body(const ProbRec* rec, cons
       dv = P.c[tt * NX + i];
       double acc = ldc<double>(P, tt * NX + i);
 #pragma unroll
-      for (int j = 0; j < NX; ++j)
-        acc += ldA<double>(P, tt * NX * NX + i * NX + j) * xz[tt * NX + j];
+      for (int j = 0; j < NX; ++j) acc += aent(tt, i, j) * xz[tt * NX + j];
       for (int l = 0; l < m; ++l) acc += ldB<double>(P, tt * NX * m + i * m + l) * uz[tt * m + l];
       res = xz[rho] - acc;
     }
     w1[NX + rho] = (float)res;
     r2 += (float)(res * res);
     b2 += q[rho] * q[rho] + dv * dv;
+  };
+  if (P.Ad == nullptr) {
+    constexpr int U = gather_rows<NX>();
+    for (int base = tid; base < R; base += U * BT) {
+      float a[U][NX];
+      gather_A<NX, U, false>(P.A, base, BT, NX, T * NX, a);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int rho = base + u * BT;
+        if (rho < R) defect_row(rho, [&](int, int, int j) { return (double)a[u][j]; });
+      }
+    }
+  } else {
+    for (int rho = tid; rho < R; rho += BT)
+      defect_row(rho, [&](int tt, int i, int j) { return ldA<double>(P, tt * NX * NX + i * NX + j); });
   }
   for (int idx = tid; idx < TM; idx += BT) b2 += rr[idx] * rr[idx];
   const ResNorms n = block_sum2(r2, b2, smem + C.red, nwv);
@@ -2502,8 +2563,17 @@ __device__ __forceinline__ void ls_rows_ltv(const Prob& P, const LsParams& lp, c
     for (int a = 0; a <= kMaxAlphas; ++a)
       cs[a] += a <= lp.n ? cost_x1<NX>(P, t, i, xb + al[a] * dx, COST) : 0.0;
     dn += dcost_x1<NX>(P, t, i, xb, dx, COST);
-    if (t < T) {
-      const float* Ai = P.A + (t * NX + i) * NX;
+  }
+  // dynamics defects, rows t < T
+  constexpr int U = gather_rows<NX>();
+  for (int base = tid; base < T * NX; base += U * BT) {
+    float ag[U][NX];
+    gather_A<NX, U, false>(P.A, base, BT, 0, T * NX, ag);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int rho = base + u * BT;
+      if (rho >= T * NX) continue;
+      const int t = rho / NX, i = rho - t * NX;
       const float* Bi = P.B + (t * NX + i) * m;
       const float* xs = xbar + t * NX;
       const float* qs = xp + t * NX;
@@ -2511,8 +2581,8 @@ __device__ __forceinline__ void ls_rows_ltv(const Prob& P, const LsParams& lp, c
 #pragma unroll
       for (int j = 0; j < NX; ++j) {
         const double xj = xs[j];
-        a0 += (double)Ai[j] * xj;
-        a1 += (double)Ai[j] * ((double)qs[j] - xj);
+        a0 += (double)ag[u][j] * xj;
+        a1 += (double)ag[u][j] * ((double)qs[j] - xj);
       }
       for (int l = 0; l < m; ++l) {
         const double ul = ubar[t * m + l];
@@ -2559,18 +2629,41 @@ __device__ __forceinline__ LsResult fwd_recover_ls_body(const ProbRec* rec, cons
     const double* iRd = (const double*)(P.Wq + P.L.iRd);
     const float* q = P.Wq + P.L.q;
     const float* rr = P.Wq + P.L.r;
-    for (int rho = tid; rho < R; rho += BT) {
-      const int t = rho / NX, i = rho - t * NX;
-      double acc = (double)q[rho] + ((double)w0[NX + rho] + (double)w2[NX + rho]);
-      if (t < T) {
-        const int a0 = t * NX * NX;
-        const float* lh = w0 + NX + (t + 1) * NX;
-        const float* ll = w2 + NX + (t + 1) * NX;
+      if (P.Ad == nullptr) {
+      constexpr int U = gather_rows<NX>();
+      for (int base = tid; base < R; base += U * BT) {
+        float a[U][NX];
+        gather_A<NX, U, true>(P.A, base, BT, 0, T * NX, a);
 #pragma unroll
-        for (int kk = 0; kk < NX; ++kk)
-          acc -= ldA<double>(P, a0 + kk * NX + i) * ((double)lh[kk] + (double)ll[kk]);
+        for (int u = 0; u < U; ++u) {
+          const int rho = base + u * BT;
+          if (rho < R) {
+            const int t = rho / NX;
+            double acc = (double)q[rho] + ((double)w0[NX + rho] + (double)w2[NX + rho]);
+            if (t < T) {
+              const float* lh = w0 + NX + (t + 1) * NX;
+              const float* ll = w2 + NX + (t + 1) * NX;
+#pragma unroll
+              for (int kk = 0; kk < NX; ++kk) acc -= (double)a[u][kk] * ((double)lh[kk] + (double)ll[kk]);
+            }
+            xp[rho] = (float)(-acc * iQd[rho]);
+          }
+        }
       }
-      xp[rho] = (float)(-acc * iQd[rho]);
+    } else {
+      for (int rho = tid; rho < R; rho += BT) {
+        const int t = rho / NX, i = rho - t * NX;
+        double acc = (double)q[rho] + ((double)w0[NX + rho] + (double)w2[NX + rho]);
+        if (t < T) {
+          const int a0 = t * NX * NX;
+          const float* lh = w0 + NX + (t + 1) * NX;
+          const float* ll = w2 + NX + (t + 1) * NX;
+#pragma unroll
+          for (int kk = 0; kk < NX; ++kk)
+            acc -= ldA<double>(P, a0 + kk * NX + i) * ((double)lh[kk] + (double)ll[kk]);
+        }
+        xp[rho] = (float)(-acc * iQd[rho]);
+      }
     }
     for (int idx = tid; idx < TM; idx += BT) {
       const int t = idx / m, l = idx - t * m;
@@ -2828,17 +2921,39 @@ __device__ __forceinline__ ResNorms bwd_residual64_body(const ProbRec* rec, cons
   const double* iQd = (const double*)(P.Wq + P.L.iQd);
   const double* iRd = (const double*)(P.Wq + P.L.iRd);
   const int nwv = (BT + 63) >> 6;
-  for (int rho = tid; rho < R; rho += BT) {
-    const int t = rho / NX, i = rho - t * NX;
-    double acc = (double)dlx[rho] - ((double)w0[rho] + (double)w2[rho]);
-    if (t < T) {
-      const int a0 = t * NX * NX;
+  if (P.Ad == nullptr) {
+    constexpr int U = gather_rows<NX>();
+    for (int base = tid; base < R; base += U * BT) {
+      float a[U][NX];
+      gather_A<NX, U, true>(P.A, base, BT, 0, T * NX, a);
 #pragma unroll
-      for (int k = 0; k < NX; ++k)
-        acc += ldA<double>(P, a0 + k * NX + i) *
-               ((double)w0[(t + 1) * NX + k] + (double)w2[(t + 1) * NX + k]);
+      for (int u = 0; u < U; ++u) {
+        const int rho = base + u * BT;
+        if (rho < R) {
+          const int t = rho / NX;
+          double acc = (double)dlx[rho] - ((double)w0[rho] + (double)w2[rho]);
+          if (t < T) {
+#pragma unroll
+            for (int k = 0; k < NX; ++k)
+              acc += (double)a[u][k] * ((double)w0[(t + 1) * NX + k] + (double)w2[(t + 1) * NX + k]);
+          }
+          xz[rho] = acc * iQd[rho];
+        }
+      }
     }
-    xz[rho] = acc * iQd[rho];
+  } else {
+    for (int rho = tid; rho < R; rho += BT) {
+      const int t = rho / NX, i = rho - t * NX;
+      double acc = (double)dlx[rho] - ((double)w0[rho] + (double)w2[rho]);
+      if (t < T) {
+        const int a0 = t * NX * NX;
+#pragma unroll
+        for (int k = 0; k < NX; ++k)
+          acc += ldA<double>(P, a0 + k * NX + i) *
+                 ((double)w0[(t + 1) * NX + k] + (double)w2[(t + 1) * NX + k]);
+      }
+      xz[rho] = acc * iQd[rho];
+    }
   }
   for (int idx = tid; idx < TM; idx += BT) {
     const int t = idx / m, l = idx - t * m;
@@ -2852,20 +2967,34 @@ __device__ __forceinline__ ResNorms bwd_residual64_body(const ProbRec* rec, cons
   }
   __syncthreads();
   float r2 = 0.f, b2 = 0.f;
-  for (int rho = tid; rho < R; rho += BT) {
+  auto defect_row = [&](int rho, auto&& aent) {
     const int t = rho / NX, i = rho - t * NX;
     double acc = (double)dll[rho];
     if (t > 0) {
       const int tt = t - 1;
 #pragma unroll
-      for (int j = 0; j < NX; ++j)
-        acc += ldA<double>(P, tt * NX * NX + i * NX + j) * xz[tt * NX + j];
+      for (int j = 0; j < NX; ++j) acc += aent(tt, i, j) * xz[tt * NX + j];
       for (int l = 0; l < m; ++l) acc += ldB<double>(P, tt * NX * m + i * m + l) * uz[tt * m + l];
     }
     const double res = xz[rho] - acc;
     w1[NX + rho] = (float)res;
     r2 += (float)(res * res);
     b2 += dlx[rho] * dlx[rho] + dll[rho] * dll[rho];
+  };
+  if (P.Ad == nullptr) {
+    constexpr int U = gather_rows<NX>();
+    for (int base = tid; base < R; base += U * BT) {
+      float a[U][NX];
+      gather_A<NX, U, false>(P.A, base, BT, NX, T * NX, a);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int rho = base + u * BT;
+        if (rho < R) defect_row(rho, [&](int, int, int j) { return (double)a[u][j]; });
+      }
+    }
+  } else {
+    for (int rho = tid; rho < R; rho += BT)
+      defect_row(rho, [&](int tt, int i, int j) { return ldA<double>(P, tt * NX * NX + i * NX + j); });
   }
   for (int idx = tid; idx < TM; idx += BT) b2 += dlu[idx] * dlu[idx];
   const ResNorms n = block_sum2(r2, b2, smem + C.red, nwv);
