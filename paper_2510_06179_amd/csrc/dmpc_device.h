@@ -972,9 +972,10 @@ __device__ __forceinline__ void schur_row(const Prob& P, int t, int i, R* S, R& 
 
 // The right-hand side entry g (row (t, i)) of schur_row alone: for problems
 // whose QP matrices do not change between SQP iterations only the linear
-// terms (and with them g) move.
+// terms (and with them g) move.  Ai: row i of A_{t-1} (t > 0), gathered by
+// the caller.
 template <int NX>
-__device__ __forceinline__ float schur_rhs_row(const Prob& P, int t, int i) {
+__device__ __forceinline__ float schur_rhs_row(const Prob& P, int t, int i, const float* Ai) {
   const float* W = P.Wq;
   const float* iQ = W + P.L.iQ;
   const float* q = W + P.L.q;
@@ -983,10 +984,10 @@ __device__ __forceinline__ float schur_rhs_row(const Prob& P, int t, int i) {
   const int m = P.m;
   if (t == 0) return -(P.x0[i] + q[i] * iQ[i]);
   const int tt = t - 1;
-  const int a0 = tt * NX * NX, b0 = tt * NX * m;
+  const int b0 = tt * NX * m;
   float gs = 0.f;
 #pragma unroll
-  for (int j = 0; j < NX; ++j) gs += (P.A[a0 + i * NX + j] * iQ[tt * NX + j]) * q[tt * NX + j];
+  for (int j = 0; j < NX; ++j) gs += (Ai[j] * iQ[tt * NX + j]) * q[tt * NX + j];
   for (int l = 0; l < m; ++l) gs += (P.B[b0 + i * m + l] * iR[tt * m + l]) * r[tt * m + l];
   return -(P.c[tt * NX + i] - gs + q[t * NX + i] * iQ[t * NX + i]);
 }
@@ -2253,9 +2254,15 @@ __device__ __forceinline__ int fwd_blocks_body(const ProbRec* rec, const float* 
     // depend on A, B and the projected Hessians only, which do not change
     // between SQP iterations; the rows of the first iteration stay, and only
     // the right-hand side follows the linear terms
-    for (int rho = tid; rho < P.R; rho += BT) {
-      const int t = rho / NX, i = rho - t * NX;
-      gv[rho] = schur_rhs_row<NX>(P, t, i);
+    constexpr int U = gather_rows<NX>();
+    for (int base = tid; base < P.R; base += U * BT) {
+      float ag[U][NX];   // row i of A_{t-1}
+      gather_A<NX, U, false>(P.A, base, BT, NX, P.T * NX, ag);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int rho = base + u * BT;
+        if (rho < P.R) gv[rho] = schur_rhs_row<NX>(P, rho / NX, rho % NX, ag[u]);
+      }
     }
     __syncthreads();
     return 0;
@@ -2330,6 +2337,82 @@ __device__ __forceinline__ ResNorms block_sum2(float a, float b, float* red, int
 // (rounded to float) to w1[NX + rho]; returns the norms of r and of the KKT
 // right-hand side [-b; d] = [-(q, r); (x_s, c)] (Eq. ocp:KKT), identical in
 // every thread.
+// Scaled system (kRecScaled): r~ = L^-1 r, the right-hand side of the PCG on
+// the scaled system, from the residual r in LDS (unpadded view) to out, at
+// the end of the residual call, where the double rows of L^-1 of several
+// rows can be loaded at once (in the PCG's context the rows of the Schur
+// system hold the registers).  Row rho: the double row of L_t^-1 (zero
+// above its diagonal) times the stage's residual, accumulated in double.
+template <int NX>
+__device__ __forceinline__ void scaled_rhs(const Prob& P, const float* r, float* out) {
+  const int tid = threadIdx.x, BT = blockDim.x, R = P.R;
+  const double* Li = (const double*)(P.W + P.L.Lid);
+  constexpr int U = gather_rows<NX>();
+  for (int base = tid; base < R; base += U * BT) {
+    double l[U][NX];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int rho = base + u * BT;
+      const double* row = Li + (int64_t)(rho < R ? rho : 0) * NX;
+#pragma unroll
+      for (int j = 0; j < NX; ++j) l[u][j] = row[j];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int rho = base + u * BT;
+      if (rho < R) {
+        const float* rt = r + (rho / NX) * NX;
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < NX; ++j) acc = fma(l[u][j], (double)rt[j], acc);
+        out[rho] = (float)acc;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Scaled system: d = L^-T d~, the PCG's solution mapped back, from d~ in LDS
+// (unpadded view of w1) to the line-search region (floats), in a call of its
+// own for the same reason: column i of the double L_t^-1 (zero above its
+// diagonal) times the stage's d~, accumulated in double.
+template <int NX>
+__device__ __noinline__ void scaled_solution_call(const ProbRec* rec, const float* data,
+                                                  float* ws) {
+  extern __shared__ float smem[];
+  const Prob P = make_prob<NX>(*rec, data, ws);
+  const Carve C = carve_of<NX>(P);
+  const int tid = threadIdx.x, BT = blockDim.x, R = P.R;
+  const float* dt = smem + C.w1 + NX;
+  float* out = bulk_base(smem, P) + C.ls;
+  const double* Li = (const double*)(P.W + P.L.Lid);
+  constexpr int U = gather_rows<NX>();
+  for (int base = tid; base < R; base += U * BT) {
+    double l[U][NX];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int rho = base + u * BT;
+      const int rr = rho < R ? rho : 0;
+      const int t = rr / NX, i = rr - t * NX;
+      const double* col = Li + (int64_t)t * NX * NX + i;
+#pragma unroll
+      for (int j = 0; j < NX; ++j) l[u][j] = col[j * NX];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int rho = base + u * BT;
+      if (rho < R) {
+        const float* wt = dt + (rho / NX) * NX;
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < NX; ++j) acc = fma(l[u][j], (double)wt[j], acc);
+        out[rho] = (float)acc;
+      }
+    }
+  }
+  __syncthreads();
+}
+
 template <int NX>
 __device__ __forceinline__ ResNorms fwd_residual64_body(const ProbRec* rec, const float* data,
                                                         float* ws) {
@@ -2432,6 +2515,9 @@ __device__ __forceinline__ ResNorms fwd_residual64_body(const ProbRec* rec, cons
   for (int idx = tid; idx < TM; idx += BT) b2 += rr[idx] * rr[idx];
   const ResNorms n = block_sum2(r2, b2, smem + C.red, nwv);
   __syncthreads();   // xz is the line search's region
+  if constexpr (NX == 8 || NX == 12 || NX == 16) {
+    if (P.flags & kRecScaled) scaled_rhs<NX>(P, smem + C.w1 + NX, smem + C.w2 + NX);
+  }
   return n;
 }
 
@@ -2999,6 +3085,9 @@ __device__ __forceinline__ ResNorms bwd_residual64_body(const ProbRec* rec, cons
   for (int idx = tid; idx < TM; idx += BT) b2 += dlu[idx] * dlu[idx];
   const ResNorms n = block_sum2(r2, b2, smem + C.red, nwv);
   __syncthreads();
+  if constexpr (NX == 8 || NX == 12 || NX == 16) {
+    if (P.flags & kRecScaled) scaled_rhs<NX>(P, smem + C.w1 + NX, smem + C.w2 + NX);
+  }
   return n;
 }
 
@@ -3558,11 +3647,13 @@ __device__ __forceinline__ void load_rows(const Prob& P, const Lds& sh,
   load_reg_rows<NX, SLOTS, REG, WAVE, DINV, TAIL, SC>(P, S, Ph);
 }
 
-// Scaled system (kRecScaled): out = L^-1 v (TRANS = false) or L^-T v, stage by
-// stage, through the window w, accumulated in double with the double L_t^-1
-// (zero above its diagonal): for ill-conditioned diagonal blocks a float
-// copy of L^-1 would limit what the refinement passes can reach.
-template <int NX, int SLOTS, bool TRANS>
+// Scaled system (kRecScaled): out = L^-1 v, stage by stage, through the
+// window w, accumulated in double with the double L_t^-1 (zero above its
+// diagonal): for ill-conditioned diagonal blocks a float copy of L^-1 would
+// limit what the refinement passes can reach.  (Used for the preconditioned
+// norm of the right-hand side; the refinement passes map their residuals in
+// the residual call, scaled_rhs.)
+template <int NX, int SLOTS>
 __device__ __forceinline__ void scale_vec(const Prob& P, float* w, const float (&v)[SLOTS],
                                           float (&out)[SLOTS]) {
   const int tid = threadIdx.x, BT = blockDim.x, R = P.R;
@@ -3574,18 +3665,11 @@ __device__ __forceinline__ void scale_vec(const Prob& P, float* w, const float (
     const int rho = row_of<NX, false>(s, tid, BT);
     out[s] = 0.f;
     if (rho < R) {
-      const int t = rho / NX, i = rho - t * NX;
-      const float* wt = w + NX + t * NX;
+      const float* wt = w + NX + (rho / NX) * NX;
+      const double* row = Li + (int64_t)rho * NX;
       double acc = 0.0;
-      if constexpr (!TRANS) {
-        const double* row = Li + (int64_t)rho * NX;
 #pragma unroll
-        for (int j = 0; j < NX; ++j) acc = fma(row[j], (double)wt[j], acc);
-      } else {
-        const double* col = Li + (int64_t)t * NX * NX + i;
-#pragma unroll
-        for (int j = 0; j < NX; ++j) acc = fma(col[j * NX], (double)wt[j], acc);
-      }
+      for (int j = 0; j < NX; ++j) acc = fma(row[j], (double)wt[j], acc);
       out[s] = (float)acc;
     }
   }
@@ -3601,10 +3685,10 @@ __device__ __forceinline__ void scale_vec(const Prob& P, float* w, const float (
 // relative tolerance ref_tol.  Passes stop once the residual meets the KKT
 // target (||r||_2 <= kkt_tol ||rhs||_2) -- before pass 0 too, when the warm
 // start already meets it (converged SQP iterates).  SC: the PCG runs on the
-// scaled system (scaled_blocks), its right-hand side L^-1 r and its solution
-// mapped back by L^-T.
+// scaled system (scaled_blocks); the residual call returns its right-hand
+// side L^-1 r, and the solution is mapped back by L^-T.
 template <int NX, int SLOTS, bool REG, bool WAVE, bool DINV, bool TAIL, bool SC,
-          typename ResidualFn>
+          typename ResidualFn, typename UnscaleFn>
 __device__ __forceinline__ int qp_solve(const Prob& P, const Lds& sh,
                                         RowRegs<NX, SLOTS - TAIL, REG>& S,
                                         RowRegs<NX, SLOTS - TAIL, REG && !DINV>& Ph,
@@ -3612,7 +3696,8 @@ __device__ __forceinline__ int qp_solve(const Prob& P, const Lds& sh,
                                         float (&hi)[SLOTS], float (&lo)[SLOTS], int steps,
                                         int maxit, float tol, float abs_tol, float ref_tol,
                                         float kkt_tol, int& flags, int& redi, int maxit_flag,
-                                        int unmet_flag, ResidualFn residual) {
+                                        int unmet_flag, ResidualFn residual,
+                                        UnscaleFn unscale) {
   float etab = 0.f;   // g'Phi^-1 g, formed when pass 0 runs
   int its = 0;
   float prev_r2 = 0.f;
@@ -3635,17 +3720,11 @@ __device__ __forceinline__ int qp_solve(const Prob& P, const Lds& sh,
     if (k == 0) {
       if constexpr (SC) {
         float gt[SLOTS];
-        scale_vec<NX, SLOTS, false>(P, sh.w2, g, gt);
+        scale_vec<NX, SLOTS>(P, sh.w2, g, gt);
         etab = precond_norm<NX, SLOTS, REG, WAVE, DINV, TAIL, SC>(P, sh, S, Ph, gt, redi);
       } else {
         etab = precond_norm<NX, SLOTS, REG, WAVE, DINV, TAIL, SC>(P, sh, S, Ph, g, redi);
       }
-    }
-    if constexpr (SC) {
-      float rt[SLOTS];
-      scale_vec<NX, SLOTS, false>(P, sh.w2, rr, rt);
-#pragma unroll
-      for (int s = 0; s < SLOTS; ++s) rr[s] = rt[s];
     }
     if constexpr (TAIL) {
       // the multipliers wait in the workspace while the PCG runs: in
@@ -3668,12 +3747,7 @@ __device__ __forceinline__ int qp_solve(const Prob& P, const Lds& sh,
     else
       its += pcg<NX, SLOTS, REG, WAVE, DINV, TAIL, SC>(P, sh, S, Ph, rr, d, maxit, ref_tol, 0.f,
                                        flags, redi, maxit_flag);
-    if constexpr (SC) {
-      float dd[SLOTS];
-      scale_vec<NX, SLOTS, true>(P, sh.w2, d, dd);
-#pragma unroll
-      for (int s = 0; s < SLOTS; ++s) d[s] = dd[s];
-    }
+    if constexpr (SC) unscale(d);
     if constexpr (TAIL) {
       const int tid = threadIdx.x, BT = block_threads<TAIL>();
       const float* st = P.W + P.L.stash;
@@ -3782,14 +3856,36 @@ __device__ __forceinline__ ResNorms residual_rows(const ProbRec* rec, const KArg
     ResNorms nr;
     if constexpr (BWD) nr = bwd_residual64<NX>(rec, a.data, a.ws, a.dl);
     else nr = fwd_residual64<NX>(rec, a.data, a.ws);
+    // (scaled system: the call left r~ = L^-1 r in w2)
+    const float* rw = (P.flags & kRecScaled) ? sh.w2 : sh.w1;
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
       const int rho = row_of<NX, false>(s, tid, BT);
-      rr[s] = rho < P.R ? sh.w1[NX + rho] : 0.f;
+      rr[s] = rho < P.R ? rw[NX + rho] : 0.f;
     }
     __syncthreads();
     return nr;
   }
+}
+
+// Scaled system: the PCG's solution d~ (thread's rows) mapped back to
+// d = L^-T d~ through the LDS window w1 and the call above.
+template <int NX, int SLOTS>
+__device__ __forceinline__ void scaled_solution_rows(const ProbRec* rec, const KArgs& a,
+                                                     const Prob& P, const Lds& sh,
+                                                     float (&d)[SLOTS]) {
+  extern __shared__ float smem[];
+  const int tid = threadIdx.x, BT = blockDim.x;
+  publish<NX, SLOTS, false, false>(sh.w1, d, P.R);
+  __syncthreads();
+  scaled_solution_call<NX>(rec, a.data, a.ws);
+  const float* out = bulk_base(smem, P) + carve_of<NX>(P).ls;
+#pragma unroll
+  for (int s = 0; s < SLOTS; ++s) {
+    const int rho = row_of<NX, false>(s, tid, BT);
+    d[s] = rho < P.R ? out[rho] : 0.f;
+  }
+  __syncthreads();
 }
 
 // MODE: 0 = rows of S^ and Phi^-1 read from the workspace, 1 = rows in
@@ -3851,6 +3947,9 @@ __global__ __launch_bounds__(MAXBT) void forward_kernel(KArgs a) {
           k == a.sqp_iters - 1 ? DMPC_PROB_KKT_UNMET : 0,
           [&](const float (&h)[SLOTS], const float (&l)[SLOTS], float (&rr)[SLOTS]) {
             return residual_rows<NX, SLOTS, WAVE, false>(rec, a, P, sh, h, l, rr);
+          },
+          [&](float (&dv)[SLOTS]) {
+            if constexpr (SC) scaled_solution_rows<NX, SLOTS>(rec, a, P, sh, dv);
           });
       if constexpr (WAVE) {
         wave_recover<NX, SLOTS>(P, lam, lo, bulk_base(smem, P) + lds_carve.xp,
@@ -3918,6 +4017,9 @@ __global__ __launch_bounds__(MAXBT) void backward_kernel(KArgs a) {
         redi, DMPC_PROB_BWD_PCG_MAXITER, DMPC_PROB_BWD_KKT_UNMET,
         [&](const float (&h)[SLOTS], const float (&l)[SLOTS], float (&rr)[SLOTS]) {
           return residual_rows<NX, SLOTS, WAVE, true>(rec, a, P, sh, h, l, rr);
+        },
+        [&](float (&dv)[SLOTS]) {
+          if constexpr (SC) scaled_solution_rows<NX, SLOTS>(rec, a, P, sh, dv);
         });
     publish<NX, SLOTS, false, WAVE>(sh.w0, lt, P.R);
     publish<NX, SLOTS, false, WAVE>(sh.w2, lo, P.R);
