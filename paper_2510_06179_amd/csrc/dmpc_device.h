@@ -994,9 +994,11 @@ __device__ __forceinline__ float schur_rhs_row(const Prob& P, int t, int i, cons
 
 // Right-hand side of the adjoint Schur system (the first step of Alg. backward, with
 // (-b, d) <- (dl/dz, dl/dlambda)):  g~ = H G^-1 dl/dz - dl/dlambda, row (t, i).
+// Ai: row i of A_{t-1} gathered by the caller, or null to read it here.
 template <int NX, typename R>
 __device__ __forceinline__ R adjoint_rhs_row(const Prob& P, int t, int i, const float* dlx,
-                                             const float* dlu, const float* dll) {
+                                             const float* dlu, const float* dll,
+                                             const float* Ai = nullptr) {
   const float* iQ = P.Wq + P.L.iQ;
   const float* iR = P.Wq + P.L.iR;
   const double* iQd = (const double*)(P.Wq + P.L.iQd);
@@ -1009,7 +1011,7 @@ __device__ __forceinline__ R adjoint_rhs_row(const Prob& P, int t, int i, const 
     const int a0 = tt * NX * NX + i * NX, b0 = tt * NX * m + i * m;
 #pragma unroll
     for (int j = 0; j < NX; ++j)
-      v -= ldA<R>(P, a0 + j) * ((R)dlx[tt * NX + j] * rinv<R>(iQ, iQd, tt * NX + j));
+      v -= (Ai ? (R)Ai[j] : ldA<R>(P, a0 + j)) * ((R)dlx[tt * NX + j] * rinv<R>(iQ, iQd, tt * NX + j));
     for (int l = 0; l < m; ++l)
       v -= ldB<R>(P, b0 + l) * ((R)dlu[tt * m + l] * rinv<R>(iR, iRd, tt * m + l));
   }
@@ -2974,9 +2976,23 @@ __device__ __noinline__ void bwd_begin(const ProbRec* rec, const float* data, fl
   const float* dlu = dlx + R;
   const float* dll = dlu + TM;
   float* gv = P.W + P.L.g;
-  for (int rho = tid; rho < R; rho += BT) {
-    const int t = rho / NX, i = rho - t * NX;
-    gv[rho] = (float)adjoint_rhs_row<NX, double>(P, t, i, dlx, dlu, dll);
+  if (P.Ad == nullptr) {
+    constexpr int U = gather_rows<NX>();
+    for (int base = tid; base < R; base += U * BT) {
+      float ag[U][NX];   // row i of A_{t-1}
+      gather_A<NX, U, false>(P.A, base, BT, NX, P.T * NX, ag);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int rho = base + u * BT;
+        if (rho < R)
+          gv[rho] = (float)adjoint_rhs_row<NX, double>(P, rho / NX, rho % NX, dlx, dlu, dll, ag[u]);
+      }
+    }
+  } else {
+    for (int rho = tid; rho < R; rho += BT) {
+      const int t = rho / NX, i = rho - t * NX;
+      gv[rho] = (float)adjoint_rhs_row<NX, double>(P, t, i, dlx, dlu, dll);
+    }
   }
   __syncthreads();
 }
@@ -3440,21 +3456,36 @@ __device__ __noinline__ void bwd_finish(const ProbRec* rec, const float* data, f
   float* ax = adj + rec->sol_off;
   float* au = ax + R;
   float* al = au + TM;
-  for (int rho = tid; rho < R; rho += BT) {
-    const int t = rho / NX, i = rho - t * NX;
+  auto primal_row = [&](int rho, auto&& aent) {
+    const int t = rho / NX;
     double acc = (double)dlx[rho] - ((double)lw[rho] + (double)lwl[rho]);
     if (t < T) {
-      const int a0 = t * NX * NX;
       const float* lh = lw + (t + 1) * NX;
       const float* ll = lwl + (t + 1) * NX;
 #pragma unroll
-      for (int kk = 0; kk < NX; ++kk)
-        acc += ldA<double>(P, a0 + kk * NX + i) * ((double)lh[kk] + (double)ll[kk]);
+      for (int kk = 0; kk < NX; ++kk) acc += aent(t, kk) * ((double)lh[kk] + (double)ll[kk]);
     }
     const float v = (float)(acc * iQd[rho]);
     xt[rho] = v;
     ax[rho] = v;
     al[rho] = lw[rho];
+  };
+  if (P.Ad == nullptr) {
+    constexpr int U = gather_rows<NX>();
+    for (int base = tid; base < R; base += U * BT) {
+      float a[U][NX];
+      gather_A<NX, U, true>(P.A, base, BT, 0, T * NX, a);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int rho = base + u * BT;
+        if (rho < R) primal_row(rho, [&](int, int kk) { return (double)a[u][kk]; });
+      }
+    }
+  } else {
+    for (int rho = tid; rho < R; rho += BT) {
+      const int i = rho % NX;
+      primal_row(rho, [&](int t, int kk) { return ldA<double>(P, t * NX * NX + kk * NX + i); });
+    }
   }
   for (int idx = tid; idx < TM; idx += BT) {
     const int t = idx / m, l = idx - t * m;

@@ -19,7 +19,7 @@ static const KEntry kEntries[] = {
     DMPC_K(16, 2, 640, 3), DMPC_K(16, 2, 1024, 3), DMPC_K(16, 5, 512, 4), DMPC_K(16, 3, 512, 4), DMPC_K(16, 2, 512, 4),
     DMPC_K(16, 5, 512, 5), DMPC_K(16, 3, 512, 5), DMPC_K(16, 2, 512, 5), DMPC_K(16, 2, 320, 5),
     DMPC_K(16, 1, 320, 5), DMPC_K(16, 5, 256, 5), DMPC_K(16, 3, 192, 5), DMPC_K(16, 9, 256, 5),
-    DMPC_K(16, 2, 192, 5),
+    DMPC_K(16, 2, 192, 5), DMPC_K(16, 3, 384, 5),
 };
 
 const KEntry* kernel_entries_nx16(int* n) {
