@@ -2090,6 +2090,94 @@ __device__ __forceinline__ float precond_norm(const Prob& P, const Lds& sh,
 // max(rel_tol^2 * rhs'Phi^-1 rhs, abs_thresh), or at the iteration cap.
 // (The warm start of Alg. pcg enters through rhs = g - S^ lambda, which the
 // caller computes in double.)  Returns the iteration count; ORs status bits.
+// PCG of Alg. pcg on the scaled system (kRecScaled, register rows), with
+// one barrier fewer per iteration: the Schur product is taken of z = Phi^-1 r
+// instead of p, and y = S^ p follows from y <- S^ z + beta y (the same
+// vectors in exact arithmetic), so that z's exchange and the reduction of
+// eta' = r'z share one barrier: the wave sums of eta' are written before the
+// barrier that publishes z, and beta is known before the row products.  Per
+// iteration: the reduction of p'y, the exchange of r (preconditioner), the
+// exchange of z with eta'.  Same stopping test, status bits and return as
+// pcg below; the refinement passes check each result against the residual
+// formed in double.  Used for nx >= 12.
+template <int NX, int SLOTS, bool REG>
+__device__ __forceinline__ int pcg_scaled(const Prob& P, const Lds& sh,
+                                          RowRegs<NX, SLOTS, REG>& S, RowRegs<NX, SLOTS, REG>& Ph,
+                                          const float (&rhs)[SLOTS], float (&d)[SLOTS], int maxit,
+                                          float rel_tol, float abs_thresh, int& flags, int& redi,
+                                          int maxit_flag) {
+  static_assert(REG, "scaled system: register rows");
+  const int tid = threadIdx.x, BT = blockDim.x, R = P.R;
+  const int nwv = (BT + 63) >> 6;
+  float r[SLOTS], p[SLOTS], z[SLOTS], y[SLOTS];
+#pragma unroll
+  for (int s = 0; s < SLOTS; ++s) {
+    r[s] = rhs[s];
+    d[s] = 0.f;
+  }
+  apply_precond<NX, SLOTS, REG, false, false, false, true>(P, sh, S, Ph, r, z);
+  float part = 0.f;
+#pragma unroll
+  for (int s = 0; s < SLOTS; ++s) {
+    p[s] = z[s];
+    part = fmaf(r[s], z[s], part);
+  }
+  float eta = pcg_sum<false>(part, sh, redi, nwv);
+  const float thresh = fmaxf(rel_tol * rel_tol * eta, abs_thresh);
+  int it = 0;
+  if (!isfinite(eta)) {
+    flags |= DMPC_PROB_NONFINITE;
+    return 0;
+  }
+  if (eta > thresh) apply_rows<NX, SLOTS, REG, false, false, false, true>(P, sh.w0, S, p, y);
+  while (it < maxit && eta > thresh) {
+    part = 0.f;
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) part = fmaf(p[s], y[s], part);
+    const float v = pcg_sum<false>(part, sh, redi, nwv);
+    if (!(v > 0.f)) {
+      flags |= isfinite(v) ? DMPC_PROB_NONPD : DMPC_PROB_NONFINITE;
+      break;
+    }
+    const float alpha = eta * __builtin_amdgcn_rcpf(v);
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+      d[s] = fmaf(alpha, p[s], d[s]);
+      r[s] = fmaf(-alpha, y[s], r[s]);
+    }
+    apply_precond<NX, SLOTS, REG, false, false, false, true>(P, sh, S, Ph, r, z);
+    part = 0.f;
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) part = fmaf(r[s], z[s], part);
+    // eta' and the exchange of z behind one barrier
+    float* red = sh.red + 64 * (redi++ & 1);
+    const float wpart = wave_sum(part);
+    if ((tid & 63) == 0) red[tid >> 6] = wpart;
+    publish<NX, SLOTS, REG, false, false>(sh.w0, z, R);
+    __syncthreads();
+    float etan = 0.f;
+    for (int w = 0; w < nwv; ++w) etan += red[w];
+    ++it;
+    const float beta = etan * __builtin_amdgcn_rcpf(eta);
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+      const int rho = row_of<NX, false>(s, tid, BT);
+      float e;
+      if constexpr (NX == 16) e = scaled_dot_rows16(S[s], sh.w0 + NX + rho);
+      else e = scaled_dot<NX>(S[s], sh.w0 + (rho / NX) * NX);
+      y[s] = fmaf(beta, y[s], z[s] + e);
+      p[s] = fmaf(beta, p[s], z[s]);
+    }
+    if (!isfinite(etan)) {
+      flags |= DMPC_PROB_NONFINITE;
+      break;
+    }
+    eta = etan;
+  }
+  if (it >= maxit && eta > thresh) flags |= maxit_flag;
+  return it;
+}
+
 template <int NX, int SLOTS, bool REG, bool WAVE, bool DINV, bool TAIL, bool SC = false>
 __device__ __forceinline__ int pcg(const Prob& P, const Lds& sh,
                                    RowRegs<NX, SLOTS - TAIL, REG>& S,
@@ -2097,6 +2185,11 @@ __device__ __forceinline__ int pcg(const Prob& P, const Lds& sh,
                                    const float (&rhs)[SLOTS],
                                    float (&d)[SLOTS], int maxit, float rel_tol, float abs_thresh,
                                    int& flags, int& redi, int maxit_flag) {
+  // (nx >= 12: on the bicycle (nx = 8, Schur condition numbers near 1e6)
+  // the recurrence for y lengthened the slowest problem's PCG by a tenth)
+  if constexpr (SC && NX >= 12 && !WAVE && !DINV && !TAIL)
+    return pcg_scaled<NX, SLOTS, REG>(P, sh, S, Ph, rhs, d, maxit, rel_tol, abs_thresh, flags,
+                                      redi, maxit_flag);
   const int nwv = (block_threads<TAIL>() + 63) >> 6;
   float r[SLOTS], p[SLOTS], z[SLOTS], y[SLOTS];
   // initial residual r = rhs (d = 0), r~ = Phi^-1 r, p = r~, eta = r'r~
@@ -2417,7 +2510,7 @@ __device__ __noinline__ void scaled_solution_call(const ProbRec* rec, const floa
 
 template <int NX>
 __device__ __forceinline__ ResNorms fwd_residual64_body(const ProbRec* rec, const float* data,
-                                                        float* ws) {
+                                                        float* ws, float kkt_tol) {
   extern __shared__ float smem[];
   const int tid = threadIdx.x, BT = blockDim.x;
   const Prob P = make_prob<NX>(*rec, data, ws);
@@ -2518,7 +2611,10 @@ __device__ __forceinline__ ResNorms fwd_residual64_body(const ProbRec* rec, cons
   const ResNorms n = block_sum2(r2, b2, smem + C.red, nwv);
   __syncthreads();   // xz is the line search's region
   if constexpr (NX == 8 || NX == 12 || NX == 16) {
-    if (P.flags & kRecScaled) scaled_rhs<NX>(P, smem + C.w1 + NX, smem + C.w2 + NX);
+    // (not when the residual meets the KKT target: the caller stops there,
+    // by the same test)
+    if ((P.flags & kRecScaled) && !(n.r2 <= kkt_tol * kkt_tol * n.rhs2))
+      scaled_rhs<NX>(P, smem + C.w1 + NX, smem + C.w2 + NX);
   }
   return n;
 }
@@ -3006,7 +3102,7 @@ __device__ __noinline__ void bwd_begin(const ProbRec* rec, const float* data, fl
 // Result to w1; norms of r and of the adjoint right-hand side (dl/dz, dl/dlambda).
 template <int NX>
 __device__ __forceinline__ ResNorms bwd_residual64_body(const ProbRec* rec, const float* data,
-                                                        float* ws, const float* dl) {
+                                                        float* ws, const float* dl, float kkt_tol) {
   extern __shared__ float smem[];
   const int tid = threadIdx.x, BT = blockDim.x;
   const Prob P = make_prob<NX>(*rec, data, ws);
@@ -3102,7 +3198,10 @@ __device__ __forceinline__ ResNorms bwd_residual64_body(const ProbRec* rec, cons
   const ResNorms n = block_sum2(r2, b2, smem + C.red, nwv);
   __syncthreads();
   if constexpr (NX == 8 || NX == 12 || NX == 16) {
-    if (P.flags & kRecScaled) scaled_rhs<NX>(P, smem + C.w1 + NX, smem + C.w2 + NX);
+    // (not when the residual meets the KKT target: the caller stops there,
+    // by the same test)
+    if ((P.flags & kRecScaled) && !(n.r2 <= kkt_tol * kkt_tol * n.rhs2))
+      scaled_rhs<NX>(P, smem + C.w1 + NX, smem + C.w2 + NX);
   }
   return n;
 }
@@ -3828,25 +3927,25 @@ __device__ __noinline__ LsResult fwd_recover_ls_call(const ProbRec* rec, const f
 }
 template <int NX>
 __device__ __noinline__ ResNorms fwd_residual64_call(const ProbRec* rec, const float* data,
-                                                     float* ws) {
-  return fwd_residual64_body<NX>(rec, data, ws);
+                                                     float* ws, float kkt_tol) {
+  return fwd_residual64_body<NX>(rec, data, ws, kkt_tol);
 }
 template <int NX>
 __device__ __noinline__ ResNorms bwd_residual64_call(const ProbRec* rec, const float* data,
-                                                     float* ws, const float* dl) {
-  return bwd_residual64_body<NX>(rec, data, ws, dl);
+                                                     float* ws, const float* dl, float kkt_tol) {
+  return bwd_residual64_body<NX>(rec, data, ws, dl, kkt_tol);
 }
 template <int NX>
 __device__ __forceinline__ ResNorms fwd_residual64(const ProbRec* rec, const float* data,
-                                                   float* ws) {
-  if constexpr (NX <= 4) return fwd_residual64_body<NX>(rec, data, ws);
-  return fwd_residual64_call<NX>(rec, data, ws);
+                                                   float* ws, float kkt_tol) {
+  if constexpr (NX <= 4) return fwd_residual64_body<NX>(rec, data, ws, kkt_tol);
+  return fwd_residual64_call<NX>(rec, data, ws, kkt_tol);
 }
 template <int NX>
 __device__ __forceinline__ ResNorms bwd_residual64(const ProbRec* rec, const float* data,
-                                                   float* ws, const float* dl) {
-  if constexpr (NX <= 4) return bwd_residual64_body<NX>(rec, data, ws, dl);
-  return bwd_residual64_call<NX>(rec, data, ws, dl);
+                                                   float* ws, const float* dl, float kkt_tol) {
+  if constexpr (NX <= 4) return bwd_residual64_body<NX>(rec, data, ws, dl, kkt_tol);
+  return bwd_residual64_call<NX>(rec, data, ws, dl, kkt_tol);
 }
 template <int NX>
 __device__ __forceinline__ int fwd_blocks(const ProbRec* rec, const float* data, float* ws,
@@ -3885,9 +3984,10 @@ __device__ __forceinline__ ResNorms residual_rows(const ProbRec* rec, const KArg
     publish<NX, SLOTS, false, false>(sh.w2, lo, P.R);
     __syncthreads();
     ResNorms nr;
-    if constexpr (BWD) nr = bwd_residual64<NX>(rec, a.data, a.ws, a.dl);
-    else nr = fwd_residual64<NX>(rec, a.data, a.ws);
-    // (scaled system: the call left r~ = L^-1 r in w2)
+    if constexpr (BWD) nr = bwd_residual64<NX>(rec, a.data, a.ws, a.dl, a.kkt_tol);
+    else nr = fwd_residual64<NX>(rec, a.data, a.ws, a.kkt_tol);
+    // (scaled system: the call left r~ = L^-1 r in w2 unless r met the KKT
+    // target, when the caller does not use rr)
     const float* rw = (P.flags & kRecScaled) ? sh.w2 : sh.w1;
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
