@@ -388,7 +388,11 @@ dmpc_status dmpc_server_trace(dmpc_server* srv, char* buf, size_t len);
  * Schur rows of the last slot (those past (slots - 1) * block_threads) in
  * LDS; variants with register_rows = 2 run one wave per problem with a lane per stage block
  * (rows (T+1)*nx <= 64 * slots) and exchange neighbouring blocks between lanes
- * without LDS.  Without a
+ * without LDS; register_rows = 5 (nx 8, 12, 16) runs the PCG on the system
+ * scaled by the Cholesky factors of its diagonal blocks (the same iterates in
+ * other variables, Eq. S_Phiinv's preconditioner becoming I - E~), with the
+ * rows of its two off-diagonal blocks in registers, and applies only where
+ * block_threads is a multiple of nx (whole stages per group of rows).  Without a
  * tuning-table entry the library picks the instantiated variant with the
  * lowest modelled cost.
  *
@@ -407,7 +411,9 @@ int32_t dmpc_list_variants(int32_t* out, int32_t max_rows);
  * Affects plans and sessions created afterwards.  INVALID_ARG on a malformed
  * row (nothing is installed then); a row with register_rows = 2 must have
  * launch_bound 64 and slots a multiple of nx; one with register_rows = 4
- * launch_bound and block_threads 512 and slots >= 2.  Host only; thread safe. */
+ * launch_bound and block_threads 512 and slots >= 2; register_rows is at
+ * most 5, and a register_rows = 5 row is passed over for a problem whose nx
+ * does not divide block_threads.  Host only; thread safe. */
 dmpc_status dmpc_set_tuning(const int32_t* rows, int32_t n_rows);
 
 /* Copies up to max_rows rows of the installed table into the HOST array rows
