@@ -572,10 +572,10 @@ __device__ __forceinline__ void gather_A(const float* A, int base, int BT, int o
     for (int k = 0; k < NX; ++k) a[u][k] = s[COL ? k * NX : k];
   }
 }
-// rows gathered at once: 32 floats of A per thread (the passes are calls
-// with at most 128 registers)
+// rows gathered at once: at most 32 floats of A per thread (the passes are
+// calls with at most 128 registers; one row at nx = 32)
 template <int NX>
-constexpr int gather_rows() { return NX >= 12 ? 2 : (NX >= 8 ? 4 : 8); }
+constexpr int gather_rows() { return NX >= 32 ? 1 : (NX >= 12 ? 2 : (NX >= 8 ? 4 : 8)); }
 
 __device__ __forceinline__ float softplusf(float v) {
   return v > 20.f ? v : log1pf(expf(v));
