@@ -2740,16 +2740,42 @@ __device__ __forceinline__ void ls_rows_ltv(const Prob& P, const LsParams& lp, c
     cs[a] = ds[a] = 0.0;
   }
   dn = 0.0;
-  for (int rho = tid; rho < R; rho += BT) {
-    const int t = rho / NX, i = rho - t * NX;
-    const double xb = xbar[rho], dx = (double)xp[rho] - xb;
+  constexpr int U = gather_rows<NX>();
+  if constexpr (COST == DMPC_COST_DIAG) {
+    // the diagonal Hessian and linear term of U rows loaded before any is used
+    for (int base = tid; base < R; base += U * BT) {
+      float qd[U], ql[U];
 #pragma unroll
-    for (int a = 0; a <= kMaxAlphas; ++a)
-      cs[a] += a <= lp.n ? cost_x1<NX>(P, t, i, xb + al[a] * dx, COST) : 0.0;
-    dn += dcost_x1<NX>(P, t, i, xb, dx, COST);
+      for (int u = 0; u < U; ++u) {
+        const int r = base + u * BT < R ? base + u * BT : 0;
+        qd[u] = P.costp[r];
+        ql[u] = P.costp[R + r];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int rho = base + u * BT;
+        if (rho >= R) continue;
+        const double xb = xbar[rho], dx = (double)xp[rho] - xb;
+        const double h = qd[u], q = ql[u];
+#pragma unroll
+        for (int a = 0; a <= kMaxAlphas; ++a) {
+          const double x = xb + al[a] * dx;
+          cs[a] += a <= lp.n ? 0.5 * h * x * x + q * x : 0.0;
+        }
+        dn += (h * xb + q) * dx;
+      }
+    }
+  } else {
+    for (int rho = tid; rho < R; rho += BT) {
+      const int t = rho / NX, i = rho - t * NX;
+      const double xb = xbar[rho], dx = (double)xp[rho] - xb;
+#pragma unroll
+      for (int a = 0; a <= kMaxAlphas; ++a)
+        cs[a] += a <= lp.n ? cost_x1<NX>(P, t, i, xb + al[a] * dx, COST) : 0.0;
+      dn += dcost_x1<NX>(P, t, i, xb, dx, COST);
+    }
   }
   // dynamics defects, rows t < T
-  constexpr int U = gather_rows<NX>();
   for (int base = tid; base < T * NX; base += U * BT) {
     float ag[U][NX];
     gather_A<NX, U, false>(P.A, base, BT, 0, T * NX, ag);
