@@ -2910,7 +2910,7 @@ __device__ __forceinline__ LsResult fwd_recover_ls_body(const ProbRec* rec, cons
     wave_sum_d_multi<kMaxAlphas + 1>(csum);
     wave_sum_d_multi<kMaxAlphas + 1>(dsum);
     constexpr int K = kMaxAlphas + 1;
-    if (nwv > 1 && 2 * K * nwv <= 2 * K * (N + 1)) {   // (the region holds 2 K (N + 1) doubles)
+    if (nwv > 1 && nwv <= N) {   // (the region holds 2 K (N + 1) doubles: the waves' rows, totals)
       if ((tid & 63) == 0) {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -2919,15 +2919,18 @@ __device__ __forceinline__ LsResult fwd_recover_ls_body(const ProbRec* rec, cons
         }
       }
       __syncthreads();
+      // 2 K threads total the waves' rows in order; the others read the totals
+      double* tot = tc + nwv * 2 * K;
+      if (tid < 2 * K) {
+        double acc = 0.0;
+        for (int w = 0; w < nwv; ++w) acc += tc[w * 2 * K + tid];
+        tot[tid] = acc;
+      }
+      __syncthreads();
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        double c0 = 0.0, d0 = 0.0;
-        for (int w = 0; w < nwv; ++w) {
-          c0 += tc[w * 2 * K + k];
-          d0 += tc[w * 2 * K + K + k];
-        }
-        csum[k] = c0;
-        dsum[k] = d0;
+        csum[k] = tot[k];
+        dsum[k] = tot[K + k];
       }
       __syncthreads();
     } else if (nwv > 1) {
