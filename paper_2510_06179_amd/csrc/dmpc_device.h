@@ -2529,20 +2529,27 @@ __device__ __forceinline__ ResNorms fwd_residual64_body(const ProbRec* rec, cons
   if (P.Ad == nullptr) {
     constexpr int U = gather_rows<NX>();
     for (int base = tid; base < R; base += U * BT) {
-      float a[U][NX];
+      float a[U][NX], qv[U];
+      double iq[U];
       gather_A<NX, U, true>(P.A, base, BT, 0, T * NX, a);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int r = base + u * BT < R ? base + u * BT : 0;
+        qv[u] = q[r];
+        iq[u] = iQd[r];
+      }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int rho = base + u * BT;
         if (rho < R) {
           const int t = rho / NX;
-          double acc = (double)q[rho] + ((double)w0[rho] + (double)w2[rho]);
+          double acc = (double)qv[u] + ((double)w0[rho] + (double)w2[rho]);
           if (t < T) {
 #pragma unroll
             for (int k = 0; k < NX; ++k)
               acc -= (double)a[u][k] * ((double)w0[(t + 1) * NX + k] + (double)w2[(t + 1) * NX + k]);
           }
-          xz[rho] = -acc * iQd[rho];
+          xz[rho] = -acc * iq[u];
         }
       }
     }
@@ -2777,8 +2784,10 @@ __device__ __forceinline__ void ls_rows_ltv(const Prob& P, const LsParams& lp, c
   }
   // dynamics defects, rows t < T
   for (int base = tid; base < T * NX; base += U * BT) {
-    float ag[U][NX];
+    float ag[U][NX], cv[U];
     gather_A<NX, U, false>(P.A, base, BT, 0, T * NX, ag);
+#pragma unroll
+    for (int u = 0; u < U; ++u) cv[u] = P.c[base + u * BT < T * NX ? base + u * BT : 0];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int rho = base + u * BT;
@@ -2787,7 +2796,7 @@ __device__ __forceinline__ void ls_rows_ltv(const Prob& P, const LsParams& lp, c
       const float* Bi = P.B + (t * NX + i) * m;
       const float* xs = xbar + t * NX;
       const float* qs = xp + t * NX;
-      double a0 = P.c[rho], a1 = 0.0;
+      double a0 = cv[u], a1 = 0.0;
 #pragma unroll
       for (int j = 0; j < NX; ++j) {
         const double xj = xs[j];
@@ -2842,21 +2851,28 @@ __device__ __forceinline__ LsResult fwd_recover_ls_body(const ProbRec* rec, cons
       if (P.Ad == nullptr) {
       constexpr int U = gather_rows<NX>();
       for (int base = tid; base < R; base += U * BT) {
-        float a[U][NX];
+        float a[U][NX], qv[U];
+        double iq[U];
         gather_A<NX, U, true>(P.A, base, BT, 0, T * NX, a);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int r = base + u * BT < R ? base + u * BT : 0;
+          qv[u] = q[r];
+          iq[u] = iQd[r];
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int rho = base + u * BT;
           if (rho < R) {
             const int t = rho / NX;
-            double acc = (double)q[rho] + ((double)w0[NX + rho] + (double)w2[NX + rho]);
+            double acc = (double)qv[u] + ((double)w0[NX + rho] + (double)w2[NX + rho]);
             if (t < T) {
               const float* lh = w0 + NX + (t + 1) * NX;
               const float* ll = w2 + NX + (t + 1) * NX;
 #pragma unroll
               for (int kk = 0; kk < NX; ++kk) acc -= (double)a[u][kk] * ((double)lh[kk] + (double)ll[kk]);
             }
-            xp[rho] = (float)(-acc * iQd[rho]);
+            xp[rho] = (float)(-acc * iq[u]);
           }
         }
       }
@@ -3151,20 +3167,27 @@ __device__ __forceinline__ ResNorms bwd_residual64_body(const ProbRec* rec, cons
   if (P.Ad == nullptr) {
     constexpr int U = gather_rows<NX>();
     for (int base = tid; base < R; base += U * BT) {
-      float a[U][NX];
+      float a[U][NX], dv[U];
+      double iq[U];
       gather_A<NX, U, true>(P.A, base, BT, 0, T * NX, a);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int r = base + u * BT < R ? base + u * BT : 0;
+        dv[u] = dlx[r];
+        iq[u] = iQd[r];
+      }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int rho = base + u * BT;
         if (rho < R) {
           const int t = rho / NX;
-          double acc = (double)dlx[rho] - ((double)w0[rho] + (double)w2[rho]);
+          double acc = (double)dv[u] - ((double)w0[rho] + (double)w2[rho]);
           if (t < T) {
 #pragma unroll
             for (int k = 0; k < NX; ++k)
               acc += (double)a[u][k] * ((double)w0[(t + 1) * NX + k] + (double)w2[(t + 1) * NX + k]);
           }
-          xz[rho] = acc * iQd[rho];
+          xz[rho] = acc * iq[u];
         }
       }
     }
