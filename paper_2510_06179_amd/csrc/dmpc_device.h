@@ -1294,6 +1294,7 @@ __device__ __forceinline__ bool scaled_blocks(const Prob& P, double* xch) {
   float* blk = P.W + P.L.blk;
   double* Lid = (double*)(P.W + P.L.Lid);
   double* xg = xch + (tid / NX) * NX;   // exchange row of this thread's stage group
+  double* xr = xg + BT;                  // reciprocals of the pivots (the region holds 2 BT)
   int bad = 0;
   // (1), (2) per group of BT rows (whole stages); rows past R factor
   // identity blocks and store nothing
@@ -1305,18 +1306,22 @@ __device__ __forceinline__ bool scaled_blocks(const Prob& P, double* xch) {
 #pragma unroll
     for (int j = 0; j < NX; ++j)
       a[j] = live ? (double)blk[blk_at<NX>(rho, NX + j)] : (j == i ? 1.0 : 0.0);
-    // Cholesky, one column per step: lane i ends with row i of L_t in a[0..i]
+    // Cholesky, one column per step: lane i ends with row i of L_t in a[0..i];
+    // the pivot lane publishes L_kk and 1 / L_kk, so that the column is a
+    // product (the division leaves the step's dependent chain)
 #pragma unroll
     for (int k = 0; k < NX; ++k) {
       if (i == k) {
         if (!(a[k] > 0.0)) bad = 1;
-        xg[k] = sqrt(a[k] > 0.0 ? a[k] : 1.0);
+        const double l = sqrt(a[k] > 0.0 ? a[k] : 1.0);
+        xg[k] = l;
+        xr[k] = 1.0 / l;
       }
       sync();
       const double lkk = xg[k];
       if (i == k) a[k] = lkk;
       if (i > k) {
-        a[k] /= lkk;
+        a[k] *= xr[k];
         xg[i] = a[k];
       }
       sync();
@@ -1338,7 +1343,7 @@ __device__ __forceinline__ bool scaled_blocks(const Prob& P, double* xch) {
       double acc = m == i ? 1.0 : 0.0;
 #pragma unroll
       for (int q = 0; q < m; ++q) acc -= xg[q] * x[q];
-      x[m] = m < i ? 0.0 : acc / xg[m];
+      x[m] = m < i ? 0.0 : acc * xr[m];
       sync();
     }
     if (live) {
